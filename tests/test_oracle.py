@@ -1,0 +1,300 @@
+"""Pins of the FP64 oracle against the paper and against mathematics.
+
+Nothing here retypes the oracle's formulas: each check comes from the
+paper's worked example, a closed form, an algebraic identity of the gates,
+or an agreement between the oracle's three independent routes (state
+vector, variable elimination, brute-force labelling sum).
+"""
+import cmath
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.elimination import exact_sum, min_fill_order
+from oracle.gates import gate_matrix
+from oracle.graph import Graph
+from oracle.network import build_network, project
+from tests.conftest import golden_path
+from workload import generate_circuit, random_bitstrings, random_thetas
+
+X = np.array([[0, 1], [1, 0]], dtype=complex)
+Y = np.array([[0, -1j], [1j, 0]], dtype=complex)
+Z = np.diag([1.0, -1.0]).astype(complex)
+I2 = np.eye(2, dtype=complex)
+
+
+# --------------------------------------------------------------- gate tables
+def test_gate_identities():
+    sx, sy, t, h = (gate_matrix(g) for g in ("SX", "SY", "T", "H"))
+    assert np.allclose(sx @ sx, X, atol=1e-15)
+    assert np.allclose(sy @ sy, Y, atol=1e-15)
+    assert np.allclose(h @ h, I2, atol=1e-15)
+    assert np.allclose(t @ t, np.diag([1, 1j]), atol=1e-15)
+    assert np.allclose(np.linalg.matrix_power(t, 8), I2, atol=1e-15)
+    for m in (sx, sy, t, h, gate_matrix("RZ", 0.7)):
+        assert np.allclose(m.conj().T @ m, I2, atol=1e-15)
+    # T = e^{i pi/8} RZ(pi/4)
+    assert np.allclose(t, cmath.exp(1j * math.pi / 8) * gate_matrix("RZ", math.pi / 4), atol=1e-15)
+    # d RZ / d theta = (1/2) RZ(theta + pi)
+    th, h_ = 0.37, 1e-6
+    num = (gate_matrix("RZ", th + h_) - gate_matrix("RZ", th - h_)) / (2 * h_)
+    assert np.allclose(num, 0.5 * gate_matrix("RZ", th + math.pi), atol=1e-9)
+
+
+def test_cz_pair_identity():
+    # CZ_12 CZ_13 = |0><0| (x) I_23 + |1><1| (x) Z_2 Z_3 (Discussion section)
+    cz = gate_matrix("CZ")
+    cz12 = np.kron(cz, I2)
+    cz13 = np.zeros((8, 8), dtype=complex)
+    for i in range(8):
+        b1, b2, b3 = (i >> 2) & 1, (i >> 1) & 1, i & 1
+        cz13[i, i] = -1 if (b1 and b3) else 1
+    p0 = np.diag([1, 0]).astype(complex)
+    p1 = np.diag([0, 1]).astype(complex)
+    rhs = np.kron(p0, np.kron(I2, I2)) + np.kron(p1, np.kron(Z, Z))
+    assert np.allclose(cz12 @ cz13, rhs)
+
+
+# ------------------------------------------------------- worked example
+def _read_fig3():
+    sec = {}
+    cur = None
+    with open(golden_path("fig3_graph.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if line.startswith("["):
+                cur = line.strip("[]")
+                sec[cur] = []
+            else:
+                sec[cur].append(line)
+    return sec
+
+
+def _edges(line):
+    return {tuple(sorted(e)) for e in line.split()[1:]}
+
+
+def _letter_map(net):
+    """letter -> variable id, from the labelling i_1..i_7 of the example."""
+    sec = _read_fig3()
+    mapping = {}
+    for line in sec["labelling"]:
+        t, letters = line.split()
+        cycle = int(t) - 1  # paper cycle C_t is cycle t-1 here
+        for q, ch in enumerate(letters):
+            cands = [v.id for v in net.variables if v.qubit == q and v.cycle <= cycle]
+            vid = max(cands)
+            assert mapping.setdefault(ch, vid) == vid, f"letter {ch} maps to two variables"
+    assert len(set(mapping.values())) == len(mapping), "two letters share a variable"
+    return mapping
+
+
+def test_fig2_network_is_fig3_graph(fig2_text):
+    net = build_network(fig2_text)
+    sec = _read_fig3()
+    m = _letter_map(net)
+    inv = {v: k for k, v in m.items()}
+    free = net.free_vars
+    assert sorted(inv[v] for v in free) == sorted(sec["graph"][0].split()[1])
+    outs = [v.id for v in net.variables if v.is_output]
+    ours = {tuple(sorted(inv[a] + inv[b])) for a, b in net.graph_edges(exclude=outs)}
+    assert ours == _edges(sec["graph"][1])
+    # 2^28 terms before merging, 2^10 after (seven 4-bit strings -> 10 vars)
+    before, after = map(int, sec["terms"][0].split())
+    assert 7 * 4 == before and len(free) == after
+
+
+@pytest.mark.parametrize("op,v", [("fix", "c"), ("fix", "e"), ("eliminate", "c"), ("eliminate", "e")])
+def test_fig5_fig6_graph_operations(op, v):
+    sec = _read_fig3()
+    verts = set(sec["graph"][0].split()[1])
+    g = Graph(verts, _edges(sec["graph"][1]))
+    rank = getattr(g, op)(v)
+    want = sec[f"{op} {v}"]
+    assert g.vertices == set(want[0].split()[1])
+    assert {tuple(sorted(e)) for e in g.edges} == _edges(want[1])
+    if len(want) > 2:
+        assert rank == int(want[2].split()[1])
+
+
+# ---------------------------------------------------------- closed forms
+def _all_x(n):
+    return [tuple(b) for b in itertools.product([0, 1], repeat=n)]
+
+
+def test_empty_circuit_is_delta():
+    text = "qubits 3\n"
+    for x in _all_x(3):
+        want = 1.0 if x == (0, 0, 0) else 0.0
+        assert oracle.sv_amplitudes(text, [x])[0] == want
+        assert oracle.ve_amplitude(text, x) == want
+        assert oracle.brute_amplitude(text, x) == want
+
+
+def test_h_then_diagonal_closed_form():
+    rng = np.random.default_rng(5)
+    n = 5
+    lines = [f"qubits {n}"] + [f"0 H {q}" for q in range(n)]
+    czs, ts, rzs = [], [], []
+    thetas = rng.uniform(0, 2 * np.pi, 4)
+    for cyc in range(1, 7):
+        a, b = rng.choice(n, 2, replace=False)
+        lines.append(f"{cyc} CZ {a} {b}")
+        czs.append((a, b))
+        used = {a, b}
+        q = int(rng.choice([q for q in range(n) if q not in used]))
+        if cyc <= 4:
+            lines.append(f"{cyc} RZ {q} {cyc - 1}")
+            rzs.append((q, thetas[cyc - 1]))
+        else:
+            lines.append(f"{cyc} T {q}")
+            ts.append(q)
+    text = "\n".join(lines)
+    for x in _all_x(n):
+        want = 2 ** (-n / 2)
+        for a, b in czs:
+            want *= (-1) ** (x[a] * x[b])
+        for q in ts:
+            want *= cmath.exp(1j * math.pi * x[q] / 4)
+        for q, th in rzs:
+            want *= cmath.exp(1j * th * (2 * x[q] - 1) / 2)
+        for got in (oracle.sv_amplitudes(text, [x], thetas)[0], oracle.ve_amplitude(text, x, params=thetas),
+                    oracle.brute_amplitude(text, x, params=thetas)):
+            assert abs(got - want) < 1e-14
+
+
+def test_double_hadamard_and_t8():
+    n = 4
+    hh = "\n".join([f"qubits {n}"] + [f"{c} H {q}" for c in (0, 1) for q in range(n)])
+    t8 = "\n".join([f"qubits {n}"] + [f"0 H {q}" for q in range(n)]
+                   + [f"{c} T {q}" for c in range(1, 9) for q in range(n)]
+                   + [f"9 H {q}" for q in range(n)])
+    for text in (hh, t8):
+        for x in _all_x(n):
+            want = 1.0 if sum(x) == 0 else 0.0
+            assert abs(oracle.sv_amplitudes(text, [x])[0] - want) < 1e-14
+            assert abs(oracle.ve_amplitude(text, x) - want) < 1e-14
+
+
+def test_bit_order_is_qubit_index():
+    # SX SX = X on qubit 0 only: all amplitude on x = (1, 0, 0)
+    text = "qubits 3\n0 SX 0\n1 SX 0\n"
+    for x in _all_x(3):
+        want = 1.0 if x == (1, 0, 0) else 0.0
+        assert abs(oracle.sv_amplitudes(text, [x])[0] - want) < 1e-15
+        assert abs(oracle.ve_amplitude(text, x) - want) < 1e-15
+    assert oracle.sv_state(text)[1] != 0  # index 1 = bit 0 set
+
+
+def test_qubit_without_nondiagonal_gate():
+    text = "qubits 2\n0 H 0\n1 T 1\n2 CZ 0 1\n"
+    for x in _all_x(2):
+        want = 2 ** -0.5 if x[1] == 0 else 0.0
+        assert abs(oracle.ve_amplitude(text, x) - want) < 1e-15
+        assert abs(oracle.sv_amplitudes(text, [x])[0] - want) < 1e-15
+
+
+# ------------------------------------------------- three routes agree
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sv_ve_brute_agree_4x4x10(seed):
+    text = generate_circuit(4, 10, seed)
+    for x in random_bitstrings(16, 4, seed + 1000):
+        a = oracle.sv_amplitudes(text, [x])[0]
+        b = oracle.ve_amplitude(text, x)
+        c = oracle.brute_amplitude(text, x)
+        assert abs(a - b) < 1e-13 and abs(a - c) < 1e-13
+
+
+def test_fig2_all_outputs(fig2_text):
+    for x in _all_x(4):
+        a = oracle.sv_amplitudes(fig2_text, [x])[0]
+        assert abs(a - oracle.ve_amplitude(fig2_text, x)) < 1e-14
+        assert abs(a - oracle.brute_amplitude(fig2_text, x)) < 1e-14
+
+
+def test_unitarity_sum_over_x():
+    text = generate_circuit(3, 16, 4)
+    vals = [oracle.ve_amplitude(text, x) for x in _all_x(9)]
+    assert abs(sum(abs(v) ** 2 for v in vals) - 1.0) < 1e-13
+    psi = oracle.sv_state(text)
+    assert abs(np.vdot(psi, psi) - 1.0) < 1e-13
+
+
+def test_slicing_and_order_invariance():
+    text = generate_circuit(4, 12, 9, rz=True)
+    th = random_thetas(40, 2009)
+    x = random_bitstrings(16, 1, 1009)[0]
+    net = build_network(text, th)
+    ref = oracle.sv_amplitudes(text, [x], th)[0]
+    rng = np.random.default_rng(0)
+    free = net.free_vars
+    for k in (0, 1, 3, 5):
+        sl = [int(v) for v in rng.choice(free, k, replace=False)]
+        rest = [v for v in free if v not in sl]
+        for order in (None, list(rng.permutation(rest))):
+            order = None if order is None else [int(v) for v in order]
+            got = oracle.ve_amplitude(text, x, sliced=sl, order=order, params=th, net=net)
+            assert abs(got - ref) < 1e-13
+
+
+def test_ve_rejects_bad_order():
+    text = generate_circuit(4, 10, 0)
+    net = build_network(text)
+    with pytest.raises(ValueError):
+        oracle.ve_amplitude(text, [0] * 16, order=net.free_vars[:-1])
+
+
+# -------------------------------------------------------------- gradients
+def test_gradient_shift_fd_and_slice_identity():
+    text = generate_circuit(4, 10, 2, rz=True)
+    nq = 16
+    from workload import parse_header
+    _, npar = parse_header(text)
+    th = random_thetas(npar, 2002)
+    x = random_bitstrings(nq, 1, 1002)[0]
+    shift = oracle.sv_gradient_shift(text, x, th)
+    fd = oracle.fd_gradient(lambda p: oracle.sv_amplitudes(text, [x], p)[0], th)
+    assert np.max(np.abs(shift - fd)) < 1e-8
+    # d alpha / d theta_j = (i/2) (alpha|_{u=1} - alpha|_{u=0}), u = RZ's variable
+    net = build_network(text, th)
+    from oracle.circuit import parse_circuit
+    circ = parse_circuit(text)
+    cur = {}
+    var_at = {}
+    for g in sorted(circ.gates, key=lambda g: (g.cycle, min(g.qubits))):
+        if g.name in ("H", "SX", "SY"):
+            cur[g.qubits[0]] = max(v.id for v in net.variables
+                                   if v.qubit == g.qubits[0] and v.cycle == g.cycle)
+        if g.name == "RZ":
+            var_at[g.param] = cur.get(g.qubits[0])
+    for j in range(npar):
+        u = var_at[j]
+        if u is None or net.variables[u].is_output:
+            continue
+        vals = oracle.ve_slice_values(text, x, sliced=[u], params=th, net=net)
+        assert abs(0.5j * (vals[1] - vals[0]) - shift[j]) < 1e-13
+
+
+def test_exact_sum_is_exactly_rounded():
+    vals = np.array([1e16, 1.0, -1e16, 1.0j], dtype=complex)
+    assert exact_sum(vals) == complex(1.0, 1.0)
+
+
+def test_min_fill_order_small_width():
+    text = generate_circuit(5, 20, 0)
+    net = build_network(text)
+    factors, _ = project(net, [0] * 25)
+    edges = set()
+    for vs, _ in factors:
+        for i in range(len(vs)):
+            for j in range(i + 1, len(vs)):
+                edges.add(tuple(sorted((vs[i], vs[j]))))
+    order = min_fill_order(net.free_vars, edges)
+    cost, width = oracle.order_cost(net.free_vars, edges, order)
+    assert sorted(order) == sorted(net.free_vars)
+    assert width <= 12 and cost < 1 << 16
