@@ -1,0 +1,198 @@
+/* qgm -- single output amplitudes <x|C|0^N> of grid random circuits by
+ * sliced variable elimination on the undirected graphical model, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Chen, Zhang, Huang, Newman, Shi, "Classical Simulation of
+ * Intermediate-Size Quantum Circuits", arXiv:1805.01450):
+ *   - the amplitude is the Feynman sum of Eq. (1);
+ *   - diagonal gates identify indices, every distinct index is a binary
+ *     variable, gates are factors (Section "Undirected Graphical Model",
+ *     gadgets of Fig. "tensornodes");
+ *   - output variables are fixed to x and k chosen variables are fixed
+ *     ("sliced") to the bits of s in [0, 2^k), giving 2^k independent sums
+ *     whose total is the amplitude (Section "Parallelization by fixing the
+ *     values of variables");
+ *   - each slice is evaluated by variable elimination along a fixed order
+ *     (Section "Variable elimination"), and the slices are summed.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a qgm_status; no C++ exception crosses the ABI.
+ *     On a non-OK status qgm_last_error() returns a thread-local message
+ *     (valid until the next failing call on the same thread).
+ *   - The caller owns every array it passes; arrays are read during the call
+ *     only.  Opaque handles are owned by the library until their *_free.
+ *   - Device workspace and HIP stream belong to the caller.
+ *   - Bitstrings are bytes 0/1, row-major (n_bs rows of n_qubits); x[q] is
+ *     the value of qubit q.  Amplitudes are FP64 (re, im) pairs.
+ *   - Variable ids: variables are created by non-diagonal one-qubit gates
+ *     taken by ascending cycle, then ascending qubit, and numbered 0, 1, ...
+ *     in that order; the output variable of a qubit is its last variable.
+ *   - Slice s fixes sliced_vars[j] to bit j of s.
+ */
+#ifndef QGM_H
+#define QGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QGM_OK = 0,
+  QGM_E_ARG = -1,         /* bad argument (null pointer, size, bitstring value) */
+  QGM_E_PARSE = -2,       /* circuit text rejected */
+  QGM_E_ORDER = -3,       /* order is not a permutation of the free, non-sliced variables */
+  QGM_E_SLICE = -4,       /* sliced variables not distinct free variables, or k > 40 */
+  QGM_E_WORKSPACE = -5,   /* workspace too small, or plan exceeds the caller's cap */
+  QGM_E_HIP = -6,         /* HIP runtime error (message has hipGetErrorString) */
+  QGM_E_UNSUPPORTED = -7  /* option not supported by this build */
+} qgm_status;
+
+typedef enum {
+  QGM_C128 = 0, /* complex128 contraction */
+  QGM_C64 = 1   /* complex64 contraction, FP32 accumulation */
+} qgm_precision;
+
+typedef struct qgm_circuit qgm_circuit;
+typedef struct qgm_plan qgm_plan;
+
+typedef struct {
+  int32_t id, qubit, cycle_created, is_output;
+} qgm_var_info;
+
+typedef struct {
+  int32_t prec;          /* qgm_precision */
+  int32_t profile;       /* 1 = record HIP events around each kernel of every run (qgm_plan_timing) */
+  size_t workspace_cap;  /* 0 = no cap; else plan_create fails with QGM_E_WORKSPACE when the
+                            per-item memory of the plan cannot fit in it */
+  int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
+  int32_t reserved[7];
+} qgm_plan_opts;
+
+/* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
+ * memory fits in registers and INTERPRETER otherwise.
+ * GENERATED: plan_create emits straight-line HIP for the plan (every operand
+ *   offset is static) and compiles it for gfx950 with hiprtc; item tensors
+ *   live in registers; slice sums are fused into the kernel.
+ * INTERPRETER: one prebuilt persistent kernel walks a step table with a
+ *   device work queue; item tensors live in LDS (or global scratch). */
+enum { QGM_ENGINE_AUTO = 0, QGM_ENGINE_INTERPRETER = 1, QGM_ENGINE_GENERATED = 2 };
+
+typedef struct {
+  int32_t n_steps;        /* elimination + leaf steps of the compiled program */
+  int32_t n_const_steps;  /* steps independent of the output bits and the slice */
+  int32_t max_rank;       /* largest intermediate tensor rank */
+  int32_t item_elems;     /* peak live tensor elements per work item */
+  int32_t n_leaves;       /* factors read at fixed (output or sliced) values per item */
+  int32_t k;              /* sliced variables */
+  double flops_item;      /* useful real flops per slice contraction (6 per complex
+                             multiply, 2 per complex add) */
+  double flops_const;     /* flops of the constant steps, once per call */
+  double bytes_item;      /* bytes read + written per slice if every intermediate made
+                             one trip to memory, at 8 B per element */
+  double cost;            /* sum over eliminations of 2^deg(v) (Section "Variable elimination") */
+  int32_t engine;         /* engine the plan runs with (QGM_ENGINE_INTERPRETER or _GENERATED) */
+  int32_t pad0;
+  double compile_s;       /* seconds spent generating and compiling the plan's kernel */
+} qgm_stats;
+
+/* Circuit text v1, one gate per line, '#' starts a comment:
+ *   qubits N            (N <= 64)
+ *   grid R C            (optional)
+ *   <cycle> <GATE> <q0> [<q1>] [<param_index>]
+ * GATE in {H, CZ, T, SX, SY, RZ, I}.  CZ takes two qubits, RZ one qubit and
+ * a parameter index into the params array of the amplitude calls.  Gates of
+ * one cycle must act on distinct qubits.  Matrices: H = [[1,1],[1,-1]]/sqrt2,
+ * SX and SY the principal square roots of X and Y, T = diag(1, e^{i pi/4}),
+ * RZ(t) = diag(e^{-it/2}, e^{it/2}), CZ = diag(1,1,1,-1).
+ * (Clock cycles C_1..C_d of Eq. (1); gates of Fig. 2 and Rule 3.)
+ * Errors: QGM_E_ARG (null), QGM_E_PARSE (message names the line). */
+qgm_status qgm_circuit_parse(const char* text, size_t len, qgm_circuit** out);
+qgm_status qgm_circuit_info(const qgm_circuit* c, int32_t* n_qubits, int32_t* n_vars, int32_t* n_params);
+/* Variable table (Section "Undirected Graphical Model"): writes min(cap, n_vars)
+ * entries of buf. */
+qgm_status qgm_circuit_vars(const qgm_circuit* c, qgm_var_info* buf, int32_t cap);
+/* Edges (u, w), u < w, of the graph over the free (non-output) variables:
+ * two variables are adjacent when a gate acts on both (Fig. 3).  Writes up to
+ * cap pairs into edges[2*cap]; *n_edges gets the total count. */
+qgm_status qgm_circuit_graph(const qgm_circuit* c, int32_t* edges, int32_t cap, int32_t* n_edges);
+void qgm_circuit_free(qgm_circuit* c);
+
+/* Host planner (Section "The variable elimination ordering", Section
+ * "Parallelization by fixing the values of variables"): a min-fill ordering
+ * (best of randomised restarts within the time budget), then greedy removal of
+ * key vertices, each minimising sum 2^deg under that fixed ordering, then a
+ * new ordering of the remaining variables.  k_req >= 0 removes exactly k_req
+ * vertices; k_req < 0 removes vertices until the width is <= target_rank
+ * (at most 40).  sliced_out needs room for 40 ids (or k_req), order_out for
+ * n_vars ids.  Errors: QGM_E_ARG. */
+qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
+                           uint64_t seed, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
+                           int32_t* n_order_out);
+/* Cost (sum of 2^deg(v)) and width (max deg(v)) of eliminating `order` after
+ * removing the sliced vertices (Section "Variable elimination", cost model).
+ * Errors: QGM_E_SLICE, QGM_E_ORDER as for qgm_plan_create. */
+qgm_status qgm_order_cost(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
+                          int32_t n_order, double* cost, int32_t* width);
+
+/* Compile the per-slice contraction program for (circuit, sliced_vars,
+ * order).  Host only; device tables are uploaded at the first run on the
+ * then-current device.  opts may be NULL (complex128, no cap).
+ * Errors: QGM_E_SLICE (ids not distinct free variables, or k > 40),
+ * QGM_E_ORDER (order not a permutation of the free non-sliced variables),
+ * QGM_E_WORKSPACE (over opts->workspace_cap), QGM_E_UNSUPPORTED (precision). */
+qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
+                           int32_t n_order, const qgm_plan_opts* opts, qgm_plan** out);
+qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out);
+/* Device workspace bytes needed by a run over n_bs bitstrings and n_slices
+ * slices, including the staging room that the host-pointer entry points use. */
+qgm_status qgm_workspace_size(const qgm_plan* p, int32_t n_bs, uint64_t n_slices, size_t* bytes);
+
+/* alpha_x for n_bs bitstrings, summed over all 2^k slices.  Host inputs
+ * (bitstrings n_bs x n_qubits bytes; params n_params doubles, or NULL when
+ * the circuit has no RZ), host output out[2*n_bs] = (re, im).  The slice sum
+ * is FP64 with Neumaier compensation in ascending s.  Synchronises `stream`
+ * (a hipStream_t, NULL = default stream).
+ * Errors: QGM_E_ARG (bitstring entry not 0/1, n_bs < 0, missing params),
+ * QGM_E_WORKSPACE (ws_bytes < qgm_workspace_size), QGM_E_HIP. */
+qgm_status qgm_amplitudes(qgm_plan* p, const uint8_t* bitstrings, int32_t n_bs, const double* params,
+                          void* d_workspace, size_t ws_bytes, void* hip_stream, double* out);
+/* Slices [s_begin, s_end) only.  partial[4*n_bs] = (sum re, sum im, comp re,
+ * comp im) per bitstring: the Neumaier sum and its compensation, so ranges run
+ * separately (e.g. after a failure) combine to the full result.
+ * Errors: as qgm_amplitudes, plus QGM_E_ARG when the range is not inside
+ * [0, 2^k). */
+qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bitstrings, int32_t n_bs, const double* params,
+                                uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
+                                void* hip_stream, double* partial);
+/* Same as qgm_amplitudes_range with every array in device memory and no
+ * synchronisation: d_bitstrings (n_bs x n_qubits bytes), d_params, and
+ * d_partial[4*n_bs] are device pointers; the work is queued on `stream`.
+ * Bitstring entries are used as (value & 1).  Errors: QGM_E_ARG,
+ * QGM_E_WORKSPACE, QGM_E_HIP. */
+qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
+                                 uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
+                                 void* hip_stream, double* d_partial);
+/* Kernel durations of the runs made since the last reset by a plan created
+ * with opts.profile = 1: ms[0] prologue (tables, constant steps), ms[1]
+ * per-item contraction chain, ms[2] slice reduction, each averaged over the
+ * runs and measured with HIP events recorded on each run's own stream.
+ * Waits for the last recorded run.  reset = 1 forgets the runs afterwards.
+ * Errors: QGM_E_ARG (plan not profiling), QGM_E_HIP. */
+qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_runs);
+void qgm_plan_free(qgm_plan* p);
+const char* qgm_last_error(void);
+
+/* One-shot form plan(circuit, bitstring, sliced_vars, order) -> amplitude:
+ * parse, plan, run one bitstring in complex128 with a library-allocated
+ * workspace on the default stream, free.  out[2] = (re, im). */
+qgm_status qgm_amplitude(const char* circuit_text, size_t len, const uint8_t* bitstring,
+                         const int32_t* sliced_vars, int32_t k, const int32_t* order, int32_t n_order,
+                         const double* params, double out[2]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QGM_H */

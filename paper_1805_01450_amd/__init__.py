@@ -1,0 +1,240 @@
+"""qgm: single amplitudes <x|C|0^N> by sliced variable elimination on MI355X.
+
+Thin Python binding of the C-ABI in include/qgm.h.  The functions below have
+the C names and only marshal arguments; every step of the computation runs
+in libqgm.so (host planner/compiler in C++, contraction in HIP kernels).
+PyTorch supplies device memory and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._lib import DECLARED, LIB_PATH, PlanOpts, QgmError, Stats, VarInfo, check, lib  # noqa: F401
+
+QGM_C128 = 0
+QGM_C64 = 1
+QGM_ENGINE_AUTO = 0
+QGM_ENGINE_INTERPRETER = 1
+QGM_ENGINE_GENERATED = 2
+
+
+def _i32(seq):
+    arr = (C.c_int32 * max(1, len(seq)))(*[int(v) for v in seq])
+    return arr
+
+
+def qgm_circuit_parse(text: str) -> C.c_void_p:
+    raw = text.encode()
+    h = C.c_void_p()
+    check(lib.qgm_circuit_parse(raw, len(raw), C.byref(h)))
+    return h
+
+
+def qgm_circuit_info(c):
+    nq, nv, npar = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib.qgm_circuit_info(c, C.byref(nq), C.byref(nv), C.byref(npar)))
+    return nq.value, nv.value, npar.value
+
+
+def qgm_circuit_vars(c):
+    _, nv, _ = qgm_circuit_info(c)
+    buf = (VarInfo * max(1, nv))()
+    check(lib.qgm_circuit_vars(c, buf, nv))
+    return [(v.id, v.qubit, v.cycle_created, v.is_output) for v in buf[:nv]]
+
+
+def qgm_circuit_graph(c):
+    n = C.c_int32()
+    check(lib.qgm_circuit_graph(c, None, 0, C.byref(n)))
+    buf = (C.c_int32 * max(2, 2 * n.value))()
+    check(lib.qgm_circuit_graph(c, buf, n.value, C.byref(n)))
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+
+def qgm_circuit_free(c) -> None:
+    lib.qgm_circuit_free(c)
+
+
+def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0):
+    _, nv, _ = qgm_circuit_info(c)
+    sl = (C.c_int32 * 40)()
+    order = (C.c_int32 * max(1, nv))()
+    k, n = C.c_int32(), C.c_int32()
+    check(lib.qgm_plan_slices(c, k_req, target_rank, float(time_budget_s), seed, sl, C.byref(k), order, C.byref(n)))
+    return list(sl[: k.value]), list(order[: n.value])
+
+
+def qgm_order_cost(c, sliced, order):
+    cost, width = C.c_double(), C.c_int32()
+    check(lib.qgm_order_cost(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(cost), C.byref(width)))
+    return cost.value, width.value
+
+
+def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
+                    engine: int = QGM_ENGINE_AUTO):
+    opts = PlanOpts()
+    opts.prec = prec
+    opts.profile = 1 if profile else 0
+    opts.engine = engine
+    opts.workspace_cap = workspace_cap
+    h = C.c_void_p()
+    check(lib.qgm_plan_create(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(opts), C.byref(h)))
+    return h
+
+
+def qgm_plan_stats(p) -> dict:
+    s = Stats()
+    check(lib.qgm_plan_stats(p, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+
+def qgm_workspace_size(p, n_bs: int, n_slices: int) -> int:
+    out = C.c_size_t()
+    check(lib.qgm_workspace_size(p, n_bs, n_slices, C.byref(out)))
+    return out.value
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _host_inputs(bitstrings, params):
+    bs = np.ascontiguousarray(np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8)))
+    par = None if params is None else np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    return bs, par
+
+
+def qgm_amplitudes(p, bitstrings, params, workspace, stream=None) -> np.ndarray:
+    """Host arrays in, complex128 numpy array out; workspace is a CUDA uint8 tensor."""
+    bs, par = _host_inputs(bitstrings, params)
+    out = np.empty(2 * bs.shape[0], dtype=np.float64)
+    check(lib.qgm_amplitudes(p, bs.ctypes.data_as(C.POINTER(C.c_uint8)), bs.shape[0],
+                             None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)),
+                             _ptr(workspace), workspace.numel(), _stream(stream),
+                             out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out[0::2] + 1j * out[1::2]
+
+
+def qgm_amplitudes_range(p, bitstrings, params, s_begin: int, s_end: int, workspace, stream=None) -> np.ndarray:
+    """(n_bs, 4) float64: sum re, sum im, compensation re, compensation im."""
+    bs, par = _host_inputs(bitstrings, params)
+    out = np.empty(4 * bs.shape[0], dtype=np.float64)
+    check(lib.qgm_amplitudes_range(p, bs.ctypes.data_as(C.POINTER(C.c_uint8)), bs.shape[0],
+                                   None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)),
+                                   s_begin, s_end, _ptr(workspace), workspace.numel(), _stream(stream),
+                                   out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out.reshape(-1, 4)
+
+
+def qgm_amplitudes_device(p, d_bits, d_params, s_begin: int, s_end: int, workspace, d_partial, stream=None) -> None:
+    """All-device form: d_bits uint8 (n_bs, n_qubits), d_params float64, d_partial float64 (n_bs, 4)."""
+    check(lib.qgm_amplitudes_device(p, _ptr(d_bits), d_bits.shape[0], _ptr(d_params), s_begin, s_end,
+                                    _ptr(workspace), workspace.numel(), _stream(stream), _ptr(d_partial)))
+
+
+def qgm_plan_timing(p, reset: bool = True):
+    """(prologue ms, chain ms, reduction ms) averaged over the profiled runs, and the run count."""
+    ms = (C.c_double * 3)()
+    n = C.c_int32()
+    check(lib.qgm_plan_timing(p, 1 if reset else 0, ms, C.byref(n)))
+    return (ms[0], ms[1], ms[2]), n.value
+
+
+def qgm_plan_free(p) -> None:
+    lib.qgm_plan_free(p)
+
+
+def qgm_last_error() -> str:
+    m = lib.qgm_last_error()
+    return m.decode() if m else ""
+
+
+def qgm_amplitude(text: str, bitstring, sliced=(), order=None, params=None) -> complex:
+    raw = text.encode()
+    x = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8))
+    par = None if params is None else np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    out = (C.c_double * 2)()
+    order = [] if order is None else order
+    check(lib.qgm_amplitude(raw, len(raw), x.ctypes.data_as(C.POINTER(C.c_uint8)), _i32(sliced), len(sliced),
+                            _i32(order), len(order),
+                            None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)), out))
+    return complex(out[0], out[1])
+
+
+class Circuit:
+    """Owning wrapper of a qgm_circuit handle."""
+
+    def __init__(self, text: str):
+        self.h = qgm_circuit_parse(text)
+        self.n_qubits, self.n_vars, self.n_params = qgm_circuit_info(self.h)
+
+    def vars(self):
+        return qgm_circuit_vars(self.h)
+
+    def graph(self):
+        return qgm_circuit_graph(self.h)
+
+    def plan_slices(self, k_req=-1, target_rank=0, time_budget_s=1.0, seed=0):
+        return qgm_plan_slices(self.h, k_req, target_rank, time_budget_s, seed)
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h and lib is not None:
+            try:
+                lib.qgm_circuit_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+
+
+class Plan:
+    """Owning wrapper of a qgm_plan handle plus a cached device workspace."""
+
+    def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
+                 profile: bool = False, engine: int = QGM_ENGINE_AUTO):
+        self.circuit = circuit
+        self.sliced = list(sliced)
+        self.order = list(order)
+        self.prec = prec
+        self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine)
+        self._ws = None
+
+    @property
+    def k(self):
+        return len(self.sliced)
+
+    def stats(self):
+        return qgm_plan_stats(self.h)
+
+    def workspace(self, n_bs: int, n_slices: int | None = None):
+        import torch
+        n_slices = (1 << self.k) if n_slices is None else n_slices
+        need = qgm_workspace_size(self.h, n_bs, n_slices)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def amplitudes(self, bitstrings, params=None, stream=None):
+        bs = np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8))
+        return qgm_amplitudes(self.h, bs, params, self.workspace(bs.shape[0]), stream)
+
+    def amplitudes_range(self, bitstrings, params, s_begin, s_end, stream=None):
+        bs = np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8))
+        ws = self.workspace(bs.shape[0], s_end - s_begin)
+        return qgm_amplitudes_range(self.h, bs, params, s_begin, s_end, ws, stream)
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h and lib is not None:
+            try:
+                lib.qgm_plan_free(h)
+            except Exception:  # interpreter shutdown
+                pass

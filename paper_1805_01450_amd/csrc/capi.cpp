@@ -1,0 +1,486 @@
+// extern "C" entry points declared in include/qgm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qgm.h"
+#include "exec.h"
+#include "host.h"
+
+using namespace qgm;
+
+struct qgm_circuit {
+  Network net;
+};
+
+struct qgm_plan {
+  Network net;
+  std::vector<int> sliced, order;
+  Program prog;
+  DevProgram dev;
+  int engine = QGM_ENGINE_INTERPRETER;  // engine in use
+  std::vector<char> code;                // generated kernel code object (engine GENERATED)
+  double compile_s = 0;
+  qgm_plan_opts opts;
+  double cost = 0;
+  std::mutex mu;
+  std::vector<std::array<hipEvent_t, 4>> runs;  // profiling events, one set per run
+  ~qgm_plan() {
+    for (auto& r : runs)
+      for (hipEvent_t e : r) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+qgm_status fail(qgm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                              \
+  }                                                            \
+  catch (const std::bad_alloc&) {                              \
+    return fail(QGM_E_ARG, "out of host memory");              \
+  }                                                            \
+  catch (const std::exception& e) {                            \
+    return fail(QGM_E_ARG, std::string("internal: ") + e.what()); \
+  }                                                            \
+  catch (...) {                                                \
+    return fail(QGM_E_ARG, "internal error");                  \
+  }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Staging {
+  size_t bits, params, partial, total;
+};
+
+Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params) {
+  Staging st;
+  size_t off = ws.total;
+  st.bits = off;
+  off = align256(off + (size_t)std::max(1, n_bs) * std::max(1, n_qubits));
+  st.params = off;
+  off = align256(off + (size_t)std::max(1, n_params) * sizeof(double));
+  st.partial = off;
+  off = align256(off + (size_t)std::max(1, n_bs) * 4 * sizeof(double));
+  st.total = off;
+  return st;
+}
+
+qgm_status ensure_device(qgm_plan* p) {
+  std::string err;
+  int rc = dev_upload(p->prog, p->code, p->dev, err);
+  if (rc) return fail((qgm_status)rc, err);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->dev.device)
+    return fail(QGM_E_ARG, "plan was uploaded to device " + std::to_string(p->dev.device) +
+                               " but the current device is " + std::to_string(dev));
+  return QGM_OK;
+}
+
+qgm_status layout_for(qgm_plan* p, int n_bs, uint64_t n_s, WsLayout& ws, LaunchCfg& cfg) {
+  cfg.prec = p->opts.prec;
+  cfg.generated = p->engine == QGM_ENGINE_GENERATED ? 1 : 0;
+  cfg.n_qubits = p->net.n_qubits;
+  cfg.n_bs = n_bs;
+  cfg.s_begin = 0;
+  cfg.n_s = n_s;
+  cfg.n_params = p->net.n_params;
+  std::string err;
+  int rc = dev_layout(p->prog, p->dev, cfg, ws, err);
+  if (rc) return fail((qgm_status)rc, err);
+  return QGM_OK;
+}
+
+qgm_status check_range(const qgm_plan* p, uint64_t s_begin, uint64_t s_end) {
+  const uint64_t ns = 1ull << p->sliced.size();
+  if (s_begin > s_end || s_end > ns) return fail(QGM_E_ARG, "slice range outside [0, 2^k)");
+  return QGM_OK;
+}
+
+qgm_status validate_plan_inputs(const Network& net, const int32_t* sliced, int32_t k, const int32_t* order,
+                                int32_t n_order, std::vector<int>& sv, std::vector<int>& ov) {
+  if (k < 0 || (k > 0 && !sliced)) return fail(QGM_E_SLICE, "bad sliced_vars / k");
+  if (k > 40) return fail(QGM_E_SLICE, "at most 40 sliced variables");
+  if (n_order < 0 || (n_order > 0 && !order)) return fail(QGM_E_ORDER, "bad order / n_order");
+  sv.assign(sliced, sliced + k);
+  ov.assign(order, order + n_order);
+  (void)net;
+  return QGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qgm_last_error(void) { return g_err.c_str(); }
+
+qgm_status qgm_circuit_parse(const char* text, size_t len, qgm_circuit** out) {
+  GUARD_BEGIN
+  if (!out || (!text && len)) return fail(QGM_E_ARG, "null argument");
+  *out = nullptr;
+  auto* c = new qgm_circuit();
+  std::string err;
+  if (!parse_circuit(text ? text : "", len, c->net, err)) {
+    delete c;
+    return fail(QGM_E_PARSE, err);
+  }
+  build_network(c->net);
+  *out = c;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_circuit_info(const qgm_circuit* c, int32_t* n_qubits, int32_t* n_vars, int32_t* n_params) {
+  if (!c) return fail(QGM_E_ARG, "null circuit");
+  if (n_qubits) *n_qubits = c->net.n_qubits;
+  if (n_vars) *n_vars = (int32_t)c->net.vars.size();
+  if (n_params) *n_params = c->net.n_params;
+  return QGM_OK;
+}
+
+qgm_status qgm_circuit_vars(const qgm_circuit* c, qgm_var_info* buf, int32_t cap) {
+  if (!c || (cap > 0 && !buf) || cap < 0) return fail(QGM_E_ARG, "null argument");
+  int n = std::min<int>(cap, (int)c->net.vars.size());
+  for (int i = 0; i < n; ++i) {
+    const Var& v = c->net.vars[i];
+    buf[i] = qgm_var_info{v.id, v.qubit, v.cycle, v.is_output};
+  }
+  return QGM_OK;
+}
+
+qgm_status qgm_circuit_graph(const qgm_circuit* c, int32_t* edges, int32_t cap, int32_t* n_edges) {
+  GUARD_BEGIN
+  if (!c || cap < 0 || (cap > 0 && !edges) || !n_edges) return fail(QGM_E_ARG, "null argument");
+  std::vector<int> vov;
+  Graph g = model_graph(c->net, vov);
+  int cnt = 0;
+  for (int a = 0; a < g.n; ++a)
+    for (int b = a + 1; b < g.n; ++b)
+      if (g.has(a, b)) {
+        if (cnt < cap) {
+          edges[2 * cnt] = c->net.free_vars[a];
+          edges[2 * cnt + 1] = c->net.free_vars[b];
+        }
+        ++cnt;
+      }
+  *n_edges = cnt;
+  return QGM_OK;
+  GUARD_END
+}
+
+void qgm_circuit_free(qgm_circuit* c) { delete c; }
+
+qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
+                           uint64_t seed, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
+                           int32_t* n_order_out) {
+  GUARD_BEGIN
+  if (!c || !sliced_out || !k_out || !order_out || !n_order_out) return fail(QGM_E_ARG, "null argument");
+  if (k_req > 40) return fail(QGM_E_ARG, "k_req > 40");
+  if (!(time_budget_s >= 0)) return fail(QGM_E_ARG, "negative time budget");
+  std::vector<int> sl, ord;
+  plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord);
+  for (size_t i = 0; i < sl.size(); ++i) sliced_out[i] = sl[i];
+  *k_out = (int32_t)sl.size();
+  for (size_t i = 0; i < ord.size(); ++i) order_out[i] = ord[i];
+  *n_order_out = (int32_t)ord.size();
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_order_cost(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
+                          int32_t n_order, double* cost, int32_t* width) {
+  GUARD_BEGIN
+  if (!c || !cost || !width) return fail(QGM_E_ARG, "null argument");
+  std::vector<int> sv, ov;
+  qgm_status s = validate_plan_inputs(c->net, sliced_vars, k, order, n_order, sv, ov);
+  if (s) return s;
+  std::string err;
+  int code = 0;
+  if (!validate_plan(c->net, sv, ov, err, code)) return fail((qgm_status)code, err);
+  std::vector<int> vov;
+  Graph g = model_graph(c->net, vov);
+  std::vector<char> removed(g.n, 0);
+  for (int v : sv) removed[vov[v]] = 1;
+  std::vector<int> o;
+  for (int v : ov) o.push_back(vov[v]);
+  OrderCost oc = order_cost(g, o, removed);
+  *cost = oc.cost;
+  *width = oc.width;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
+                           int32_t n_order, const qgm_plan_opts* opts, qgm_plan** out) {
+  GUARD_BEGIN
+  if (!c || !out) return fail(QGM_E_ARG, "null argument");
+  *out = nullptr;
+  std::vector<int> sv, ov;
+  qgm_status s = validate_plan_inputs(c->net, sliced_vars, k, order, n_order, sv, ov);
+  if (s) return s;
+  qgm_plan_opts o{};
+  o.prec = QGM_C128;
+  if (opts) o = *opts;
+  if (o.prec != QGM_C128 && o.prec != QGM_C64) return fail(QGM_E_UNSUPPORTED, "unknown precision");
+  if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_GENERATED) return fail(QGM_E_ARG, "unknown engine");
+  auto* p = new qgm_plan();
+  p->net = c->net;
+  p->sliced = sv;
+  p->order = ov;
+  p->opts = o;
+  std::string err;
+  int code = 0;
+  if (!compile_program(p->net, sv, ov, p->prog, err, code)) {
+    delete p;
+    return fail((qgm_status)code, err);
+  }
+  if (o.workspace_cap) {
+    const size_t el = o.prec == QGM_C128 ? 16 : 8;
+    size_t need = (size_t)p->prog.item_elems * 64 * el + (size_t)p->prog.n_const * el;
+    if (need > o.workspace_cap) {
+      delete p;
+      return fail(QGM_E_WORKSPACE, "plan needs " + std::to_string(need) + " bytes per wavefront, over the cap");
+    }
+  }
+  std::vector<int> vov;
+  Graph g = model_graph(p->net, vov);
+  std::vector<char> removed(g.n, 0);
+  for (int v : sv) removed[vov[v]] = 1;
+  std::vector<int> og;
+  for (int v : ov) og.push_back(vov[v]);
+  p->cost = order_cost(g, og, removed).cost;
+  // Engine: the generated kernel keeps item tensors in registers, so it is
+  // chosen automatically only when the live item memory is small.
+  const int reg_limit = o.prec == QGM_C128 ? 48 : 112;
+  bool want_gen = o.engine == QGM_ENGINE_GENERATED ||
+                  (o.engine == QGM_ENGINE_AUTO && p->prog.item_elems <= reg_limit);
+  p->engine = QGM_ENGINE_INTERPRETER;
+  if (want_gen) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::string src = generate_chain_source(p->prog, o.prec);
+    std::string jerr;
+    bool ok = jit_compile(src, "qgm_chain.hip", p->code, jerr);
+    if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
+      // debugging aid: keep the generated source and code object
+      std::string base = std::string(dir) + "/qgm_chain_" + std::to_string((uintptr_t)p);
+      if (FILE* f = std::fopen((base + ".hip").c_str(), "w")) {
+        std::fwrite(src.data(), 1, src.size(), f);
+        std::fclose(f);
+      }
+      if (ok)
+        if (FILE* f = std::fopen((base + ".co").c_str(), "wb")) {
+          std::fwrite(p->code.data(), 1, p->code.size(), f);
+          std::fclose(f);
+        }
+    }
+    if (ok) {
+      p->engine = QGM_ENGINE_GENERATED;
+    } else if (o.engine == QGM_ENGINE_GENERATED) {
+      delete p;
+      return fail(QGM_E_UNSUPPORTED, "generated kernel did not compile: " + jerr);
+    }
+    p->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  *out = p;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
+  if (!p || !out) return fail(QGM_E_ARG, "null argument");
+  qgm_stats s{};
+  s.n_steps = (int32_t)p->prog.steps.size();
+  s.n_const_steps = p->prog.n_const_steps;
+  s.max_rank = p->prog.max_rank;
+  s.item_elems = p->prog.item_elems;
+  s.n_leaves = (int32_t)p->prog.leaves.size();
+  s.k = (int32_t)p->sliced.size();
+  s.flops_item = p->prog.flops_item;
+  s.flops_const = p->prog.flops_const;
+  s.bytes_item = p->prog.bytes_item;
+  s.cost = p->cost;
+  s.engine = p->engine;
+  s.compile_s = p->compile_s;
+  *out = s;
+  return QGM_OK;
+}
+
+qgm_status qgm_workspace_size(const qgm_plan* pc, int32_t n_bs, uint64_t n_slices, size_t* bytes) {
+  GUARD_BEGIN
+  auto* p = const_cast<qgm_plan*>(pc);
+  if (!p || !bytes || n_bs < 0) return fail(QGM_E_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(p->mu);
+  qgm_status s = ensure_device(p);
+  if (s) return s;
+  WsLayout ws;
+  LaunchCfg cfg;
+  if ((s = layout_for(p, n_bs, n_slices, ws, cfg))) return s;
+  *bytes = staging(ws, n_bs, p->net.n_qubits, p->net.n_params).total;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                                 uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream,
+                                 double* d_partial) {
+  GUARD_BEGIN
+  if (!p || n_bs < 0 || (n_bs > 0 && (!d_bits || !d_partial)) || !d_ws) return fail(QGM_E_ARG, "bad argument");
+  if (p->net.n_params > 0 && !d_params) return fail(QGM_E_ARG, "circuit has RZ gates but params is NULL");
+  qgm_status s = check_range(p, s_begin, s_end);
+  if (s) return s;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if ((s = ensure_device(p))) return s;
+  WsLayout ws;
+  LaunchCfg cfg;
+  if ((s = layout_for(p, n_bs, s_end - s_begin, ws, cfg))) return s;
+  if (ws_bytes < ws.total) return fail(QGM_E_WORKSPACE, "workspace holds " + std::to_string(ws_bytes) +
+                                                             " bytes, run needs " + std::to_string(ws.total));
+  cfg.s_begin = s_begin;
+  if (n_bs == 0) return QGM_OK;
+  std::string err;
+  void* ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (p->opts.profile) {
+    std::array<hipEvent_t, 4> r{};
+    for (auto& e : r)
+      if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
+    p->runs.push_back(r);
+    for (int i = 0; i < 4; ++i) ev[i] = r[i];
+  }
+  int rc = dev_run(p->prog, p->dev, cfg, ws, d_bits, d_params, d_ws, stream, d_partial,
+                   p->opts.profile ? ev : nullptr, err);
+  if (rc) return fail((qgm_status)rc, err);
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bits, int32_t n_bs, const double* params,
+                                uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream_,
+                                double* partial) {
+  GUARD_BEGIN
+  if (!p || n_bs < 0 || (n_bs > 0 && (!bits || !partial)) || !d_ws) return fail(QGM_E_ARG, "bad argument");
+  const int nq = p->net.n_qubits;
+  for (size_t i = 0; i < (size_t)n_bs * nq; ++i)
+    if (bits[i] > 1) return fail(QGM_E_ARG, "bitstring entries must be 0 or 1");
+  if (p->net.n_params > 0 && !params) return fail(QGM_E_ARG, "circuit has RZ gates but params is NULL");
+  qgm_status s = check_range(p, s_begin, s_end);
+  if (s) return s;
+  hipStream_t stream = (hipStream_t)stream_;
+  WsLayout ws;
+  LaunchCfg cfg;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if ((s = ensure_device(p))) return s;
+    if ((s = layout_for(p, n_bs, s_end - s_begin, ws, cfg))) return s;
+  }
+  Staging st = staging(ws, n_bs, nq, p->net.n_params);
+  if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace holds " + std::to_string(ws_bytes) +
+                                                             " bytes, run needs " + std::to_string(st.total));
+  char* base = (char*)d_ws;
+  if (n_bs == 0) return QGM_OK;
+  if (hipMemcpyAsync(base + st.bits, bits, (size_t)n_bs * nq, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return fail(QGM_E_HIP, "bitstring upload failed");
+  if (p->net.n_params > 0 &&
+      hipMemcpyAsync(base + st.params, params, (size_t)p->net.n_params * sizeof(double), hipMemcpyHostToDevice,
+                     stream) != hipSuccess)
+    return fail(QGM_E_HIP, "parameter upload failed");
+  s = qgm_amplitudes_device(p, (const uint8_t*)(base + st.bits), n_bs,
+                            p->net.n_params > 0 ? (const double*)(base + st.params) : nullptr, s_begin, s_end, d_ws,
+                            ws.total, stream, (double*)(base + st.partial));
+  if (s) return s;
+  if (hipMemcpyAsync(partial, base + st.partial, (size_t)n_bs * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                     stream) != hipSuccess)
+    return fail(QGM_E_HIP, "result download failed");
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(QGM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_amplitudes(qgm_plan* p, const uint8_t* bits, int32_t n_bs, const double* params, void* d_ws,
+                          size_t ws_bytes, void* stream, double* out) {
+  GUARD_BEGIN
+  if (!p || n_bs < 0 || (n_bs > 0 && !out)) return fail(QGM_E_ARG, "bad argument");
+  std::vector<double> part((size_t)std::max(1, n_bs) * 4);
+  qgm_status s = qgm_amplitudes_range(p, bits, n_bs, params, 0, 1ull << p->sliced.size(), d_ws, ws_bytes, stream,
+                                      part.data());
+  if (s) return s;
+  for (int b = 0; b < n_bs; ++b) {
+    out[2 * b] = part[4 * b] + part[4 * b + 2];
+    out[2 * b + 1] = part[4 * b + 1] + part[4 * b + 3];
+  }
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_runs) {
+  GUARD_BEGIN
+  if (!p || !ms || !n_runs) return fail(QGM_E_ARG, "null argument");
+  if (!p->opts.profile) return fail(QGM_E_ARG, "plan was not created with opts.profile = 1");
+  std::lock_guard<std::mutex> lk(p->mu);
+  double acc[3] = {0, 0, 0};
+  for (auto& r : p->runs) {
+    if (hipEventSynchronize(r[3]) != hipSuccess) return fail(QGM_E_HIP, "hipEventSynchronize failed");
+    for (int i = 0; i < 3; ++i) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, r[i], r[i + 1]) != hipSuccess) return fail(QGM_E_HIP, "hipEventElapsedTime failed");
+      acc[i] += t;
+    }
+  }
+  const int n = (int)p->runs.size();
+  for (int i = 0; i < 3; ++i) ms[i] = n ? acc[i] / n : 0.0;
+  *n_runs = n;
+  if (reset) {
+    for (auto& r : p->runs)
+      for (hipEvent_t e : r) (void)hipEventDestroy(e);
+    p->runs.clear();
+  }
+  return QGM_OK;
+  GUARD_END
+}
+
+void qgm_plan_free(qgm_plan* p) {
+  if (!p) return;
+  dev_free(p->dev);
+  delete p;
+}
+
+qgm_status qgm_amplitude(const char* text, size_t len, const uint8_t* bitstring, const int32_t* sliced, int32_t k,
+                         const int32_t* order, int32_t n_order, const double* params, double out[2]) {
+  GUARD_BEGIN
+  if (!out) return fail(QGM_E_ARG, "null output");
+  qgm_circuit* c = nullptr;
+  qgm_status s = qgm_circuit_parse(text, len, &c);
+  if (s) return s;
+  qgm_plan* p = nullptr;
+  s = qgm_plan_create(c, sliced, k, order, n_order, nullptr, &p);
+  qgm_circuit_free(c);
+  if (s) return s;
+  size_t bytes = 0;
+  s = qgm_workspace_size(p, 1, 1ull << k, &bytes);
+  void* ws = nullptr;
+  if (!s && hipMalloc(&ws, bytes) != hipSuccess) s = fail(QGM_E_HIP, "hipMalloc of workspace failed");
+  if (!s) s = qgm_amplitudes(p, bitstring, 1, params, ws, bytes, nullptr, out);
+  if (ws) (void)hipFree(ws);
+  qgm_plan_free(p);
+  return s;
+  GUARD_END
+}
+
+}  // extern "C"

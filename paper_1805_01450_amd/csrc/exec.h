@@ -1,0 +1,63 @@
+// Device executor of the per-item contraction program (host-side API).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+namespace qgm {
+
+// Device-resident copy of a compiled program (owned by a plan).
+struct DevProgram {
+  int device = -1;
+  void* raw = nullptr;     // double2 per raw entry
+  void* rawp = nullptr;    // int per raw entry (RZ parameter index or -1)
+  void* rawb = nullptr;    // int per raw entry (RZ variable value)
+  void* steps = nullptr;
+  void* leaves = nullptr;
+  void* optab = nullptr;
+  int n_steps = 0, n_const_steps = 0;
+  int n_cu = 0;
+  size_t max_lds = 0;
+  void* module = nullptr;  // hipModule_t of the generated chain kernel
+  void* chain_fn = nullptr;  // hipFunction_t "qgm_chain"
+};
+
+// Precision of the slice contraction: 0 = complex128, 1 = complex64.
+struct LaunchCfg {
+  int prec;
+  int generated;        // 1 = generated chain kernel, 0 = interpreter
+  int n_qubits;
+  int n_bs;             // bitstrings
+  uint64_t s_begin;     // first slice index
+  uint64_t n_s;         // slices per bitstring in this call
+  int n_params;
+};
+
+struct WsLayout {
+  size_t cst, bits, res, counter, chunks, scratch, total;
+  int fused;            // generated kernel sums each block's 64 slices itself
+  int use_lds;
+  int grid;             // persistent workgroups (one wave each)
+  size_t lds_bytes;     // dynamic LDS per workgroup
+};
+
+// All functions return 0 or a negative qgm status; `err` gets a message.
+// Uploads the program tables and, when `code` is not empty, loads the
+// generated kernel's code object on the current device.
+int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& dp, std::string& err);
+void dev_free(DevProgram& dp);
+int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, WsLayout& ws, std::string& err);
+// Runs prologue, persistent chain and slice reduction on `stream`.  Device
+// inputs: bits (n_bs x n_qubits bytes), params (n_params doubles or null).
+// Device output: partial (n_bs x 4 doubles: sum re, sum im, comp re, comp im).
+// events: null, or 4 HIP events recorded before the prologue, before the
+// chain, after the chain and after the reduction.
+int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
+            const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream, double* d_partial,
+            void* const* events, std::string& err);
+int dev_query(int& n_cu, size_t& max_lds, std::string& err);
+
+}  // namespace qgm

@@ -1,0 +1,453 @@
+// Device executor: prologue (tables, constant steps), persistent per-item
+// contraction chain, and the FP64 compensated slice reduction.
+//
+// Work items are (bitstring b, slice s) pairs.  A wavefront runs 64 items
+// at once, one per lane, all following the same program; every operand
+// offset is therefore wave-uniform and is read with scalar loads.  Item
+// tensors live in LDS as [element][lane] rows, so each wavefront access is a
+// contiguous, conflict-free 64-lane row.  Constant tensors (those that depend
+// on no fixed variable) are computed once per call and read through the
+// scalar cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "exec.h"
+
+namespace qgm {
+
+namespace {
+
+struct DevStep {
+  int kind, out, r, ns, m, ops, leaf, pad;
+};
+
+struct DevLeaf {
+  int nfree, fs0, fs1, ndep;
+  int src0, bit0, ds0, src1;
+  int bit1, ds1, table, pad;
+};
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  cx<R> c;
+  c.x = a.x * b.x - a.y * b.y;
+  c.y = a.x * b.y + a.y * b.x;
+  return c;
+}
+
+constexpr uint32_t kConst = 0x80000000u;
+constexpr int kLanes = 64;
+
+#define HIP_OK(expr)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) {                                            \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return -6;                                                       \
+    }                                                                  \
+  } while (0)
+
+// ---------------------------------------------------------------- prologue
+// One workgroup.  Zeroes the work counter, packs the bitstrings, writes the
+// raw factor tables in the working precision (RZ(theta) entries
+// e^{i theta (2u-1)/2} from the angles), then runs the constant steps in
+// order.
+template <typename R>
+__global__ void __launch_bounds__(256) prologue_kernel(const double* __restrict__ raw, const int* __restrict__ rawp,
+                                                       const int* __restrict__ rawb, int n_raw,
+                                                       const double* __restrict__ params,
+                                                       const DevStep* __restrict__ steps, int n_const_steps,
+                                                       const uint32_t* __restrict__ optab, cx<R>* __restrict__ cst,
+                                                       const uint8_t* __restrict__ bits, int n_bs, int n_qubits,
+                                                       uint64_t* __restrict__ packed, unsigned* __restrict__ counter) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *counter = 0u;
+  for (int b = tid; b < n_bs; b += blockDim.x) {
+    uint64_t w = 0;
+    for (int q = 0; q < n_qubits; ++q) w |= (uint64_t)(bits[(size_t)b * n_qubits + q] & 1) << q;
+    packed[b] = w;
+  }
+  for (int e = tid; e < n_raw; e += blockDim.x) {
+    cx<R> v;
+    int p = rawp[e];
+    if (p >= 0) {
+      double half = 0.5 * params[p] * (2.0 * rawb[e] - 1.0);
+      v.x = (R)cos(half);
+      v.y = (R)sin(half);
+    } else {
+      v.x = (R)raw[2 * e];
+      v.y = (R)raw[2 * e + 1];
+    }
+    cst[e] = v;
+  }
+  __syncthreads();
+  for (int si = 0; si < n_const_steps; ++si) {
+    const DevStep st = steps[si];
+    const int nc = 1 << st.r, nsum = 1 << st.ns;
+    for (int c = tid; c < nc; c += blockDim.x) {
+      cx<R> acc{0, 0};
+      const uint32_t* op = optab + st.ops + (size_t)c * nsum * st.m;
+      for (int s = 0; s < nsum; ++s) {
+        cx<R> prod = cst[op[0] & ~kConst];
+        for (int i = 1; i < st.m; ++i) prod = cmul(prod, cst[op[i] & ~kConst]);
+        op += st.m;
+        acc.x += prod.x;
+        acc.y += prod.y;
+      }
+      cst[st.out + c] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------- chain (per item)
+template <typename R, bool LDS>
+__global__ void __launch_bounds__(64) chain_kernel(const DevStep* __restrict__ steps, int first_step, int n_steps,
+                                                   const DevLeaf* __restrict__ leaves,
+                                                   const uint32_t* __restrict__ optab,
+                                                   const cx<R>* __restrict__ cst,
+                                                   const uint64_t* __restrict__ packed, int n_bs,
+                                                   uint64_t s_begin, uint64_t n_s, uint64_t n_items,
+                                                   unsigned* __restrict__ counter, cx<R>* __restrict__ res,
+                                                   cx<R>* __restrict__ gscratch, int item_elems) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cx<R>* mem = LDS ? reinterpret_cast<cx<R>*>(lds_raw)
+                   : gscratch + (size_t)blockIdx.x * (size_t)item_elems * kLanes;
+  const int lane = threadIdx.x;
+  __shared__ unsigned chunk_sh;
+  const uint64_t n_chunks = (n_items + kLanes - 1) / kLanes;
+  for (;;) {
+    if (lane == 0) chunk_sh = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint64_t chunk = chunk_sh;
+    __syncthreads();
+    if (chunk >= n_chunks) break;
+    uint64_t item = chunk * kLanes + lane;
+    const bool valid = item < n_items;
+    if (!valid) item = n_items - 1;
+    const uint64_t b = item / n_s;
+    const uint64_t sl = item - b * n_s;
+    const uint64_t s = s_begin + sl;
+    const uint64_t xb = packed[b];
+    for (int si = first_step; si < n_steps; ++si) {
+      const DevStep st = steps[si];
+      if (st.kind == 0) {
+        const DevLeaf L = leaves[st.leaf];
+        int lane_off = 0;
+        if (L.ndep > 0) {
+          uint64_t w = L.src0 ? s : xb;
+          lane_off += (int)((w >> L.bit0) & 1) * L.ds0;
+        }
+        if (L.ndep > 1) {
+          uint64_t w = L.src1 ? s : xb;
+          lane_off += (int)((w >> L.bit1) & 1) * L.ds1;
+        }
+        const int nc = 1 << st.r;
+        for (int c = 0; c < nc; ++c) {
+          int off = L.table + lane_off + (c & 1) * L.fs0 + ((c >> 1) & 1) * L.fs1;
+          mem[(size_t)(st.out + c) * kLanes + lane] = cst[off];
+        }
+      } else {
+        const int nc = 1 << st.r, nsum = 1 << st.ns;
+        const uint32_t* op = optab + st.ops;
+        for (int c = 0; c < nc; ++c) {
+          cx<R> acc{0, 0};
+          for (int s2 = 0; s2 < nsum; ++s2) {
+            cx<R> prod{1, 0};
+            for (int i = 0; i < st.m; ++i) {
+              const uint32_t e = op[i];
+              cx<R> v;
+              if (e & kConst)
+                v = cst[e & ~kConst];
+              else
+                v = mem[(size_t)e * kLanes + lane];
+              prod = (i == 0) ? v : cmul(prod, v);
+            }
+            op += st.m;
+            acc.x += prod.x;
+            acc.y += prod.y;
+          }
+          if (st.kind == 2) {
+            if (valid) res[sl * (uint64_t)n_bs + b] = acc;
+          } else {
+            mem[(size_t)(st.out + c) * kLanes + lane] = acc;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ reduction
+// alpha_x = sum over slices, ascending s, in FP64 with Neumaier's
+// compensation (improved Kahan summation).  partial = (sum, comp) per part.
+__device__ __forceinline__ void neumaier(double& sum, double& comp, double x) {
+  double t = sum + x;
+  if (fabs(sum) >= fabs(x))
+    comp += (sum - t) + x;
+  else
+    comp += (x - t) + sum;
+  sum = t;
+}
+
+// Two-level order shared by every path: slices are taken in chunks of 64
+// (ascending s); each chunk is summed with compensation into (sum_c, comp_c);
+// the chunk sums are then added in ascending chunk order with compensation and
+// the compensations are accumulated alongside.
+template <typename R>
+__global__ void reduce_kernel(const cx<R>* __restrict__ res, int n_bs, uint64_t n_s, double* __restrict__ partial) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bs) return;
+  double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
+  for (uint64_t c0 = 0; c0 < n_s; c0 += 64) {
+    const uint64_t c1 = c0 + 64 < n_s ? c0 + 64 : n_s;
+    double cs[2] = {0, 0}, cc[2] = {0, 0};
+    for (uint64_t s = c0; s < c1; ++s) {
+      cx<R> v = res[s * (uint64_t)n_bs + b];
+      neumaier(cs[0], cc[0], (double)v.x);
+      neumaier(cs[1], cc[1], (double)v.y);
+    }
+    for (int j = 0; j < 2; ++j) {
+      neumaier(S[j], SC[j], cs[j]);
+      CC[j] += cc[j];
+    }
+  }
+  partial[4 * b + 0] = S[0];
+  partial[4 * b + 1] = S[1];
+  partial[4 * b + 2] = SC[0] + CC[0];
+  partial[4 * b + 3] = SC[1] + CC[1];
+}
+
+// Chunk partials [b][chunk][4] of the generated kernel -> per-bitstring partial.
+__global__ void combine_kernel(const double* __restrict__ chunks, int n_bs, uint64_t per_bs,
+                               double* __restrict__ partial) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bs) return;
+  double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
+  const double* p = chunks + (size_t)b * per_bs * 4;
+  for (uint64_t c = 0; c < per_bs; ++c) {
+    for (int j = 0; j < 2; ++j) {
+      neumaier(S[j], SC[j], p[4 * c + j]);
+      CC[j] += p[4 * c + 2 + j];
+    }
+  }
+  partial[4 * b + 0] = S[0];
+  partial[4 * b + 1] = S[1];
+  partial[4 * b + 2] = SC[0] + CC[0];
+  partial[4 * b + 3] = SC[1] + CC[1];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int dev_query(int& n_cu, size_t& max_lds, std::string& err) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  int lds = 0;
+  HIP_OK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  max_lds = (size_t)lds;
+  return 0;
+}
+
+int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& dp, std::string& err) {
+  if (dp.steps) return 0;
+  if (!code.empty()) {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    HIP_OK(hipModuleLoadData(&mod, code.data()));
+    hipError_t e = hipModuleGetFunction(&fn, mod, "qgm_chain");
+    if (e != hipSuccess) {
+      (void)hipModuleUnload(mod);
+      err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+      return -6;
+    }
+    dp.module = mod;
+    dp.chain_fn = fn;
+  }
+  HIP_OK(hipGetDevice(&dp.device));
+  int rc = dev_query(dp.n_cu, dp.max_lds, err);
+  if (rc) return rc;
+  std::vector<DevStep> ds(prog.steps.size());
+  for (size_t i = 0; i < prog.steps.size(); ++i) {
+    const Step& s = prog.steps[i];
+    ds[i] = DevStep{s.kind, s.out, s.r, s.ns, s.m, s.ops, s.leaf, 0};
+  }
+  std::vector<DevLeaf> dl(prog.leaves.size());
+  for (size_t i = 0; i < prog.leaves.size(); ++i) {
+    const Leaf& L = prog.leaves[i];
+    dl[i] = DevLeaf{L.nfree, L.free_stride[0], L.free_stride[1], L.ndep, L.dep_src[0], L.dep_bit[0],
+                    L.dep_stride[0], L.dep_src[1], L.dep_bit[1], L.dep_stride[1], L.table, 0};
+  }
+  auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+    HIP_OK(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+    if (bytes) HIP_OK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return 0;
+  };
+  if ((rc = up(&dp.raw, prog.raw.data(), prog.raw.size() * sizeof(double)))) return rc;
+  if ((rc = up(&dp.rawp, prog.raw_param.data(), prog.raw_param.size() * sizeof(int)))) return rc;
+  if ((rc = up(&dp.rawb, prog.raw_bit.data(), prog.raw_bit.size() * sizeof(int)))) return rc;
+  if ((rc = up(&dp.leaves, dl.data(), dl.size() * sizeof(DevLeaf)))) return rc;
+  if ((rc = up(&dp.optab, prog.optab.data(), prog.optab.size() * sizeof(uint32_t)))) return rc;
+  if ((rc = up(&dp.steps, ds.data(), ds.size() * sizeof(DevStep)))) return rc;
+  dp.n_steps = (int)prog.steps.size();
+  dp.n_const_steps = prog.n_const_steps;
+  return 0;
+}
+
+void dev_free(DevProgram& dp) {
+  void* ps[] = {dp.raw, dp.rawp, dp.rawb, dp.steps, dp.leaves, dp.optab};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  if (dp.module) (void)hipModuleUnload((hipModule_t)dp.module);
+  dp = DevProgram();
+}
+
+int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, WsLayout& ws, std::string& err) {
+  const size_t el = cfg.prec == 0 ? 16 : 8;
+  const uint64_t n_items = (uint64_t)cfg.n_bs * cfg.n_s;
+  const uint64_t n_chunks = (n_items + kLanes - 1) / kLanes;
+  ws.fused = (cfg.generated && cfg.n_s % kLanes == 0) ? 1 : 0;
+  size_t lds = (size_t)prog.item_elems * kLanes * el;
+  if (cfg.generated) lds = 0;
+  // 64 bytes of headroom for the kernel's static LDS (the work-queue slot)
+  ws.use_lds = (!cfg.generated && lds + 64 <= dp.max_lds) ? 1 : 0;
+  ws.lds_bytes = ws.use_lds ? lds : 0;
+  int per_cu = 8;
+  if (ws.use_lds) {
+    int occ = 0;
+    hipError_t e = cfg.prec == 0
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<double, true>, 64, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<float, true>, 64, lds);
+    if (e != hipSuccess || occ <= 0) occ = (int)std::max<size_t>(1, dp.max_lds / std::max<size_t>(lds, 1));
+    per_cu = std::min(occ, 8);
+    if (lds > 65536) {
+      if (cfg.prec == 0)
+        (void)hipFuncSetAttribute((const void*)chain_kernel<double, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      else
+        (void)hipFuncSetAttribute((const void*)chain_kernel<float, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+  }
+  uint64_t grid = (uint64_t)std::max(1, dp.n_cu) * per_cu;
+  if (grid > n_chunks) grid = n_chunks;
+  if (grid == 0) grid = 1;
+  ws.grid = (int)grid;
+  size_t off = 0;
+  ws.cst = off;
+  off = align256(off + (size_t)std::max(prog.n_const, 1) * el);
+  ws.bits = off;
+  off = align256(off + (size_t)std::max(cfg.n_bs, 1) * 8);
+  ws.res = off;
+  off = align256(off + (size_t)std::max<uint64_t>(n_items, 1) * el);
+  ws.counter = off;
+  off = align256(off + 256);
+  ws.chunks = off;
+  off = align256(off + (size_t)std::max<uint64_t>(n_chunks, 1) * 4 * sizeof(double));
+  ws.scratch = off;
+  if (!cfg.generated && !ws.use_lds) off = align256(off + (size_t)ws.grid * prog.item_elems * kLanes * el);
+  ws.total = off;
+  (void)err;
+  return 0;
+}
+
+namespace {
+
+template <typename R>
+int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
+              const uint8_t* d_bits, const double* d_params, char* base, hipStream_t stream, double* d_partial,
+              void* const* events, std::string& err) {
+  auto mark = [&](int i) {
+    if (events) (void)hipEventRecord((hipEvent_t)events[i], stream);
+  };
+  const uint64_t n_items = (uint64_t)cfg.n_bs * cfg.n_s;
+  auto* packed = (uint64_t*)(base + ws.bits);
+  auto* counter = (unsigned*)(base + ws.counter);
+  auto* cst = (cx<R>*)(base + ws.cst);
+  auto* res = (cx<R>*)(base + ws.res);
+  auto* scr = (cx<R>*)(base + ws.scratch);
+  auto* chunks = (double*)(base + ws.chunks);
+  const int first = dp.n_const_steps;
+  const dim3 red_grid((cfg.n_bs + 63) / 64);
+  mark(0);
+  // The generated kernel reads the FP64 tables and the bitstring bytes itself.
+  if (!cfg.generated || n_items == 0)
+    hipLaunchKernelGGL(prologue_kernel<R>, dim3(1), dim3(256), 0, stream, (const double*)dp.raw, (const int*)dp.rawp,
+                       (const int*)dp.rawb, prog.n_raw, d_params, (const DevStep*)dp.steps, dp.n_const_steps,
+                       (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs, cfg.n_qubits, packed, counter);
+  mark(1);
+  if (n_items == 0) {
+    mark(2);
+    hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    mark(3);
+    HIP_OK(hipGetLastError());
+    return 0;
+  }
+  if (cfg.generated) {
+    const uint64_t n_blocks = (n_items + kLanes - 1) / kLanes;
+    const uint64_t per_bs = cfg.n_s / kLanes;
+    // With one block per bitstring the block partial is the final partial.
+    double* part = (ws.fused && per_bs == 1) ? d_partial : chunks;
+    unsigned long long a_nbs = (unsigned long long)cfg.n_bs, a_sb = cfg.s_begin, a_ns = cfg.n_s, a_ni = n_items;
+    const void* a_raw = dp.raw;
+    const void* a_par = d_params;
+    const void* a_bits = d_bits;
+    int a_nq = cfg.n_qubits;
+    void* a_res = res;
+    void* a_part = part;
+    int a_fused = ws.fused;
+    void* args[] = {&a_raw, &a_par, &a_bits, &a_nq, &a_nbs, &a_sb, &a_ns, &a_ni, &a_res, &a_part, &a_fused};
+    HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes, 1, 1, 0, stream,
+                                 args, nullptr));
+    mark(2);
+    if (!ws.fused)
+      hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    else if (per_bs > 1)
+      hipLaunchKernelGGL(combine_kernel, red_grid, dim3(64), 0, stream, chunks, cfg.n_bs, per_bs, d_partial);
+    mark(3);
+  } else {
+    if (ws.use_lds)
+      hipLaunchKernelGGL((chain_kernel<R, true>), dim3(ws.grid), dim3(64), ws.lds_bytes, stream,
+                         (const DevStep*)dp.steps, first, dp.n_steps, (const DevLeaf*)dp.leaves,
+                         (const uint32_t*)dp.optab, cst, packed, cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res,
+                         scr, prog.item_elems);
+    else
+      hipLaunchKernelGGL((chain_kernel<R, false>), dim3(ws.grid), dim3(64), 0, stream, (const DevStep*)dp.steps,
+                         first, dp.n_steps, (const DevLeaf*)dp.leaves, (const uint32_t*)dp.optab, cst, packed,
+                         cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res, scr, prog.item_elems);
+    mark(2);
+    hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    mark(3);
+  }
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
+            const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream_, double* d_partial,
+            void* const* events, std::string& err) {
+  if (cfg.n_bs == 0) return 0;
+  if (cfg.generated && !dp.chain_fn) {
+    err = "generated kernel not loaded";
+    return -6;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  if (cfg.prec == 0)
+    return run_typed<double>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, events, err);
+  return run_typed<float>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, events, err);
+}
+
+}  // namespace qgm

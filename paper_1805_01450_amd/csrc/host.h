@@ -1,0 +1,128 @@
+// Host-side data structures of the qgm library: circuit, graphical model,
+// planner and the compiled per-slice contraction program.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qgm {
+
+enum GateKind { G_H = 0, G_SX, G_SY, G_T, G_RZ, G_I, G_CZ };
+
+struct Gate {
+  int cycle;
+  GateKind kind;
+  int q0, q1;
+  int param;
+  int line;
+};
+
+// One binary variable of the undirected graphical model: a distinct index
+// value i_k^(j) of the Feynman sum, Eq. (1).
+struct Var {
+  int id, qubit, cycle, is_output;
+};
+
+// A factor over at most two variables.  Table entry b = sum_j bit(var_j) << j.
+// param >= 0 marks an RZ(theta_param) diagonal whose table is made on the
+// device from the angle.
+struct Factor {
+  int nv;
+  int var[2];
+  int param;
+  double tab[8];  // re, im pairs
+};
+
+struct Network {
+  int n_qubits = 0, n_params = 0;
+  std::vector<Gate> gates;
+  std::vector<Var> vars;
+  std::vector<Factor> factors;
+  std::vector<int> output_var;  // per qubit; -1 = input constant
+  std::vector<int> free_vars;   // non-output variables, ascending id
+};
+
+bool parse_circuit(const char* text, size_t len, Network& net, std::string& err);
+void build_network(Network& net);
+
+// ------------------------------------------------------------------ planner
+struct Graph {
+  int n = 0, words = 0;
+  std::vector<uint64_t> adj;  // n rows of `words` words
+  uint64_t* row(int v) { return adj.data() + (size_t)v * words; }
+  const uint64_t* row(int v) const { return adj.data() + (size_t)v * words; }
+  void init(int n_);
+  void add_edge(int a, int b);
+  bool has(int a, int b) const { return (row(a)[b >> 6] >> (b & 63)) & 1; }
+};
+
+// Graph over the free variables (vertex i = net.free_vars[i]); outputs fixed.
+Graph model_graph(const Network& net, std::vector<int>& vertex_of_var);
+
+struct OrderCost {
+  double cost;  // sum over steps of 2^deg(v)
+  int width;    // max deg(v)
+};
+OrderCost order_cost(const Graph& g, const std::vector<int>& order, const std::vector<char>& removed);
+std::vector<int> min_fill_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, int randomize);
+bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars);
+
+// ------------------------------------------------------------------ program
+// Operand reference of a fused elimination step.
+enum : uint32_t { OP_CONST = 0x80000000u };
+
+struct Leaf {
+  int factor;        // index into net.factors, or -1 for a delta(x_q, 0) leaf
+  int nfree;         // free variables (0..2)
+  int free_var[2];
+  int free_stride[2];
+  int ndep;          // fixed variables the table is indexed at (0..2)
+  int dep_src[2];    // 0 = output bit (qubit), 1 = slice bit
+  int dep_bit[2];
+  int dep_stride[2];
+  int table;         // element offset of the raw table in the constant area
+};
+
+// Step kinds of the per-item program.
+enum StepKind { ST_LEAF = 0, ST_ELIM = 1, ST_FINAL = 2 };
+
+struct Step {
+  int kind;
+  int is_const;   // runs once per call in the prologue (all operands constant)
+  int out;        // element offset: item memory (LDS) or constant area
+  int r, ns, m;   // output rank, summed variables, operands
+  int ops;        // offset into the operand table (2^(r+ns) * m entries)
+  int leaf;       // ST_LEAF: leaf index
+  double flops;   // useful real flops per item
+};
+
+struct Program {
+  std::vector<Leaf> leaves;
+  std::vector<Step> steps;
+  std::vector<uint32_t> optab;
+  std::vector<double> raw;       // raw factor tables, complex (re,im), const-area layout
+  std::vector<int> raw_param;    // per raw complex entry: RZ parameter index or -1
+  std::vector<int> raw_bit;      // per raw complex entry: 0/1 value of the RZ variable
+  int n_raw = 0;                 // complex entries of raw tables
+  int n_const = 0;               // total constant-area elements (raw + const intermediates)
+  int item_elems = 0;            // peak item-memory elements per item
+  int n_const_steps = 0;
+  int max_rank = 0;
+  double flops_item = 0, flops_const = 0;
+  double bytes_item = 0;         // algorithmic bytes per item at 8 B per element
+};
+
+bool validate_plan(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
+                   std::string& err, int& code);
+bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
+                     Program& prog, std::string& err, int& code);
+
+// Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
+// prec 0 = complex128, 1 = complex64.
+std::string generate_chain_source(const Program& prog, int prec);
+// hiprtc compilation of `src` for gfx950 into a code object.
+bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
+
+}  // namespace qgm

@@ -1,0 +1,267 @@
+// Planner (Section "The variable elimination ordering" and Section
+// "Parallelization by fixing the values of variables").
+//
+// * Cost of an ordering: eliminating v creates a tensor of size 2^deg(v) in
+//   the graph at that moment; the cost of an ordering is the sum over steps.
+// * Ordering: greedy min-fill (the branching heuristic the paper runs its
+//   anytime search with), with randomised tie-breaking restarts kept when
+//   they lower the cost.
+// * Slicing: vertices are removed greedily, each time the one that most
+//   lowers the cost under one fixed ordering; the ordering is recomputed
+//   after the removals.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+#include "host.h"
+
+namespace qgm {
+
+void Graph::init(int n_) {
+  n = n_;
+  words = (n + 63) / 64;
+  if (words == 0) words = 1;
+  adj.assign((size_t)n * words, 0);
+}
+
+void Graph::add_edge(int a, int b) {
+  if (a == b) return;
+  row(a)[b >> 6] |= 1ull << (b & 63);
+  row(b)[a >> 6] |= 1ull << (a & 63);
+}
+
+Graph model_graph(const Network& net, std::vector<int>& vertex_of_var) {
+  vertex_of_var.assign(net.vars.size(), -1);
+  for (size_t i = 0; i < net.free_vars.size(); ++i) vertex_of_var[net.free_vars[i]] = (int)i;
+  Graph g;
+  g.init((int)net.free_vars.size());
+  for (const Factor& f : net.factors) {
+    if (f.nv == 2) {
+      int a = vertex_of_var[f.var[0]], b = vertex_of_var[f.var[1]];
+      if (a >= 0 && b >= 0) g.add_edge(a, b);
+    }
+  }
+  return g;
+}
+
+static inline int popcount_row(const uint64_t* r, int words) {
+  int c = 0;
+  for (int w = 0; w < words; ++w) c += __builtin_popcountll(r[w]);
+  return c;
+}
+
+// Eliminate v in place: connect its neighbours, then drop v.
+static int eliminate(Graph& g, int v) {
+  uint64_t* rv = g.row(v);
+  int deg = popcount_row(rv, g.words);
+  std::vector<uint64_t> nb(rv, rv + g.words);
+  for (int w = 0; w < g.words; ++w) {
+    uint64_t bits = nb[w];
+    while (bits) {
+      int u = w * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      uint64_t* ru = g.row(u);
+      for (int x = 0; x < g.words; ++x) ru[x] |= nb[x];
+      ru[u >> 6] &= ~(1ull << (u & 63));
+      ru[v >> 6] &= ~(1ull << (v & 63));
+    }
+  }
+  std::memset(rv, 0, sizeof(uint64_t) * g.words);
+  return deg;
+}
+
+static void drop(Graph& g, int v) {
+  uint64_t* rv = g.row(v);
+  for (int w = 0; w < g.words; ++w) {
+    uint64_t bits = rv[w];
+    while (bits) {
+      int u = w * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      g.row(u)[v >> 6] &= ~(1ull << (v & 63));
+    }
+    rv[w] = 0;
+  }
+}
+
+OrderCost order_cost(const Graph& g0, const std::vector<int>& order, const std::vector<char>& removed) {
+  Graph g = g0;
+  for (int v = 0; v < g.n; ++v)
+    if (removed[v]) drop(g, v);
+  OrderCost c{0.0, 0};
+  for (int v : order) {
+    if (removed[v]) continue;
+    int d = eliminate(g, v);
+    c.cost += std::ldexp(1.0, d);
+    c.width = std::max(c.width, d);
+  }
+  return c;
+}
+
+static int fill_in(const Graph& g, int v) {
+  const uint64_t* rv = g.row(v);
+  int missing = 0;
+  for (int w = 0; w < g.words; ++w) {
+    uint64_t bits = rv[w];
+    while (bits) {
+      int u = w * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      // neighbours of v that are not neighbours of u (excluding u), counted once per pair
+      const uint64_t* ru = g.row(u);
+      for (int x = 0; x < g.words; ++x) {
+        uint64_t m = rv[x] & ~ru[x];
+        if (x == (u >> 6)) m &= ~(1ull << (u & 63));
+        missing += __builtin_popcountll(m);
+      }
+    }
+  }
+  return missing / 2;
+}
+
+std::vector<int> min_fill_order(const Graph& g0, const std::vector<char>& removed, uint64_t seed, int randomize) {
+  Graph g = g0;
+  std::vector<char> alive(g.n, 1);
+  int left = 0;
+  for (int v = 0; v < g.n; ++v) {
+    if (removed[v]) {
+      drop(g, v);
+      alive[v] = 0;
+    } else {
+      ++left;
+    }
+  }
+  std::mt19937_64 rng(seed);
+  std::vector<int> order;
+  order.reserve(left);
+  std::vector<int> fill(g.n, 0);
+  std::vector<char> dirty(g.n, 1);
+  while (left > 0) {
+    int best = -1;
+    long best_key = 0;
+    std::vector<int> ties;
+    for (int v = 0; v < g.n; ++v) {
+      if (!alive[v]) continue;
+      if (dirty[v]) {
+        fill[v] = fill_in(g, v);
+        dirty[v] = 0;
+      }
+      long key = (long)fill[v] * 4096 + popcount_row(g.row(v), g.words);
+      if (best < 0 || key < best_key) {
+        best = v;
+        best_key = key;
+        ties.clear();
+        ties.push_back(v);
+      } else if (key == best_key) {
+        ties.push_back(v);
+      }
+    }
+    if (randomize && ties.size() > 1) best = ties[rng() % ties.size()];
+    // fill counts change for the neighbours of `best` and their neighbours
+    const uint64_t* rb = g.row(best);
+    for (int w = 0; w < g.words; ++w) {
+      uint64_t bits = rb[w];
+      while (bits) {
+        int u = w * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        dirty[u] = 1;
+        const uint64_t* ru = g.row(u);
+        for (int x = 0; x < g.words; ++x) {
+          uint64_t b2 = ru[x];
+          while (b2) {
+            dirty[x * 64 + __builtin_ctzll(b2)] = 1;
+            b2 &= b2 - 1;
+          }
+        }
+      }
+    }
+    eliminate(g, best);
+    alive[best] = 0;
+    order.push_back(best);
+    --left;
+  }
+  return order;
+}
+
+}  // namespace qgm
+
+namespace qgm {
+
+// Best of several min-fill orderings (deterministic first, then randomised
+// tie-breaking) until the time budget is spent.
+static std::vector<int> best_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, double budget_s,
+                                   OrderCost* out_cost) {
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<int> best = min_fill_order(g, removed, seed, 0);
+  OrderCost bc = order_cost(g, best, removed);
+  // At most kMaxRestarts restarts, so small graphs give the same ordering on
+  // every run; large graphs may stop earlier on the time budget.
+  const int kMaxRestarts = 128;
+  for (int it = 1; it <= kMaxRestarts; ++it) {
+    double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (el >= budget_s) break;
+    std::vector<int> o = min_fill_order(g, removed, seed + 0x9e3779b97f4a7c15ull * it, 1);
+    OrderCost c = order_cost(g, o, removed);
+    if (c.cost < bc.cost || (c.cost == bc.cost && c.width < bc.width)) {
+      best.swap(o);
+      bc = c;
+    }
+  }
+  if (out_cost) *out_cost = bc;
+  return best;
+}
+
+// Greedy key-vertex removal: at each round remove the vertex whose removal
+// gives the lowest cost under the fixed ordering `order0` (ties: lower width,
+// then lower vertex id).  Candidates are the `n_cand` highest-degree
+// vertices of the graph with the previous picks removed.
+bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars) {
+  std::vector<int> vov;
+  Graph g = model_graph(net, vov);
+  std::vector<char> removed(g.n, 0);
+  double b0 = k_req == 0 ? time_budget_s : time_budget_s * 0.4;
+  OrderCost c0;
+  std::vector<int> order0 = best_order(g, removed, seed, b0, &c0);
+  std::vector<int> picks;
+  const int n_cand = 64;
+  int kmax = k_req >= 0 ? k_req : 40;
+  OrderCost cur = c0;
+  while ((int)picks.size() < kmax && (int)picks.size() < g.n) {
+    if (k_req < 0 && cur.width <= target_rank) break;
+    // current graph degrees (with picks removed)
+    Graph gr = g;
+    for (int p : picks) drop(gr, p);
+    std::vector<std::pair<int, int>> cand;
+    for (int v = 0; v < g.n; ++v)
+      if (!removed[v]) cand.push_back({-popcount_row(gr.row(v), gr.words), v});
+    std::sort(cand.begin(), cand.end());
+    if ((int)cand.size() > n_cand) cand.resize(n_cand);
+    int best_v = -1;
+    OrderCost best_c{0, 0};
+    for (auto& cv : cand) {
+      int v = cv.second;
+      removed[v] = 1;
+      OrderCost c = order_cost(g, order0, removed);
+      removed[v] = 0;
+      if (best_v < 0 || c.cost < best_c.cost || (c.cost == best_c.cost && (c.width < best_c.width ||
+                                                                           (c.width == best_c.width && v < best_v)))) {
+        best_v = v;
+        best_c = c;
+      }
+    }
+    if (best_v < 0) break;
+    removed[best_v] = 1;
+    picks.push_back(best_v);
+    cur = best_c;
+  }
+  double b1 = k_req == 0 ? 0.0 : time_budget_s * 0.6;
+  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr);
+  sliced_vars.clear();
+  for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
+  order_vars.clear();
+  for (int v : order1) order_vars.push_back(net.free_vars[v]);
+  return true;
+}
+
+}  // namespace qgm

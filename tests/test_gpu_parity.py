@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Error measure: e = |alpha - alpha_ref| / max(|alpha_ref|, 2^{-N/2}); this is
+the relative error for amplitudes of typical size (|alpha| ~ 2^{-N/2} for
+random circuits) and a scaled absolute error for near-zero ones.
+Tolerances: complex128 1e-12; complex64 (FP32 arithmetic, unit roundoff
+u = 2^-24) C64_TOL, a bound on accumulated rounding over a few hundred
+dependent operations per slice times the slice-sum cancellation factor.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1805_01450_amd as q
+from tests.conftest import golden_path
+from workload import generate_circuit, parse_header, random_bitstrings, random_thetas
+
+pytestmark = pytest.mark.gpu
+
+C128_TOL = 1e-12
+C64_TOL = 2e-4
+
+
+def nerr(a, ref, n_qubits):
+    a = np.asarray(a)
+    ref = np.asarray(ref)
+    return np.abs(a - ref) / np.maximum(np.abs(ref), 2.0 ** (-n_qubits / 2))
+
+
+def note(*args):
+    print("[gpu-parity]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+ENGINES = [q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED]
+
+
+def run(text, bits, k=0, prec=q.QGM_C128, params=None, seed=0, engine=q.QGM_ENGINE_AUTO):
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=k, time_budget_s=0.5, seed=seed)
+    p = q.Plan(c, sl, order, prec=prec, engine=engine)
+    if engine != q.QGM_ENGINE_AUTO:
+        assert p.stats()["engine"] == engine
+    return p.amplitudes(bits, params), p
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_config1_4x4x10_c128(seed):
+    text = generate_circuit(4, 10, seed)
+    x = np.zeros((1, 16), np.uint8)
+    note("4x4x10 seed", seed, "x=0^16 k=0 c128")
+    got, _ = run(text, x)
+    ref = oracle.sv_amplitudes(text, x)
+    assert nerr(got, ref, 16).max() <= C128_TOL
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("prec,tol", [(q.QGM_C128, C128_TOL), (q.QGM_C64, C64_TOL)])
+def test_fig2_all_outputs(fig2_text, prec, tol, engine):
+    bits = np.array([[(i >> j) & 1 for j in range(4)] for i in range(16)], np.uint8)
+    note("fig2 circuit, all 16 x, prec", prec, "engine", engine)
+    got, _ = run(fig2_text, bits, prec=prec, engine=engine)
+    ref = oracle.sv_amplitudes(fig2_text, bits)
+    assert np.abs(got - ref).max() <= tol
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_closed_forms(engine):
+    n = 5
+    allx = np.array([[(i >> j) & 1 for j in range(n)] for i in range(1 << n)], np.uint8)
+    note("closed forms, 5 qubits")
+    # empty circuit: delta(x, 0)
+    got, _ = run(f"qubits {n}\n", allx, engine=engine)
+    want = np.zeros(1 << n)
+    want[0] = 1
+    assert np.abs(got - want).max() == 0
+    # H layer then diagonal gates (CZ, T, RZ): closed-form phases
+    rng = np.random.default_rng(3)
+    lines = [f"qubits {n}"] + [f"0 H {qq}" for qq in range(n)]
+    th = rng.uniform(0, 2 * np.pi, 3)
+    lines += ["1 CZ 0 1", "1 T 2", "1 RZ 3 0", "2 CZ 1 4", "2 RZ 0 1", "3 CZ 2 3", "3 RZ 4 2", "4 T 0"]
+    text = "\n".join(lines)
+    got, _ = run(text, allx, params=th, engine=engine)
+    ref = oracle.sv_amplitudes(text, allx, th)
+    assert np.abs(got - ref).max() <= 1e-14
+    # a qubit that never gets a non-diagonal gate contributes delta(x_q, 0)
+    text = "qubits 3\n0 H 0\n0 H 2\n1 T 1\n2 CZ 0 1\n3 SX 2\n"
+    allx3 = allx[:8, :3]
+    got, _ = run(text, allx3, engine=engine)
+    ref = oracle.sv_amplitudes(text, allx3)
+    assert np.abs(got - ref).max() <= 1e-15
+
+
+@pytest.fixture(scope="module")
+def config2():
+    text = generate_circuit(5, 20, 0)
+    bits = random_bitstrings(25, 64, 1000)
+    ref = np.array([oracle.ve_amplitude(text, x) for x in bits])
+    return text, bits, ref
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("prec,tol", [(q.QGM_C128, C128_TOL), (q.QGM_C64, C64_TOL)])
+def test_config2_5x5x20_k6(config2, prec, tol, engine):
+    text, bits, ref = config2
+    note("5x5x20 seed 0, 64 bitstrings, k=6, prec", prec, "engine", engine)
+    got, p = run(text, bits, k=6, prec=prec, engine=engine)
+    assert p.k == 6
+    e = nerr(got, ref, 25)
+    note("max normalised error", e.max())
+    assert e.max() <= tol
+
+
+def test_slicing_and_order_invariance_on_device(config2):
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    outs = []
+    for k, seed in [(0, 0), (3, 1), (6, 2), (9, 3), (12, 4)]:
+        sl, order = c.plan_slices(k_req=k, time_budget_s=0.2, seed=seed)
+        note("invariance k", k)
+        outs.append(q.Plan(c, sl, order).amplitudes(bits[:8]))
+    # a different (random) elimination order of the same slices
+    sl, order = c.plan_slices(k_req=4, time_budget_s=0.0)
+    rng = np.random.default_rng(0)
+    outs.append(q.Plan(c, sl, list(rng.permutation(order))).amplitudes(bits[:8]))
+    for o in outs:
+        assert nerr(o, ref[:8], 25).max() <= C128_TOL
+
+
+def test_range_resume_equals_full(config2):
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    p = q.Plan(c, sl, order)
+    full = p.amplitudes_range(bits, None, 0, 64)
+    a = p.amplitudes_range(bits, None, 0, 23)     # stop after 23 slices
+    b = p.amplitudes_range(bits, None, 23, 64)    # resume
+    tot_full = full[:, 0] + full[:, 2] + 1j * (full[:, 1] + full[:, 3])
+    tot = (a[:, 0] + b[:, 0]) + (a[:, 2] + b[:, 2]) + 1j * ((a[:, 1] + b[:, 1]) + (a[:, 3] + b[:, 3]))
+    assert nerr(tot, ref, 25).max() <= C128_TOL
+    assert nerr(tot_full, ref, 25).max() <= C128_TOL
+    empty = p.amplitudes_range(bits, None, 5, 5)
+    assert np.all(empty == 0)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_engines_agree_bitwise_on_reduction_order(config2, engine):
+    """k = 8: 4 chunks of 64 slices per bitstring (fused chunk partials + combine)."""
+    text, bits, ref = config2
+    note("k=8 chunked slice sums, engine", engine)
+    got, p = run(text, bits[:16], k=8, engine=engine)
+    assert nerr(got, ref[:16], 25).max() <= C128_TOL
+
+
+def test_device_entry_matches_host_entry(config2, cuda):
+    torch = cuda
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64)
+    host = p.amplitudes(bits)
+    d_bits = torch.from_numpy(bits).cuda()
+    d_part = torch.empty((64, 4), dtype=torch.float64, device="cuda")
+    ws = p.workspace(64)
+    q.qgm_amplitudes_device(p.h, d_bits, None, 0, 64, ws, d_part)
+    part = d_part.cpu().numpy()
+    dev = part[:, 0] + part[:, 2] + 1j * (part[:, 1] + part[:, 3])
+    assert np.array_equal(dev, host)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n_bs,k", [(1, 0), (63, 1), (65, 2), (130, 0), (7, 7), (3, 8)])
+def test_ragged_batches(n_bs, k, engine):
+    text = generate_circuit(4, 12, 5)
+    bits = random_bitstrings(16, n_bs, 77 + n_bs)
+    note("ragged n_bs", n_bs, "k", k, "engine", engine)
+    got, _ = run(text, bits, k=k, prec=q.QGM_C64, engine=engine)
+    psi = oracle.sv_state(text)
+    ref = np.array([psi[int(sum(int(b) << j for j, b in enumerate(x)))] for x in bits])
+    assert nerr(got, ref, 16).max() <= C64_TOL
+
+
+def test_rz_parameters_and_gradient_by_shift(cuda):
+    text = generate_circuit(4, 10, 3, rz=True)
+    _, npar = parse_header(text)
+    th = random_thetas(npar, 2003)
+    bits = random_bitstrings(16, 4, 1003)
+    note("RZ circuit, params", npar)
+    got, p = run(text, bits, k=2, params=th)
+    ref = oracle.sv_amplitudes(text, bits, th)
+    assert nerr(got, ref, 16).max() <= C128_TOL
+    # shift rule through the device path: d alpha/d theta_0 = alpha(theta + pi e_0)/2
+    th2 = th.copy()
+    th2[0] += np.pi
+    g = 0.5 * p.amplitudes(bits, th2)
+    gref = np.array([oracle.sv_gradient_shift(text, x, th, which=[0])[0] for x in bits])
+    assert np.abs(g - gref).max() <= 1e-13
+
+
+def test_errors_on_device(config2, cuda):
+    torch = cuda
+    text, bits, _ = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.1)
+    p = q.Plan(c, sl, order)
+    need = q.qgm_workspace_size(p.h, 4, 8)
+    small = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(q.QgmError) as e:
+        q.qgm_amplitudes(p.h, bits[:4], None, small)
+    assert e.value.status == -5
+    bad = bits[:2].copy()
+    bad[0, 0] = 2
+    with pytest.raises(q.QgmError) as e:
+        p.amplitudes(bad)
+    assert e.value.status == -1
+    with pytest.raises(q.QgmError) as e:
+        p.amplitudes_range(bits[:2], None, 0, 9)
+    assert e.value.status == -1
+    assert p.amplitudes(bits[:0]).shape == (0,)
+
+
+def test_one_shot_entry(config2):
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=2, time_budget_s=0.1)
+    a = q.qgm_amplitude(text, bits[5], sl, order)
+    assert nerr(a, ref[5], 25) <= C128_TOL
+
+
+def test_config3_6x6x25_one_launch():
+    text = generate_circuit(6, 25, 0)
+    bits = random_bitstrings(36, 1024, 1000)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=10, time_budget_s=1.0)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64)
+    note("6x6x25, 1024 bitstrings x 2^10 slices, c64, stats", p.stats())
+    got = p.amplitudes(bits)
+    sub = list(range(0, 1024, 64))
+    ref = np.array([oracle.ve_amplitude(text, bits[i]) for i in sub])
+    e = nerr(got[sub], ref, 36)
+    note("subset max normalised error", e.max())
+    assert e.max() <= C64_TOL
+    # sum_x |alpha_x|^2 = 1 implies E_x[2^N |alpha_x|^2] = 1 over uniform x
+    m1 = np.mean((2.0 ** 36) * np.abs(got) ** 2)
+    note("Porter-Thomas first moment", m1)
+    assert abs(m1 - 1.0) < 0.2

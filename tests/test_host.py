@@ -1,0 +1,136 @@
+"""CPU tests of the C-ABI library: loading, exported symbols, parser, graph
+model, planner and plan validation.  No device code runs here."""
+import math
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1805_01450_amd as q
+from oracle.elimination import order_cost as oracle_order_cost
+from oracle.network import build_network
+from tests.conftest import ROOT
+from workload import generate_circuit
+
+
+def test_header_symbols_are_exported():
+    import subprocess
+    hdr = open(f"{ROOT}/include/qgm.h").read()
+    declared = set(re.findall(r"\b(qgm_\w+)\s*\(", hdr))
+    assert declared == set(q.DECLARED)
+    out = subprocess.run(["nm", "-D", "--defined-only", q.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (qgm_\w+)", out))
+    assert declared <= exported
+
+
+@pytest.mark.parametrize("text,needle", [
+    ("0 H 0\n", "qubits"),
+    ("qubits 2\n0 X 0\n", "unknown gate"),
+    ("qubits 2\n0 H 2\n", "out of range"),
+    ("qubits 2\n0 CZ 1 1\n", "single qubit"),
+    ("qubits 2\n0 H 0\n0 T 0\n", "two gates"),
+    ("qubits 2\n0 RZ 0\n", "fields"),
+    ("qubits 65\n", "qubits"),
+])
+def test_parse_errors(text, needle):
+    with pytest.raises(q.QgmError) as e:
+        q.qgm_circuit_parse(text)
+    assert e.value.status == -2 and needle in str(e.value)
+
+
+@pytest.mark.parametrize("n,d,seed,rz", [(4, 10, 0, False), (5, 20, 1, True), (6, 25, 2, False)])
+def test_variables_and_graph_match_oracle(n, d, seed, rz):
+    text = generate_circuit(n, d, seed, rz=rz)
+    c = q.Circuit(text)
+    net = build_network(text, np.zeros(c.n_params))
+    assert c.n_vars == len(net.variables) and c.n_qubits == n * n
+    ours = c.vars()
+    theirs = [(v.id, v.qubit, v.cycle, int(v.is_output)) for v in net.variables]
+    assert ours == theirs
+    outs = [v.id for v in net.variables if v.is_output]
+    assert set(c.graph()) == net.graph_edges(exclude=outs)
+
+
+def test_fig2_graph(fig2_text):
+    c = q.Circuit(fig2_text)
+    # Fig. 3: 10 free vertices and 12 edges; the letters map to ids 0..9
+    # in creation order a b c d e f g h i j
+    letters = "abcdefghij"
+    edges = {"".join(sorted(letters[a] + letters[b])) for a, b in c.graph()}
+    assert edges == set("ab ae ah be bg ce df ef fg gj hi ij".split())
+
+
+def _plan(n, d, seed, k):
+    c = q.Circuit(generate_circuit(n, d, seed))
+    sl, order = c.plan_slices(k_req=k, time_budget_s=1.0, seed=seed)
+    return c, sl, order
+
+
+def test_planner_output_is_valid_and_cost_matches_oracle():
+    c, sl, order = _plan(5, 20, 0, 6)
+    free = [v for v, _, _, out in c.vars() if not out]
+    assert len(sl) == 6 and len(set(sl)) == 6 and set(sl) <= set(free)
+    assert sorted(order) == sorted(set(free) - set(sl))
+    cost, width = q.qgm_order_cost(c.h, sl, order)
+    # same cost from the oracle's graph operations on the oracle's graph
+    text = generate_circuit(5, 20, 0)
+    net = build_network(text)
+    outs = [v.id for v in net.variables if v.is_output]
+    edges = {e for e in net.graph_edges(exclude=outs + sl)}
+    rest = [v for v in net.free_vars if v not in sl]
+    ocost, owidth = oracle_order_cost(rest, edges, order)
+    assert (cost, width) == (ocost, owidth)
+    # slicing lowers the cost of the unsliced min-fill ordering
+    sl0, order0 = c.plan_slices(k_req=0, time_budget_s=0.0)
+    cost0, width0 = q.qgm_order_cost(c.h, sl0, order0)
+    assert cost < cost0 and width <= width0
+
+
+def test_planner_target_rank():
+    c = q.Circuit(generate_circuit(6, 25, 0))
+    sl, order = c.plan_slices(k_req=-1, target_rank=8, time_budget_s=0.5)
+    _, width = q.qgm_order_cost(c.h, sl, order)
+    assert width <= 8
+
+
+def test_plan_validation_errors():
+    c, sl, order = _plan(4, 10, 0, 2)
+    free = [v for v, _, _, out in c.vars() if not out]
+    outv = [v for v, _, _, out in c.vars() if out]
+    cases = [
+        (sl, order[:-1], -3),                       # order misses a variable
+        (sl, order + [order[0]], -3),               # repeated
+        (sl, order + [sl[0]], -3),                  # sliced variable in order
+        (sl, order + [outv[0]], -3),                # output variable in order
+        ([sl[0], sl[0]], order, -4),                # repeated slice
+        ([outv[0]], [v for v in free], -4),          # output variable sliced
+        (list(range(41)), order, -4),                # k > 40
+    ]
+    for s_, o_, code in cases:
+        with pytest.raises(q.QgmError) as e:
+            q.qgm_plan_create(c.h, s_, o_)
+        assert e.value.status == code, (s_, o_)
+    with pytest.raises(q.QgmError) as e:
+        q.qgm_plan_create(c.h, sl, order, prec=9)
+    assert e.value.status == -7
+    with pytest.raises(q.QgmError) as e:
+        q.qgm_plan_create(c.h, sl, order, workspace_cap=64)
+    assert e.value.status == -5
+
+
+def test_plan_stats():
+    c, sl, order = _plan(5, 20, 0, 6)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64)
+    st = p.stats()
+    cost, width = q.qgm_order_cost(c.h, sl, order)
+    assert st["k"] == 6 and st["cost"] == cost
+    assert st["max_rank"] <= width + 1
+    assert st["flops_item"] > 0 and st["item_elems"] >= 1
+
+
+def test_large_rank_step_refused_by_item_program():
+    c, sl, order = _plan(7, 30, 0, 5)
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, sl, order)
+    assert e.value.status in (-7,)
