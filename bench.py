@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published vector FP32 peak
-N, DEPTH, SEED, N_BS, K = 5, 20, 0, 64, 6
+
 
 
 def cpu_baseline(text, bits, sliced, budget_s=12.0):
@@ -49,12 +49,54 @@ def cpu_baseline(text, bits, sliced, budget_s=12.0):
                       f"{dt:.1f} s), numpy einsum per eliminated variable, FP64"}
 
 
+WORKLOADS = {
+    # name: (n, depth, seed, bitstrings, k)
+    "5x5x20": (5, 20, 0, 64, 6),
+    "6x6x25": (6, 25, 0, 1024, 10),
+    "4x4x10": (4, 10, 0, 1, 0),
+}
+
+
+def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
+    """W direct warm-up runs (HIP events around each kernel give the per-kernel
+    durations), then the timed region: one replay of a HIP graph holding
+    exactly `steps` captured runs, bracketed by synchronisation on both sides
+    and by HIP events on the launch stream."""
+    ws = plan.workspace(d_bits.shape[0], n_s)
+    q.qgm_plan_timing(plan.h, reset=True)
+    for _ in range(warmup):
+        q.qgm_amplitudes_device(plan.h, d_bits, None, 0, n_s, ws, d_part, stream)
+    torch.cuda.synchronize()
+    (ms_pro, ms_chain, ms_red), n_runs = q.qgm_plan_timing(plan.h, reset=True)
+    g = q.qgm_graph_create(plan.h, d_bits, None, 0, n_s, ws, d_part, repeat=steps)
+    q.qgm_graph_launch(g, stream)  # first replay outside the timed region
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    q.qgm_graph_launch(g, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    q.qgm_graph_free(g)
+    part = d_part.cpu().numpy()
+    amps = part[:, 0] + part[:, 2] + 1j * (part[:, 1] + part[:, 3])
+    return dict(wall=wall, gpu_ms_step=gpu_ms / steps, ms_chain=ms_chain, ms_pro=ms_pro, ms_red=ms_red, amps=amps,
+                n_runs=n_runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="5x5x20", choices=sorted(WORKLOADS))
+    ap.add_argument("--engine", default="auto", choices=["auto", "interpreter", "generated"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the c128 and interpreter comparison runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the slice axis would shard across GPUs "
@@ -67,41 +109,36 @@ def main():
     import paper_1805_01450_amd as q
     from workload import generate_circuit, random_bitstrings
 
+    n, depth, seed, n_bs, k = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    text = generate_circuit(N, DEPTH, SEED)
-    bits = random_bitstrings(N * N, N_BS, SEED + 1000)
+    text = generate_circuit(n, depth, seed)
+    bits = random_bitstrings(n * n, n_bs, seed + 1000)
     circ = q.Circuit(text)
-    sliced, order = circ.plan_slices(k_req=K, time_budget_s=1.0, seed=SEED)
-    n_items = N_BS << K
+    sliced, order = circ.plan_slices(k_req=k, time_budget_s=1.0, seed=seed)
+    n_s = 1 << k
+    n_items = n_bs * n_s
     d_bits = torch.from_numpy(bits).cuda()
-    d_part = torch.empty((N_BS, 4), dtype=torch.float64, device="cuda")
+    d_part = torch.empty((n_bs, 4), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    eng = {"auto": q.QGM_ENGINE_AUTO, "interpreter": q.QGM_ENGINE_INTERPRETER,
+           "generated": q.QGM_ENGINE_GENERATED}[args.engine]
+    runs = [("c64", q.QGM_C64, eng)]
+    if not args.no_extra:
+        runs += [("c128", q.QGM_C128, q.QGM_ENGINE_AUTO), ("c64_interp", q.QGM_C64, q.QGM_ENGINE_INTERPRETER)]
     results = {}
-    for name, prec, engine in (("c64", q.QGM_C64, q.QGM_ENGINE_AUTO), ("c128", q.QGM_C128, q.QGM_ENGINE_AUTO),
-                               ("c64_interp", q.QGM_C64, q.QGM_ENGINE_INTERPRETER)):
+    for name, prec, engine in runs:
         plan = q.Plan(circ, sliced, order, prec=prec, profile=True, engine=engine)
-        ws = plan.workspace(N_BS)
-        for _ in range(args.warmup):
-            q.qgm_amplitudes_device(plan.h, d_bits, None, 0, 1 << K, ws, d_part, stream)
-        torch.cuda.synchronize()
-        q.qgm_plan_timing(plan.h, reset=True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            q.qgm_amplitudes_device(plan.h, d_bits, None, 0, 1 << K, ws, d_part, stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        (ms_pro, ms_chain, ms_red), n_runs = q.qgm_plan_timing(plan.h, reset=True)
-        part = d_part.cpu().numpy()
-        amps = part[:, 0] + part[:, 2] + 1j * (part[:, 1] + part[:, 3])
-        results[name] = dict(plan=plan, wall=wall, ms_chain=ms_chain, ms_pro=ms_pro, ms_red=ms_red, amps=amps,
-                             n_runs=n_runs)
+        r = timed(q, torch, plan, d_bits, d_part, n_s, args.steps, args.warmup, stream)
+        r["plan"] = plan
+        results[name] = r
 
     import oracle
-    ref = np.array([oracle.ve_amplitude(text, x) for x in bits])
-    nerr = lambda a: float(np.max(np.abs(a - ref) / np.maximum(np.abs(ref), 2.0 ** (-N * N / 2))))
+    check = list(range(0, n_bs, max(1, n_bs // 16)))
+    ref = np.array([oracle.ve_amplitude(text, bits[i]) for i in check])
+    nerr = lambda a: float(np.max(np.abs(a[check] - ref) / np.maximum(np.abs(ref), 2.0 ** (-n * n / 2))))
 
-    st = results["c64"]["plan"].stats()
     r = results["c64"]
+    st = r["plan"].stats()
     ms_step = 1e3 * r["wall"] / args.steps
     value = n_items / (r["wall"] / args.steps)
     flops_launch = st["flops_item"] * n_items
@@ -119,23 +156,29 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 (fp32 complex arithmetic, fp64 slice reduction)",
         "data": "synthetic",
-        "config": {"workload": f"{N}x{N} grid depth {DEPTH} Rules 1-3 circuit seed {SEED}, {N_BS} random "
-                               f"bitstrings, k={K} planner-sliced variables: {n_items} slice contractions per step",
+        "config": {"workload": f"{n}x{n} grid depth {depth} Rules 1-3 circuit seed {seed}, {n_bs} random "
+                               f"bitstrings, k={k} planner-sliced variables: {n_items} slice contractions per step",
                    "sliced_vars": sliced, "max_rank": st["max_rank"], "item_elems": st["item_elems"],
                    "flops_per_slice": st["flops_item"], "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
                      "kernel": "qgm_chain (generated)" if st["engine"] == 2 else "chain_kernel<float>",
-                     "kernel_ms": r["ms_chain"]},
-        "amplitude_error_c64": nerr(r["amps"]),
-        "amplitude_error_c128": nerr(results["c128"]["amps"]),
-        "c128_value": n_items / (results["c128"]["wall"] / args.steps),
+                     "kernel_ms": r["ms_chain"], "flops_per_launch": flops_launch},
         "engine": {1: "interpreter", 2: "generated"}[st["engine"]],
-        "interpreter_c64_value": n_items / (results["c64_interp"]["wall"] / args.steps),
-        "interpreter_c64_error": nerr(results["c64_interp"]["amps"]),
+        "timing": "timed region = one HIP graph replay of `steps` captured runs (events on the launch stream); "
+                  "kernel_ms = HIP events around each kernel over the warm-up runs",
+        "gpu_ms_per_step": r["gpu_ms_step"],
+        "amplitude_error_c64": nerr(r["amps"]),
         "mfma_frac": 0.0,
         "kernel_ms": {"prologue": r["ms_pro"], "chain": r["ms_chain"], "reduce": r["ms_red"]},
     }
+    if "c128" in results:
+        line["c128_value"] = n_items / (results["c128"]["wall"] / args.steps)
+        line["amplitude_error_c128"] = nerr(results["c128"]["amps"])
+        line["c128_engine"] = {1: "interpreter", 2: "generated"}[results["c128"]["plan"].stats()["engine"]]
+    if "c64_interp" in results:
+        line["interpreter_c64_value"] = n_items / (results["c64_interp"]["wall"] / args.steps)
+        line["interpreter_c64_error"] = nerr(results["c64_interp"]["amps"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(text, bits, sliced)
     print(json.dumps(line), flush=True)

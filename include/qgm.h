@@ -68,7 +68,8 @@ typedef struct {
   size_t workspace_cap;  /* 0 = no cap; else plan_create fails with QGM_E_WORKSPACE when the
                             per-item memory of the plan cannot fit in it */
   int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
-  int32_t reserved[7];
+  int32_t gradient;      /* 1 = also compile the reverse-mode steps for d alpha / d theta */
+  int32_t reserved[6];
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
@@ -175,6 +176,20 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bitstrings, int32_t 
 qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
                                  uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
                                  void* hip_stream, double* d_partial);
+/* HIP graph of `repeat` back-to-back runs of qgm_amplitudes_device with
+ * these arguments (every array a device pointer, read at each replay).  The
+ * runs are captured from a private stream; each replay executes them again
+ * on the launch stream, so repeated amplitude batches cost one host call.
+ * Captured runs record no profiling events (time a replay with events around
+ * qgm_graph_launch on the launch stream).  Errors: as qgm_amplitudes_device, QGM_E_ARG (repeat < 1),
+ * QGM_E_HIP (capture or instantiation failed). */
+typedef struct qgm_graph qgm_graph;
+qgm_status qgm_graph_create(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
+                            uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
+                            double* d_partial, int32_t repeat, qgm_graph** out);
+qgm_status qgm_graph_launch(qgm_graph* g, void* hip_stream);
+void qgm_graph_free(qgm_graph* g);
+
 /* Kernel durations of the runs made since the last reset by a plan created
  * with opts.profile = 1: ms[0] prologue (tables, constant steps), ms[1]
  * per-item contraction chain, ms[2] slice reduction, each averaged over the
@@ -182,6 +197,27 @@ qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bitstrings, int32
  * Waits for the last recorded run.  reset = 1 forgets the runs afterwards.
  * Errors: QGM_E_ARG (plan not profiling), QGM_E_HIP. */
 qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_runs);
+/* Amplitudes and their derivatives with respect to every RZ angle, for a
+ * plan created with opts.gradient = 1.  Reverse mode over the elimination
+ * steps: the adjoint of alpha_{x,s} is 1; a step out = sum_S prod_i op_i
+ * gives each operand the adjoint sum over the variables it lacks of
+ * adj(out) * prod_{j != i} op_j (no conjugation: alpha is holomorphic in
+ * the gate entries); an RZ(theta) table f(u) = e^{i theta (2u-1)/2} then
+ * contributes sum_u adj(u) * (i/2)(2u-1) f(u) to d alpha / d theta.  Forward
+ * tensors stay in item memory until their reverse step (no recomputation).
+ * Slice sums of gradients use the amplitudes' FP64 compensated order.
+ * d_grad_partial[4 * (b * n_params + j)] = (sum re, sum im, comp re, comp
+ * im) of d alpha_b / d theta_j.  Device pointers, no synchronisation.
+ * Errors: as qgm_amplitudes_device; QGM_E_ARG when the plan has no gradient
+ * program or d_grad_partial is NULL. */
+qgm_status qgm_gradients_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
+                                uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
+                                void* hip_stream, double* d_partial, double* d_grad_partial);
+/* Host form for one bitstring over all slices: amp_out[2] = alpha,
+ * dalpha_dtheta[2 * n_params] = (re, im) of d alpha / d theta_j.  Synchronises
+ * `stream`.  Errors: as qgm_gradients_device, QGM_E_WORKSPACE. */
+qgm_status qgm_amplitude_grad(qgm_plan* p, const uint8_t* bitstring, const double* params, void* d_workspace,
+                              size_t ws_bytes, void* hip_stream, double* amp_out, double* dalpha_dtheta);
 void qgm_plan_free(qgm_plan* p);
 const char* qgm_last_error(void);
 

@@ -73,11 +73,12 @@ def qgm_order_cost(c, sliced, order):
 
 
 def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
-                    engine: int = QGM_ENGINE_AUTO):
+                    engine: int = QGM_ENGINE_AUTO, gradient: bool = False):
     opts = PlanOpts()
     opts.prec = prec
     opts.profile = 1 if profile else 0
     opts.engine = engine
+    opts.gradient = 1 if gradient else 0
     opts.workspace_cap = workspace_cap
     h = C.c_void_p()
     check(lib.qgm_plan_create(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(opts), C.byref(h)))
@@ -141,6 +142,43 @@ def qgm_amplitudes_device(p, d_bits, d_params, s_begin: int, s_end: int, workspa
                                     _ptr(workspace), workspace.numel(), _stream(stream), _ptr(d_partial)))
 
 
+def qgm_gradients_device(p, d_bits, d_params, s_begin: int, s_end: int, workspace, d_partial, d_grad_partial,
+                         stream=None) -> None:
+    """All-device amplitudes and d alpha / d theta: d_grad_partial float64 (n_bs, n_params, 4)."""
+    check(lib.qgm_gradients_device(p, _ptr(d_bits), d_bits.shape[0], _ptr(d_params), s_begin, s_end,
+                                   _ptr(workspace), workspace.numel(), _stream(stream), _ptr(d_partial),
+                                   _ptr(d_grad_partial)))
+
+
+def qgm_amplitude_grad(p, bitstring, params, workspace, n_params: int, stream=None):
+    """(alpha, d alpha / d theta as a complex128 array) for one bitstring."""
+    x = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8))
+    par = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    amp = np.empty(2, dtype=np.float64)
+    grad = np.empty(max(1, 2 * n_params), dtype=np.float64)
+    check(lib.qgm_amplitude_grad(p, x.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 par.ctypes.data_as(C.POINTER(C.c_double)), _ptr(workspace), workspace.numel(),
+                                 _stream(stream), amp.ctypes.data_as(C.POINTER(C.c_double)),
+                                 grad.ctypes.data_as(C.POINTER(C.c_double))))
+    return complex(amp[0], amp[1]), grad[0:2 * n_params:2] + 1j * grad[1:2 * n_params:2]
+
+
+def qgm_graph_create(p, d_bits, d_params, s_begin: int, s_end: int, workspace, d_partial, repeat: int = 1):
+    """HIP graph of `repeat` runs of qgm_amplitudes_device with these device tensors."""
+    g = C.c_void_p()
+    check(lib.qgm_graph_create(p, _ptr(d_bits), d_bits.shape[0], _ptr(d_params), s_begin, s_end, _ptr(workspace),
+                               workspace.numel(), _ptr(d_partial), repeat, C.byref(g)))
+    return g
+
+
+def qgm_graph_launch(g, stream=None) -> None:
+    check(lib.qgm_graph_launch(g, _stream(stream)))
+
+
+def qgm_graph_free(g) -> None:
+    lib.qgm_graph_free(g)
+
+
 def qgm_plan_timing(p, reset: bool = True):
     """(prologue ms, chain ms, reduction ms) averaged over the profiled runs, and the run count."""
     ms = (C.c_double * 3)()
@@ -199,12 +237,14 @@ class Plan:
     """Owning wrapper of a qgm_plan handle plus a cached device workspace."""
 
     def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
-                 profile: bool = False, engine: int = QGM_ENGINE_AUTO):
+                 profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False):
         self.circuit = circuit
         self.sliced = list(sliced)
         self.order = list(order)
         self.prec = prec
-        self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine)
+        self.gradient = gradient
+        self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine,
+                                 gradient)
         self._ws = None
 
     @property
@@ -231,6 +271,10 @@ class Plan:
         ws = self.workspace(bs.shape[0], s_end - s_begin)
         return qgm_amplitudes_range(self.h, bs, params, s_begin, s_end, ws, stream)
 
+    def amplitude_grad(self, bitstring, params, stream=None):
+        """(alpha, d alpha / d theta) for one bitstring; needs gradient=True."""
+        return qgm_amplitude_grad(self.h, bitstring, params, self.workspace(1), self.circuit.n_params, stream)
+
     def __del__(self):
         h, self.h = getattr(self, "h", None), None
         if h and lib is not None:
@@ -238,3 +282,37 @@ class Plan:
                 lib.qgm_plan_free(h)
             except Exception:  # interpreter shutdown
                 pass
+
+
+def _amplitude_fn():
+    import torch
+
+    class AmplitudeFn(torch.autograd.Function):
+        """alpha_x(theta) as a differentiable function of the RZ angles.
+
+        forward(theta, plan, bitstring) -> complex128 scalar tensor.  The
+        backward returns Re(conj(grad_out) * d alpha / d theta), PyTorch's
+        convention for a real input and a complex output; d alpha / d theta
+        comes from the library's reverse-mode pass run together with alpha.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, plan, bitstring):
+            th = theta.detach().to("cpu", torch.float64).numpy()
+            amp, grad = plan.amplitude_grad(bitstring, th)
+            ctx.save_for_backward(torch.from_numpy(grad).to(theta.device))
+            return torch.tensor(amp, dtype=torch.complex128, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (grad,) = ctx.saved_tensors
+            g = (grad_out.conj() * grad).real.to(torch.float64)
+            return g, None, None
+
+    return AmplitudeFn
+
+
+def __getattr__(name):
+    if name == "AmplitudeFn":
+        return _amplitude_fn()
+    raise AttributeError(name)

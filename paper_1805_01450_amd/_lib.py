@@ -24,7 +24,7 @@ class VarInfo(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("profile", C.c_int32), ("workspace_cap", C.c_size_t),
-                ("engine", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("engine", C.c_int32), ("gradient", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class Stats(C.Structure):
@@ -63,6 +63,11 @@ def _load():
         "qgm_amplitudes_range": (i32, [P, pu8, i32, pd, u64, u64, P, sz, P, pd]),
         "qgm_amplitudes_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P]),
         "qgm_plan_timing": (i32, [P, i32, pd, pi32]),
+        "qgm_gradients_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P, P]),
+        "qgm_amplitude_grad": (i32, [P, pu8, pd, P, sz, P, pd, pd]),
+        "qgm_graph_create": (i32, [P, P, i32, P, u64, u64, P, sz, P, i32, C.POINTER(P)]),
+        "qgm_graph_launch": (i32, [P, P]),
+        "qgm_graph_free": (None, [P]),
         "qgm_plan_free": (None, [P]),
         "qgm_last_error": (C.c_char_p, []),
         "qgm_amplitude": (i32, [C.c_char_p, sz, pu8, pi32, i32, pi32, i32, pd, pd]),
@@ -77,7 +82,8 @@ def _load():
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
             "qgm_plan_slices", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
-            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_plan_timing", "qgm_plan_free",
+            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
+            "qgm_plan_timing", "qgm_plan_free",
             "qgm_last_error", "qgm_amplitude")
 
 

@@ -24,6 +24,11 @@ struct qgm_circuit {
   Network net;
 };
 
+struct qgm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct qgm_plan {
   Network net;
   std::vector<int> sliced, order;
@@ -67,10 +72,10 @@ qgm_status fail(qgm_status s, const std::string& msg) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Staging {
-  size_t bits, params, partial, total;
+  size_t bits, params, partial, gpartial, total;
 };
 
-Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params) {
+Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool grads) {
   Staging st;
   size_t off = ws.total;
   st.bits = off;
@@ -79,6 +84,8 @@ Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params) {
   off = align256(off + (size_t)std::max(1, n_params) * sizeof(double));
   st.partial = off;
   off = align256(off + (size_t)std::max(1, n_bs) * 4 * sizeof(double));
+  st.gpartial = off;
+  if (grads) off = align256(off + (size_t)std::max(1, n_bs) * std::max(1, n_params) * 4 * sizeof(double));
   st.total = off;
   return st;
 }
@@ -247,9 +254,13 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   p->opts = o;
   std::string err;
   int code = 0;
-  if (!compile_program(p->net, sv, ov, p->prog, err, code)) {
+  if (!compile_program(p->net, sv, ov, p->prog, err, code, o.gradient != 0)) {
     delete p;
     return fail((qgm_status)code, err);
+  }
+  if (!p->prog.has_optab) {
+    delete p;
+    return fail(QGM_E_UNSUPPORTED, "plan has a step of rank + summed variables > 16, beyond the per-item engines");
   }
   if (o.workspace_cap) {
     const size_t el = o.prec == QGM_C128 ? 16 : 8;
@@ -268,7 +279,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   p->cost = order_cost(g, og, removed).cost;
   // Engine: the generated kernel keeps item tensors in registers, so it is
   // chosen automatically only when the live item memory is small.
-  const int reg_limit = o.prec == QGM_C128 ? 48 : 112;
+  const int reg_limit = o.prec == QGM_C128 ? 320 : 512;
   bool want_gen = o.engine == QGM_ENGINE_GENERATED ||
                   (o.engine == QGM_ENGINE_AUTO && p->prog.item_elems <= reg_limit);
   p->engine = QGM_ENGINE_INTERPRETER;
@@ -332,20 +343,23 @@ qgm_status qgm_workspace_size(const qgm_plan* pc, int32_t n_bs, uint64_t n_slice
   WsLayout ws;
   LaunchCfg cfg;
   if ((s = layout_for(p, n_bs, n_slices, ws, cfg))) return s;
-  *bytes = staging(ws, n_bs, p->net.n_qubits, p->net.n_params).total;
+  *bytes = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0).total;
   return QGM_OK;
   GUARD_END
 }
 
-qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
-                                 uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream,
-                                 double* d_partial) {
-  GUARD_BEGIN
+}  // extern "C"
+
+namespace {
+
+// Queue one run on `stream`; the caller holds p->mu.
+qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params, uint64_t s_begin,
+                       uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream, double* d_partial,
+                       bool capturing = false, double* d_grad_partial = nullptr) {
   if (!p || n_bs < 0 || (n_bs > 0 && (!d_bits || !d_partial)) || !d_ws) return fail(QGM_E_ARG, "bad argument");
   if (p->net.n_params > 0 && !d_params) return fail(QGM_E_ARG, "circuit has RZ gates but params is NULL");
   qgm_status s = check_range(p, s_begin, s_end);
   if (s) return s;
-  std::lock_guard<std::mutex> lk(p->mu);
   if ((s = ensure_device(p))) return s;
   WsLayout ws;
   LaunchCfg cfg;
@@ -356,18 +370,86 @@ qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bits, int32_t n_b
   if (n_bs == 0) return QGM_OK;
   std::string err;
   void* ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  if (p->opts.profile) {
+  const bool profile = p->opts.profile && !capturing;
+  if (profile) {
     std::array<hipEvent_t, 4> r{};
     for (auto& e : r)
       if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
     p->runs.push_back(r);
     for (int i = 0; i < 4; ++i) ev[i] = r[i];
   }
-  int rc = dev_run(p->prog, p->dev, cfg, ws, d_bits, d_params, d_ws, stream, d_partial,
-                   p->opts.profile ? ev : nullptr, err);
+  int rc = dev_run(p->prog, p->dev, cfg, ws, d_bits, d_params, d_ws, stream, d_partial, d_grad_partial,
+                   profile ? ev : nullptr, err);
   if (rc) return fail((qgm_status)rc, err);
   return QGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                                 uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream,
+                                 double* d_partial) {
+  GUARD_BEGIN
+  if (!p) return fail(QGM_E_ARG, "null plan");
+  std::lock_guard<std::mutex> lk(p->mu);
+  return enqueue_run(p, d_bits, n_bs, d_params, s_begin, s_end, d_ws, ws_bytes, stream, d_partial);
   GUARD_END
+}
+
+qgm_status qgm_graph_create(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                            uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, double* d_partial,
+                            int32_t repeat, qgm_graph** out) {
+  GUARD_BEGIN
+  if (!p || !out || repeat < 1) return fail(QGM_E_ARG, "bad argument");
+  *out = nullptr;
+  std::lock_guard<std::mutex> lk(p->mu);
+  qgm_status s = ensure_device(p);
+  if (s) return s;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return fail(QGM_E_HIP, "hipStreamCreateWithFlags failed");
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(QGM_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  for (int r = 0; r < repeat && !s; ++r)
+    s = enqueue_run(p, d_bits, n_bs, d_params, s_begin, s_end, d_ws, ws_bytes, cs, d_partial, true);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (s) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(QGM_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  auto* g = new qgm_graph();
+  g->graph = graph;
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(QGM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_graph_launch(qgm_graph* g, void* stream) {
+  if (!g) return fail(QGM_E_ARG, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(QGM_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  return QGM_OK;
+}
+
+void qgm_graph_free(qgm_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bits, int32_t n_bs, const double* params,
@@ -389,7 +471,7 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bits, int32_t n_bs, 
     if ((s = ensure_device(p))) return s;
     if ((s = layout_for(p, n_bs, s_end - s_begin, ws, cfg))) return s;
   }
-  Staging st = staging(ws, n_bs, nq, p->net.n_params);
+  Staging st = staging(ws, n_bs, nq, p->net.n_params, p->prog.n_grad_slots > 0);
   if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace holds " + std::to_string(ws_bytes) +
                                                              " bytes, run needs " + std::to_string(st.total));
   char* base = (char*)d_ws;
@@ -450,6 +532,70 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
     for (auto& r : p->runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->runs.clear();
+  }
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_gradients_device(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                                uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream,
+                                double* d_partial, double* d_grad_partial) {
+  GUARD_BEGIN
+  if (!p) return fail(QGM_E_ARG, "null plan");
+  if (p->prog.n_grad_slots == 0 && p->net.n_params > 0 && !p->opts.gradient)
+    return fail(QGM_E_ARG, "plan was not created with opts.gradient = 1");
+  if (n_bs > 0 && p->net.n_params > 0 && !d_grad_partial) return fail(QGM_E_ARG, "null gradient output");
+  std::lock_guard<std::mutex> lk(p->mu);
+  return enqueue_run(p, d_bits, n_bs, d_params, s_begin, s_end, d_ws, ws_bytes, stream, d_partial, false,
+                     d_grad_partial);
+  GUARD_END
+}
+
+qgm_status qgm_amplitude_grad(qgm_plan* p, const uint8_t* bitstring, const double* params, void* d_ws,
+                              size_t ws_bytes, void* stream_, double* amp_out, double* dalpha) {
+  GUARD_BEGIN
+  if (!p || !bitstring || !amp_out || !d_ws) return fail(QGM_E_ARG, "bad argument");
+  const int nq = p->net.n_qubits, np = p->net.n_params;
+  if (np > 0 && (!params || !dalpha)) return fail(QGM_E_ARG, "params and dalpha_dtheta are required");
+  if (!p->opts.gradient) return fail(QGM_E_ARG, "plan was not created with opts.gradient = 1");
+  for (int q = 0; q < nq; ++q)
+    if (bitstring[q] > 1) return fail(QGM_E_ARG, "bitstring entries must be 0 or 1");
+  hipStream_t stream = (hipStream_t)stream_;
+  WsLayout ws;
+  LaunchCfg cfg;
+  const uint64_t ns = 1ull << p->sliced.size();
+  qgm_status s;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if ((s = ensure_device(p))) return s;
+    if ((s = layout_for(p, 1, ns, ws, cfg))) return s;
+  }
+  Staging st = staging(ws, 1, nq, np, true);
+  if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace holds " + std::to_string(ws_bytes) +
+                                                             " bytes, run needs " + std::to_string(st.total));
+  char* base = (char*)d_ws;
+  if (hipMemcpyAsync(base + st.bits, bitstring, (size_t)nq, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return fail(QGM_E_HIP, "bitstring upload failed");
+  if (np > 0 && hipMemcpyAsync(base + st.params, params, (size_t)np * sizeof(double), hipMemcpyHostToDevice,
+                               stream) != hipSuccess)
+    return fail(QGM_E_HIP, "parameter upload failed");
+  s = qgm_gradients_device(p, (const uint8_t*)(base + st.bits), 1, np > 0 ? (const double*)(base + st.params) : nullptr,
+                           0, ns, d_ws, ws.total, stream, (double*)(base + st.partial),
+                           (double*)(base + st.gpartial));
+  if (s) return s;
+  std::vector<double> part(4), gpart((size_t)std::max(1, np) * 4);
+  if (hipMemcpyAsync(part.data(), base + st.partial, 4 * sizeof(double), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      (np > 0 && hipMemcpyAsync(gpart.data(), base + st.gpartial, (size_t)np * 4 * sizeof(double),
+                                hipMemcpyDeviceToHost, stream) != hipSuccess))
+    return fail(QGM_E_HIP, "result download failed");
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(QGM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  amp_out[0] = part[0] + part[2];
+  amp_out[1] = part[1] + part[3];
+  for (int j = 0; j < np; ++j) {
+    dalpha[2 * j] = gpart[4 * j] + gpart[4 * j + 2];
+    dalpha[2 * j + 1] = gpart[4 * j + 1] + gpart[4 * j + 3];
   }
   return QGM_OK;
   GUARD_END

@@ -80,7 +80,8 @@ class Gen {
   void ensure_param(int k) {
     if (done_const[k]) return;
     done_const[k] = 1;
-    o << "  const C2 p" << k << " = ptab[" << 2 * prog.raw_param[k] + prog.raw_bit[k] << "];\n";
+    o << "  const C2 p" << k << " = ptab[" << 4 * prog.raw_param[k] + 2 * prog.raw_deriv[k] + prog.raw_bit[k]
+      << "];\n";
   }
 
   // Emit constant steps in order until element k exists.
@@ -131,7 +132,7 @@ std::string generate_chain_source(const Program& prog, int prec) {
        << "extern \"C\" __global__ void __launch_bounds__(64) qgm_chain(const double* __restrict__ rawd, "
           "const double* __restrict__ params, const unsigned char* __restrict__ bits, int n_qubits, "
           "unsigned long long n_bs, unsigned long long s_begin, unsigned long long n_s, unsigned long long n_items, "
-          "C2* __restrict__ res, double* __restrict__ part, int fused) {\n"
+          "C2* __restrict__ res, C2* __restrict__ gres, double* __restrict__ part, int fused) {\n"
        << "  (void)rawd; (void)params;\n"
        << "  const int lane = threadIdx.x;\n"
        << "  unsigned long long item = (unsigned long long)blockIdx.x * 64ull + lane;\n"
@@ -146,14 +147,17 @@ std::string generate_chain_source(const Program& prog, int prec) {
   int n_params = 0;
   for (int k = 0; k < prog.n_raw; ++k) n_params = std::max(n_params, prog.raw_param[k] + 1);
   if (n_params > 0) {
-    // RZ(theta_j) entries for u = 0, 1: e^{-i theta_j / 2}, e^{+i theta_j / 2};
-    // the lanes of the block share the work, one angle per lane.
-    head << "  __shared__ C2 ptab[" << 2 * n_params << "];\n"
+    // Per angle theta_j, u = 0, 1: RZ entries e^{-+i h} (h = theta_j / 2)
+    // and their theta-derivatives (i/2)(2u - 1) e^{i (2u - 1) h}; the lanes
+    // of the block share the work, one angle per lane.
+    head << "  __shared__ C2 ptab[" << 4 * n_params << "];\n"
          << "  for (int j = lane; j < " << n_params << "; j += 64) {\n"
          << "    double sn, cs;\n"
          << "    sincos(0.5 * params[j], &sn, &cs);\n"
-         << "    ptab[2 * j] = C2{(R)cs, (R)(-sn)};\n"
-         << "    ptab[2 * j + 1] = C2{(R)cs, (R)sn};\n"
+         << "    ptab[4 * j] = C2{(R)cs, (R)(-sn)};\n"
+         << "    ptab[4 * j + 1] = C2{(R)cs, (R)sn};\n"
+         << "    ptab[4 * j + 2] = C2{(R)(-0.5 * sn), (R)(-0.5 * cs)};\n"
+         << "    ptab[4 * j + 3] = C2{(R)(-0.5 * sn), (R)(0.5 * cs)};\n"
          << "  }\n"
          << "  __syncthreads();\n";
   }
@@ -197,10 +201,14 @@ std::string generate_chain_source(const Program& prog, int prec) {
         p += st.m;
         terms.push_back(cur);
       }
-      std::string dst = st.kind == ST_FINAL ? std::string("amp") : "m" + std::to_string(st.out + c);
       o << "  { C2 a = " << terms[0] << ";";
       for (size_t t = 1; t < terms.size(); ++t) o << " a = cad(a, " << terms[t] << ");";
-      o << " " << dst << " = a; }\n";
+      if (st.kind == ST_FINAL)
+        o << " amp = a; }\n";
+      else if (st.kind == ST_GRAD)
+        o << " if (valid) gres[(" << st.grad_slot << "ull * n_s + sl) * n_bs + b] = a; }\n";
+      else
+        o << " m" << (st.out + c) << " = a; }\n";
     }
   }
   o << "  if (!fused) {\n"

@@ -15,6 +15,8 @@ struct DevProgram {
   void* raw = nullptr;     // double2 per raw entry
   void* rawp = nullptr;    // int per raw entry (RZ parameter index or -1)
   void* rawb = nullptr;    // int per raw entry (RZ variable value)
+  void* rawd = nullptr;    // int per raw entry (1 = RZ derivative table)
+  void* slot_param = nullptr;  // int per gradient slot: parameter index
   void* steps = nullptr;
   void* leaves = nullptr;
   void* optab = nullptr;
@@ -37,7 +39,7 @@ struct LaunchCfg {
 };
 
 struct WsLayout {
-  size_t cst, bits, res, counter, chunks, scratch, total;
+  size_t cst, bits, res, gres, counter, chunks, scratch, total;
   int fused;            // generated kernel sums each block's 64 slices itself
   int use_lds;
   int grid;             // persistent workgroups (one wave each)
@@ -52,12 +54,14 @@ void dev_free(DevProgram& dp);
 int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, WsLayout& ws, std::string& err);
 // Runs prologue, persistent chain and slice reduction on `stream`.  Device
 // inputs: bits (n_bs x n_qubits bytes), params (n_params doubles or null).
-// Device output: partial (n_bs x 4 doubles: sum re, sum im, comp re, comp im).
+// Device output: partial (n_bs x 4 doubles: sum re, sum im, comp re, comp im)
+// and, for gradient programs when d_grad_partial is not null, grad_partial
+// (n_bs x n_params x 4 doubles, same layout per parameter).
 // events: null, or 4 HIP events recorded before the prologue, before the
 // chain, after the chain and after the reduction.
 int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
             const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream, double* d_partial,
-            void* const* events, std::string& err);
+            double* d_grad_partial, void* const* events, std::string& err);
 int dev_query(int& n_cu, size_t& max_lds, std::string& err);
 
 }  // namespace qgm

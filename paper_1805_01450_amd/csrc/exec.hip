@@ -22,7 +22,7 @@ namespace qgm {
 namespace {
 
 struct DevStep {
-  int kind, out, r, ns, m, ops, leaf, pad;
+  int kind, out, r, ns, m, ops, leaf, grad_slot;
 };
 
 struct DevLeaf {
@@ -63,7 +63,8 @@ constexpr int kLanes = 64;
 // order.
 template <typename R>
 __global__ void __launch_bounds__(256) prologue_kernel(const double* __restrict__ raw, const int* __restrict__ rawp,
-                                                       const int* __restrict__ rawb, int n_raw,
+                                                       const int* __restrict__ rawb, const int* __restrict__ rawd,
+                                                       int n_raw,
                                                        const double* __restrict__ params,
                                                        const DevStep* __restrict__ steps, int n_const_steps,
                                                        const uint32_t* __restrict__ optab, cx<R>* __restrict__ cst,
@@ -80,9 +81,19 @@ __global__ void __launch_bounds__(256) prologue_kernel(const double* __restrict_
     cx<R> v;
     int p = rawp[e];
     if (p >= 0) {
-      double half = 0.5 * params[p] * (2.0 * rawb[e] - 1.0);
-      v.x = (R)cos(half);
-      v.y = (R)sin(half);
+      // RZ(theta) entry e^{i phi}, phi = theta (2u - 1) / 2; derivative tables
+      // hold d/dtheta of it, (i/2)(2u - 1) e^{i phi}.
+      const double sgn = 2.0 * rawb[e] - 1.0;
+      const double phi = 0.5 * params[p] * sgn;
+      double sn, cs;
+      sincos(phi, &sn, &cs);
+      if (rawd[e]) {
+        v.x = (R)(-0.5 * sgn * sn);
+        v.y = (R)(0.5 * sgn * cs);
+      } else {
+        v.x = (R)cs;
+        v.y = (R)sn;
+      }
     } else {
       v.x = (R)raw[2 * e];
       v.y = (R)raw[2 * e + 1];
@@ -118,7 +129,8 @@ __global__ void __launch_bounds__(64) chain_kernel(const DevStep* __restrict__ s
                                                    const uint64_t* __restrict__ packed, int n_bs,
                                                    uint64_t s_begin, uint64_t n_s, uint64_t n_items,
                                                    unsigned* __restrict__ counter, cx<R>* __restrict__ res,
-                                                   cx<R>* __restrict__ gscratch, int item_elems) {
+                                                   cx<R>* __restrict__ gres, cx<R>* __restrict__ gscratch,
+                                                   int item_elems) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R>* mem = LDS ? reinterpret_cast<cx<R>*>(lds_raw)
                    : gscratch + (size_t)blockIdx.x * (size_t)item_elems * kLanes;
@@ -178,6 +190,8 @@ __global__ void __launch_bounds__(64) chain_kernel(const DevStep* __restrict__ s
           }
           if (st.kind == 2) {
             if (valid) res[sl * (uint64_t)n_bs + b] = acc;
+          } else if (st.kind == 3) {
+            if (valid) gres[((uint64_t)st.grad_slot * n_s + sl) * (uint64_t)n_bs + b] = acc;
           } else {
             mem[(size_t)(st.out + c) * kLanes + lane] = acc;
           }
@@ -246,6 +260,39 @@ __global__ void combine_kernel(const double* __restrict__ chunks, int n_bs, uint
   partial[4 * b + 3] = SC[1] + CC[1];
 }
 
+// d alpha / d theta_j per bitstring: the values of every gradient slot of
+// parameter j (slots ascending) are summed over the slices in the same
+// two-level compensated order as the amplitudes.
+template <typename R>
+__global__ void grad_reduce_kernel(const cx<R>* __restrict__ gres, int n_bs, uint64_t n_s, int n_slots,
+                                   const int* __restrict__ slot_param, int n_params, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_bs * n_params) return;
+  const int b = t / n_params, j = t - b * n_params;
+  double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
+  for (int g = 0; g < n_slots; ++g) {
+    if (slot_param[g] != j) continue;
+    const cx<R>* base = gres + (uint64_t)g * n_s * (uint64_t)n_bs;
+    for (uint64_t c0 = 0; c0 < n_s; c0 += 64) {
+      const uint64_t c1 = c0 + 64 < n_s ? c0 + 64 : n_s;
+      double cs[2] = {0, 0}, cc[2] = {0, 0};
+      for (uint64_t s = c0; s < c1; ++s) {
+        cx<R> v = base[s * (uint64_t)n_bs + b];
+        neumaier(cs[0], cc[0], (double)v.x);
+        neumaier(cs[1], cc[1], (double)v.y);
+      }
+      for (int k = 0; k < 2; ++k) {
+        neumaier(S[k], SC[k], cs[k]);
+        CC[k] += cc[k];
+      }
+    }
+  }
+  out[4 * (size_t)t + 0] = S[0];
+  out[4 * (size_t)t + 1] = S[1];
+  out[4 * (size_t)t + 2] = SC[0] + CC[0];
+  out[4 * (size_t)t + 3] = SC[1] + CC[1];
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -281,7 +328,7 @@ int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& d
   std::vector<DevStep> ds(prog.steps.size());
   for (size_t i = 0; i < prog.steps.size(); ++i) {
     const Step& s = prog.steps[i];
-    ds[i] = DevStep{s.kind, s.out, s.r, s.ns, s.m, s.ops, s.leaf, 0};
+    ds[i] = DevStep{s.kind, s.out, s.r, s.ns, s.m, s.ops, s.leaf, s.grad_slot};
   }
   std::vector<DevLeaf> dl(prog.leaves.size());
   for (size_t i = 0; i < prog.leaves.size(); ++i) {
@@ -297,6 +344,8 @@ int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& d
   if ((rc = up(&dp.raw, prog.raw.data(), prog.raw.size() * sizeof(double)))) return rc;
   if ((rc = up(&dp.rawp, prog.raw_param.data(), prog.raw_param.size() * sizeof(int)))) return rc;
   if ((rc = up(&dp.rawb, prog.raw_bit.data(), prog.raw_bit.size() * sizeof(int)))) return rc;
+  if ((rc = up(&dp.rawd, prog.raw_deriv.data(), prog.raw_deriv.size() * sizeof(int)))) return rc;
+  if ((rc = up(&dp.slot_param, prog.grad_param.data(), prog.grad_param.size() * sizeof(int)))) return rc;
   if ((rc = up(&dp.leaves, dl.data(), dl.size() * sizeof(DevLeaf)))) return rc;
   if ((rc = up(&dp.optab, prog.optab.data(), prog.optab.size() * sizeof(uint32_t)))) return rc;
   if ((rc = up(&dp.steps, ds.data(), ds.size() * sizeof(DevStep)))) return rc;
@@ -306,7 +355,7 @@ int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& d
 }
 
 void dev_free(DevProgram& dp) {
-  void* ps[] = {dp.raw, dp.rawp, dp.rawb, dp.steps, dp.leaves, dp.optab};
+  void* ps[] = {dp.raw, dp.rawp, dp.rawb, dp.rawd, dp.slot_param, dp.steps, dp.leaves, dp.optab};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (dp.module) (void)hipModuleUnload((hipModule_t)dp.module);
@@ -351,6 +400,8 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   off = align256(off + (size_t)std::max(cfg.n_bs, 1) * 8);
   ws.res = off;
   off = align256(off + (size_t)std::max<uint64_t>(n_items, 1) * el);
+  ws.gres = off;
+  off = align256(off + (size_t)prog.n_grad_slots * n_items * el);
   ws.counter = off;
   off = align256(off + 256);
   ws.chunks = off;
@@ -367,7 +418,7 @@ namespace {
 template <typename R>
 int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
               const uint8_t* d_bits, const double* d_params, char* base, hipStream_t stream, double* d_partial,
-              void* const* events, std::string& err) {
+              double* d_grad_partial, void* const* events, std::string& err) {
   auto mark = [&](int i) {
     if (events) (void)hipEventRecord((hipEvent_t)events[i], stream);
   };
@@ -376,20 +427,30 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
   auto* counter = (unsigned*)(base + ws.counter);
   auto* cst = (cx<R>*)(base + ws.cst);
   auto* res = (cx<R>*)(base + ws.res);
+  auto* gres = (cx<R>*)(base + ws.gres);
   auto* scr = (cx<R>*)(base + ws.scratch);
   auto* chunks = (double*)(base + ws.chunks);
   const int first = dp.n_const_steps;
   const dim3 red_grid((cfg.n_bs + 63) / 64);
+  const bool grads = prog.n_grad_slots > 0 && d_grad_partial != nullptr;
+  auto grad_reduce = [&]() {
+    if (!grads) return;
+    const int n = cfg.n_bs * cfg.n_params;
+    hipLaunchKernelGGL(grad_reduce_kernel<R>, dim3((n + 63) / 64), dim3(64), 0, stream, gres, cfg.n_bs, cfg.n_s,
+                       prog.n_grad_slots, (const int*)dp.slot_param, cfg.n_params, d_grad_partial);
+  };
   mark(0);
   // The generated kernel reads the FP64 tables and the bitstring bytes itself.
   if (!cfg.generated || n_items == 0)
     hipLaunchKernelGGL(prologue_kernel<R>, dim3(1), dim3(256), 0, stream, (const double*)dp.raw, (const int*)dp.rawp,
-                       (const int*)dp.rawb, prog.n_raw, d_params, (const DevStep*)dp.steps, dp.n_const_steps,
-                       (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs, cfg.n_qubits, packed, counter);
+                       (const int*)dp.rawb, (const int*)dp.rawd, prog.n_raw, d_params, (const DevStep*)dp.steps,
+                       dp.n_const_steps, (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs, cfg.n_qubits, packed,
+                       counter);
   mark(1);
   if (n_items == 0) {
     mark(2);
     hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    grad_reduce();
     mark(3);
     HIP_OK(hipGetLastError());
     return 0;
@@ -405,9 +466,10 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
     const void* a_bits = d_bits;
     int a_nq = cfg.n_qubits;
     void* a_res = res;
+    void* a_gres = gres;
     void* a_part = part;
     int a_fused = ws.fused;
-    void* args[] = {&a_raw, &a_par, &a_bits, &a_nq, &a_nbs, &a_sb, &a_ns, &a_ni, &a_res, &a_part, &a_fused};
+    void* args[] = {&a_raw, &a_par, &a_bits, &a_nq, &a_nbs, &a_sb, &a_ns, &a_ni, &a_res, &a_gres, &a_part, &a_fused};
     HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes, 1, 1, 0, stream,
                                  args, nullptr));
     mark(2);
@@ -415,19 +477,21 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
       hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
     else if (per_bs > 1)
       hipLaunchKernelGGL(combine_kernel, red_grid, dim3(64), 0, stream, chunks, cfg.n_bs, per_bs, d_partial);
+    grad_reduce();
     mark(3);
   } else {
     if (ws.use_lds)
       hipLaunchKernelGGL((chain_kernel<R, true>), dim3(ws.grid), dim3(64), ws.lds_bytes, stream,
                          (const DevStep*)dp.steps, first, dp.n_steps, (const DevLeaf*)dp.leaves,
                          (const uint32_t*)dp.optab, cst, packed, cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res,
-                         scr, prog.item_elems);
+                         gres, scr, prog.item_elems);
     else
       hipLaunchKernelGGL((chain_kernel<R, false>), dim3(ws.grid), dim3(64), 0, stream, (const DevStep*)dp.steps,
                          first, dp.n_steps, (const DevLeaf*)dp.leaves, (const uint32_t*)dp.optab, cst, packed,
-                         cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res, scr, prog.item_elems);
+                         cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res, gres, scr, prog.item_elems);
     mark(2);
     hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    grad_reduce();
     mark(3);
   }
   HIP_OK(hipGetLastError());
@@ -438,7 +502,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
 
 int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, const WsLayout& ws,
             const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream_, double* d_partial,
-            void* const* events, std::string& err) {
+            double* d_grad_partial, void* const* events, std::string& err) {
   if (cfg.n_bs == 0) return 0;
   if (cfg.generated && !dp.chain_fn) {
     err = "generated kernel not loaded";
@@ -446,8 +510,10 @@ int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, con
   }
   hipStream_t stream = (hipStream_t)stream_;
   if (cfg.prec == 0)
-    return run_typed<double>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, events, err);
-  return run_typed<float>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, events, err);
+    return run_typed<double>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, d_grad_partial,
+                             events, err);
+  return run_typed<float>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, d_grad_partial, events,
+                          err);
 }
 
 }  // namespace qgm

@@ -86,38 +86,62 @@ struct Leaf {
 };
 
 // Step kinds of the per-item program.
-enum StepKind { ST_LEAF = 0, ST_ELIM = 1, ST_FINAL = 2 };
+//   ST_LEAF : materialise a leaf read at the item's fixed bits
+//   ST_ELIM : out(out_vars) = sum over sum_vars of the product of the operands
+//   ST_FINAL: the item's amplitude alpha_{x,s} (rank-0 product)
+//   ST_GRAD : one RZ gate's contribution to d alpha_{x,s} / d theta (rank 0),
+//             written to gradient slot `grad_slot`
+enum StepKind { ST_LEAF = 0, ST_ELIM = 1, ST_FINAL = 2, ST_GRAD = 3 };
+
+struct Operand {
+  int is_const;           // 1: constant area (raw table or constant intermediate)
+  int storage;            // element offset (constant area or packed item memory)
+  std::vector<int> vars;  // bit j of the element index = value of vars[j]
+  int tid = -1;           // compile-time tensor id (for the memory check)
+};
 
 struct Step {
-  int kind;
-  int is_const;   // runs once per call in the prologue (all operands constant)
-  int out;        // element offset: item memory (LDS) or constant area
-  int r, ns, m;   // output rank, summed variables, operands
-  int ops;        // offset into the operand table (2^(r+ns) * m entries)
-  int leaf;       // ST_LEAF: leaf index
-  double flops;   // useful real flops per item
+  int kind = ST_ELIM;
+  int is_const = 0;   // runs once per call in the prologue (all operands constant)
+  int out = 0;        // element offset: item memory or constant area
+  int r = 0, ns = 0, m = 0;   // output rank, summed variables, operands
+  int ops = -1;       // offset into the operand table (2^(r+ns) * m entries), -1 if not encoded
+  int leaf = -1;      // ST_LEAF: leaf index
+  int grad_slot = -1; // ST_GRAD: gradient slot
+  std::vector<int> out_vars, sum_vars;
+  std::vector<Operand> opnd;
+  int out_tid = -1;   // compile-time tensor id of the output (item memory outputs)
+  double flops = 0;   // useful real flops per item
 };
 
 struct Program {
   std::vector<Leaf> leaves;
   std::vector<Step> steps;
-  std::vector<uint32_t> optab;
+  std::vector<uint32_t> optab;   // per-element operand table (small-rank engines)
+  bool has_optab = false;
   std::vector<double> raw;       // raw factor tables, complex (re,im), const-area layout
   std::vector<int> raw_param;    // per raw complex entry: RZ parameter index or -1
   std::vector<int> raw_bit;      // per raw complex entry: 0/1 value of the RZ variable
+  std::vector<int> raw_deriv;    // per raw entry: 1 = derivative table (i/2)(2u-1) e^{i theta (2u-1)/2}
   int n_raw = 0;                 // complex entries of raw tables
   int n_const = 0;               // total constant-area elements (raw + const intermediates)
   int item_elems = 0;            // peak item-memory elements per item
   int n_const_steps = 0;
   int max_rank = 0;
+  int n_grad_slots = 0;          // gradient programs: one slot per RZ gate
+  std::vector<int> grad_param;   // slot -> parameter index
   double flops_item = 0, flops_const = 0;
   double bytes_item = 0;         // algorithmic bytes per item at 8 B per element
 };
 
 bool validate_plan(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                    std::string& err, int& code);
+// gradient = true appends the reverse-mode steps that give d alpha / d theta
+// for every RZ gate (and disables constant hoisting).  encode = true builds
+// the per-element operand table when every step is small enough (rank +
+// summed variables <= 16); otherwise has_optab stays false.
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code);
+                     Program& prog, std::string& err, int& code, bool gradient = false);
 
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.

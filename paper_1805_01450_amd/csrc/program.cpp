@@ -24,13 +24,6 @@ namespace qgm {
 
 namespace {
 
-struct Tn {
-  std::vector<int> vars;  // bit j of the element index = value of vars[j]
-  int is_const;
-  int storage;  // element offset: constant area, or item memory (-1: leaf not yet materialised)
-  int leaf;     // leaf index or -1
-  int alive;
-};
 
 // Item-memory buffers have static lifetimes [first step, last step]; after
 // compilation they are packed offline (largest first, lowest offset that does
@@ -68,9 +61,6 @@ int pack_buffers(std::vector<Buf>& bufs) {
   }
   return peak;
 }
-
-constexpr int kMaxStepBits = 16;
-constexpr size_t kMaxOptab = (size_t)1 << 26;
 
 }  // namespace
 
@@ -125,8 +115,28 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
   return true;
 }
 
+namespace {
+
+// Compile-time tensor.
+struct Tn {
+  std::vector<int> vars;  // bit j of the element index = value of vars[j]
+  int is_const = 0;
+  int storage = -1;       // constant: element offset; item: buffer id (-1: leaf not materialised)
+  int leaf = -1;          // leaf index or -1
+  int alive = 1;
+  int grad = 0;           // depends on an RZ angle (gradient programs)
+  int rz_factor = -1;     // tensor is the table/leaf of this RZ factor
+  int producer = -1;      // forward step that produced it
+  int id = -1;            // index in the tensor list
+  std::vector<int> inputs;  // tensors consumed by the producing step
+};
+
+int popc_bits(int x) { return __builtin_popcount((unsigned)x); }
+
+}  // namespace
+
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code) {
+                     Program& prog, std::string& err, int& code, bool gradient) {
   prog = Program();
   if (!validate_plan(net, sliced, order, err, code)) return false;
   const int nvars = (int)net.vars.size();
@@ -145,37 +155,43 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   std::vector<int> pos(nvars, -1);
   for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int)i;
 
-  // ---- raw tables (constant area prefix)
-  std::vector<int> raw_off(net.factors.size(), -1);
-  auto push_raw = [&](double re, double im, int param, int bit) {
+  // ---- raw tables (constant-area prefix)
+  auto push_raw = [&](double re, double im, int param, int bit, int deriv) {
     prog.raw.push_back(re);
     prog.raw.push_back(im);
     prog.raw_param.push_back(param);
     prog.raw_bit.push_back(bit);
+    prog.raw_deriv.push_back(deriv);
     return prog.n_raw++;
   };
+  std::vector<int> raw_off(net.factors.size(), -1), deriv_off(net.factors.size(), -1);
   for (size_t f = 0; f < net.factors.size(); ++f) {
     const Factor& fa = net.factors[f];
     int n = 1 << fa.nv;
     raw_off[f] = prog.n_raw;
     for (int e = 0; e < n; ++e) {
       if (fa.param >= 0)
-        push_raw(0.0, 0.0, fa.param, fa.nv == 0 ? 0 : (e & 1));
+        push_raw(0.0, 0.0, fa.param, fa.nv == 0 ? 0 : (e & 1), 0);
       else
-        push_raw(fa.tab[2 * e], fa.tab[2 * e + 1], -1, 0);
+        push_raw(fa.tab[2 * e], fa.tab[2 * e + 1], -1, 0, 0);
+    }
+    if (gradient && fa.param >= 0) {
+      deriv_off[f] = prog.n_raw;
+      for (int e = 0; e < n; ++e) push_raw(0.0, 0.0, fa.param, fa.nv == 0 ? 0 : (e & 1), 1);
     }
   }
-  int delta_tab = push_raw(1.0, 0.0, -1, 0);
-  push_raw(0.0, 0.0, -1, 0);
-  int two_tab = push_raw(2.0, 0.0, -1, 0);
+  const int delta_tab = push_raw(1.0, 0.0, -1, 0, 0);
+  push_raw(0.0, 0.0, -1, 0, 0);
+  const int two_tab = push_raw(2.0, 0.0, -1, 0, 0);
+  const int one_tab = push_raw(1.0, 0.0, -1, 0, 0);
 
   // ---- leaves and initial tensors
   std::vector<Tn> T;
-  for (size_t f = 0; f < net.factors.size(); ++f) {
+  auto make_leaf = [&](int f, int table) {
     const Factor& fa = net.factors[f];
     Leaf L{};
-    L.factor = (int)f;
-    L.table = raw_off[f];
+    L.factor = f;
+    L.table = table;
     std::vector<int> fv;
     for (int j = 0; j < fa.nv; ++j) {
       int v = fa.var[j];
@@ -193,17 +209,21 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     }
     Tn t;
     t.vars = fv;
-    t.alive = 1;
+    t.id = (int)T.size();
     if (L.ndep == 0) {
-      // constant: the raw table itself, element index = factor's own layout
       t.is_const = 1;
-      t.storage = raw_off[f];
-      t.leaf = -1;
+      t.storage = table;
     } else {
-      t.is_const = 0;
-      t.storage = -1;
       t.leaf = (int)prog.leaves.size();
       prog.leaves.push_back(L);
+    }
+    return t;
+  };
+  for (size_t f = 0; f < net.factors.size(); ++f) {
+    Tn t = make_leaf((int)f, raw_off[f]);
+    if (gradient && net.factors[f].param >= 0) {
+      t.grad = 1;
+      t.rz_factor = (int)f;
     }
     T.push_back(t);
   }
@@ -217,10 +237,8 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     L.dep_bit[0] = q;
     L.dep_stride[0] = 1;
     Tn t;
-    t.is_const = 0;
-    t.storage = -1;
     t.leaf = (int)prog.leaves.size();
-    t.alive = 1;
+    t.id = (int)T.size();
     prog.leaves.push_back(L);
     T.push_back(t);
   }
@@ -229,41 +247,95 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   for (auto& t : T)
     for (int v : t.vars) count[v]++;
 
-  std::vector<Buf> bufs;        // item-memory buffers (Tn::storage holds the buffer id)
-  std::vector<int> op_buf;       // per optab entry: buffer id or -1 (constant)
-  std::vector<int> step_buf;     // per step: output buffer id or -1
+  std::vector<Buf> bufs;
+  std::vector<int> step_buf;  // per step: output buffer id or -1
+  int const_top = prog.n_raw;
   auto new_buf = [&](int size) {
     bufs.push_back(Buf{size, (int)prog.steps.size(), (int)prog.steps.size(), 0});
     return (int)bufs.size() - 1;
   };
-  int const_top = prog.n_raw;
-  std::vector<char> done(nvars, 0);
-  int n_two = 0;
-
   auto materialise = [&](Tn& t) {
     if (t.is_const || t.storage >= 0) return;
-    int n = 1 << t.vars.size();
-    t.storage = new_buf(n);
-    Step st{};
+    t.storage = new_buf(1 << t.vars.size());
+    Step st;
     st.kind = ST_LEAF;
-    st.out = 0;
     st.r = (int)t.vars.size();
     st.leaf = t.leaf;
+    st.out_tid = t.id;
     prog.steps.push_back(st);
     step_buf.push_back(t.storage);
   };
-  // Constant operands get their final offset now; item operands are patched
-  // after buffer packing.  Reading a buffer extends its lifetime to this step.
-  auto operand_entry = [&](const Tn& t, int off) -> uint32_t {
-    if (t.is_const) {
-      op_buf.push_back(-1);
-      return OP_CONST | (uint32_t)(t.storage + off);
+  auto as_operand = [&](const Tn& t) {
+    Operand o;
+    o.is_const = t.is_const;
+    o.storage = t.storage;
+    o.vars = t.vars;
+    o.tid = t.id;
+    if (!t.is_const) bufs[t.storage].last = (int)prog.steps.size();
+    return o;
+  };
+  // Append a product-sum step; returns the index of the new tensor (or -1
+  // for FINAL / GRAD steps, which write outside item memory).
+  auto emit = [&](int kind, const std::vector<int>& in, const std::vector<int>& out_vars,
+                  const std::vector<int>& sum_vars, bool make_const, int grad_slot, int extra_const,
+                  int n_extra) -> int {
+    Step st;
+    st.kind = kind;
+    st.out_vars = out_vars;
+    st.sum_vars = sum_vars;
+    st.r = (int)out_vars.size();
+    st.ns = (int)sum_vars.size();
+    st.grad_slot = grad_slot;
+    // leaves first: a leaf step pushed between two operand reads would end the
+    // earlier operand's lifetime before this step
+    for (int i : in) materialise(T[i]);
+    for (int i : in) st.opnd.push_back(as_operand(T[i]));
+    for (int e = 0; e < n_extra; ++e) st.opnd.push_back(Operand{1, extra_const, {}});
+    st.m = (int)st.opnd.size();
+    st.flops = std::ldexp(1.0, st.r + st.ns) * (6.0 * std::max(0, st.m - 1) + 2.0);
+    int id = -1, buf = -1;
+    if (kind == ST_ELIM) {
+      Tn nt;
+      nt.vars = out_vars;
+      nt.is_const = make_const ? 1 : 0;
+      if (make_const) {
+        nt.storage = const_top;
+        const_top += 1 << st.r;
+      } else {
+        nt.storage = buf = new_buf(1 << st.r);
+      }
+      st.is_const = nt.is_const;
+      st.out = nt.storage;
+      nt.producer = (int)prog.steps.size();
+      nt.inputs = in;
+      nt.id = (int)T.size();
+      st.out_tid = nt.id;
+      for (int i : in) nt.grad |= T[i].grad;
+      T.push_back(nt);
+      id = (int)T.size() - 1;
     }
-    op_buf.push_back(t.storage);
-    bufs[t.storage].last = (int)prog.steps.size();
-    return (uint32_t)off;
+    // the output buffer is placed after inputs are read: a step's inputs and
+    // output never share memory because their lifetimes overlap at the step
+    // (first == last == this step for the output start)
+    prog.steps.push_back(st);
+    step_buf.push_back(buf);
+    prog.max_rank = std::max(prog.max_rank, st.r);
+    if (st.is_const) {
+      prog.flops_const += st.flops;
+      prog.n_const_steps++;
+    } else {
+      prog.flops_item += st.flops;
+      double in_elems = 0;
+      for (const Operand& o : prog.steps.back().opnd) in_elems += std::ldexp(1.0, (int)o.vars.size());
+      prog.bytes_item += 8.0 * (in_elems + std::ldexp(1.0, st.r));
+    }
+    return id;
   };
 
+  // ---- forward: variable elimination along the order
+  std::vector<char> done(nvars, 0);
+  int n_two = 0;
+  std::vector<int> fwd_steps;  // tensor ids produced by forward ELIM steps, in order
   for (int v : order) {
     if (done[v]) continue;
     std::vector<int> tv;
@@ -284,81 +356,23 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     std::vector<int> S{v}, out;
     for (int u : vv) {
       if (u == v) continue;
-      if (cnt_in[u] == count[u]) S.push_back(u);
-      else out.push_back(u);
+      if (cnt_in[u] == count[u])
+        S.push_back(u);
+      else
+        out.push_back(u);
     }
     std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
     std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
-    int r = (int)out.size(), ns = (int)S.size(), m = (int)tv.size();
-    bool all_const = true;
-    for (int i : tv) {
-      materialise(T[i]);
-      all_const = all_const && T[i].is_const;
-    }
-    Tn nt;
-    nt.vars = out;
-    nt.is_const = all_const ? 1 : 0;
-    nt.leaf = -1;
-    nt.alive = 1;
-    if (all_const) {
-      nt.storage = const_top;
-      const_top += 1 << r;
-    } else {
-      nt.storage = new_buf(1 << r);
-    }
-    Step st{};
-    st.kind = ST_ELIM;
-    st.is_const = nt.is_const;
-    st.out = nt.storage;
-    st.r = r;
-    st.ns = ns;
-    st.m = m;
-    st.ops = (int)prog.optab.size();
-    // value of each variable of V_v at (c, s)
-    std::vector<int> bitpos(nvars, -1), from_s(nvars, 0);
-    for (int j = 0; j < r; ++j) bitpos[out[j]] = j;
-    for (int j = 0; j < ns; ++j) {
-      bitpos[S[j]] = j;
-      from_s[S[j]] = 1;
-    }
-    if (r + ns > kMaxStepBits || prog.optab.size() + ((size_t)m << (r + ns)) > kMaxOptab) {
-      err = "plan has a step of rank " + std::to_string(r) + " summing " + std::to_string(ns) +
-            " variables; the per-item program supports rank + summed <= " + std::to_string(kMaxStepBits);
-      code = -7;
-      return false;
-    }
-    for (int c = 0; c < (1 << r); ++c)
-      for (int s = 0; s < (1 << ns); ++s)
-        for (int i : tv) {
-          int off = 0;
-          const Tn& t = T[i];
-          for (size_t j = 0; j < t.vars.size(); ++j) {
-            int u = t.vars[j];
-            int val = from_s[u] ? (s >> bitpos[u]) & 1 : (c >> bitpos[u]) & 1;
-            off |= val << j;
-          }
-          prog.optab.push_back(operand_entry(t, off));
-        }
-    st.flops = std::ldexp(1.0, r + ns) * (6.0 * (m - 1) + 2.0);
-    prog.steps.push_back(st);
-    step_buf.push_back(all_const ? -1 : nt.storage);
-    prog.max_rank = std::max(prog.max_rank, r);
-    if (all_const) {
-      prog.flops_const += st.flops;
-      prog.n_const_steps++;
-    } else {
-      prog.flops_item += st.flops;
-      double in_elems = 0;
-      for (int i : tv) in_elems += std::ldexp(1.0, (int)T[i].vars.size());
-      prog.bytes_item += 8.0 * (in_elems + std::ldexp(1.0, r));
-    }
+    bool all_const = !gradient;
+    for (int i : tv) all_const = all_const && T[i].is_const;
+    int id = emit(ST_ELIM, tv, out, S, all_const, -1, 0, 0);
+    fwd_steps.push_back(id);
     for (int i : tv) {
       for (int u : T[i].vars) count[u]--;
       T[i].alive = 0;
     }
     for (int u : S) done[u] = 1;
     for (int u : out) count[u]++;
-    T.push_back(nt);
   }
 
   // ---- final product of the remaining scalars
@@ -372,29 +386,141 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     }
     rest.push_back((int)i);
   }
-  for (int i : rest) materialise(T[i]);
-  Step fin{};
-  fin.kind = ST_FINAL;
-  fin.m = (int)rest.size() + n_two;
-  fin.ops = (int)prog.optab.size();
-  for (int i : rest) prog.optab.push_back(operand_entry(T[i], 0));
-  for (int i = 0; i < n_two; ++i) {
-    prog.optab.push_back(OP_CONST | (uint32_t)two_tab);
-    op_buf.push_back(-1);
+  emit(ST_FINAL, rest, {}, {}, false, -1, two_tab, n_two);
+
+  // ---- reverse mode (gradient programs)
+  if (gradient) {
+    std::vector<int> adj(T.size(), -1);
+    auto grad_out = [&](int t) {
+      // d alpha / d theta contribution of RZ factor f: sum_u adj(u) * D_f(u)
+      const int f = T[t].rz_factor;
+      const int slot = prog.n_grad_slots++;
+      prog.grad_param.push_back(net.factors[f].param);
+      Tn d = make_leaf(f, deriv_off[f]);  // derivative table, same fixed bits as the gate
+      T.push_back(d);
+      const int di = (int)T.size() - 1;
+      std::vector<int> sv = T[t].vars;
+      emit(ST_GRAD, {adj[t], di}, {}, sv, false, slot, 0, 0);
+    };
+    // adjoints of the FINAL operands
+    for (size_t a = 0; a < rest.size(); ++a) {
+      int t = rest[a];
+      if (!T[t].grad) continue;
+      std::vector<int> others;
+      for (size_t b = 0; b < rest.size(); ++b)
+        if (b != a) others.push_back(rest[b]);
+      adj[t] = emit(ST_ELIM, others, {}, {}, false, -1, others.empty() ? one_tab : two_tab,
+                    others.empty() ? 1 : n_two);
+      if (adj.size() < T.size()) adj.resize(T.size(), -1);
+    }
+    // reverse over the forward eliminations
+    for (int k = (int)fwd_steps.size() - 1; k >= 0; --k) {
+      const int o = fwd_steps[k];
+      if (o < 0 || adj[o] < 0) continue;
+      const Step st = prog.steps[T[o].producer];
+      std::vector<int> full = st.out_vars;
+      full.insert(full.end(), st.sum_vars.begin(), st.sum_vars.end());
+      const std::vector<int> ins = T[o].inputs;
+      for (size_t a = 0; a < ins.size(); ++a) {
+        int t = ins[a];
+        if (!T[t].grad) continue;
+        std::vector<int> ops{adj[o]};
+        for (size_t b = 0; b < ins.size(); ++b)
+          if (b != a) ops.push_back(ins[b]);
+        std::vector<int> sum;
+        for (int u : full)
+          if (std::find(T[t].vars.begin(), T[t].vars.end(), u) == T[t].vars.end()) sum.push_back(u);
+        int id = emit(ST_ELIM, ops, T[t].vars, sum, false, -1, 0, 0);
+        if (adj.size() < T.size()) adj.resize(T.size(), -1);
+        adj[t] = id;
+      }
+    }
+    for (size_t t = 0; t < T.size(); ++t)
+      if (T[t].rz_factor >= 0 && t < adj.size() && adj[t] >= 0) grad_out((int)t);
   }
-  fin.flops = 6.0 * std::max(0, fin.m - 1);
-  prog.flops_item += fin.flops;
-  prog.steps.push_back(fin);
-  step_buf.push_back(-1);
+
+  // ---- place item memory, then patch operand and output offsets
   prog.n_const = const_top;
   prog.item_elems = std::max(1, pack_buffers(bufs));
-  for (size_t i = 0; i < prog.optab.size(); ++i)
-    if (op_buf[i] >= 0) prog.optab[i] += (uint32_t)bufs[op_buf[i]].offset;
-  for (size_t i = 0; i < prog.steps.size(); ++i)
-    if (step_buf[i] >= 0) prog.steps[i].out = bufs[step_buf[i]].offset;
-  // constant steps must come first in execution; they only read constants, so
-  // a stable partition keeps every dependency satisfied.
+  for (size_t i = 0; i < prog.steps.size(); ++i) {
+    Step& st = prog.steps[i];
+    if (step_buf[i] >= 0) st.out = bufs[step_buf[i]].offset;
+    for (Operand& o : st.opnd)
+      if (!o.is_const) o.storage = bufs[o.storage].offset;
+  }
+  // constant steps first; they read constants only, so their order among
+  // themselves and the item steps' order are unchanged
   std::stable_partition(prog.steps.begin(), prog.steps.end(), [](const Step& s) { return s.is_const; });
+
+  // ---- check: replay the item steps on an ownership map of item memory;
+  // every operand must find its own tensor in place when it is read
+  {
+    std::vector<int> owner((size_t)prog.item_elems, -1);
+    for (size_t i = 0; i < prog.steps.size(); ++i) {
+      const Step& st = prog.steps[i];
+      if (st.is_const) continue;
+      for (const Operand& o : st.opnd) {
+        if (o.is_const) continue;
+        const int n = 1 << o.vars.size();
+        for (int e = 0; e < n; ++e)
+          if (o.storage + e >= prog.item_elems || owner[o.storage + e] != o.tid) {
+            err = "internal: item memory check failed at step " + std::to_string(i);
+            code = -1;
+            return false;
+          }
+      }
+      if (st.kind == ST_LEAF || st.kind == ST_ELIM) {
+        const int n = 1 << st.r;
+        if (st.out + n > prog.item_elems) {
+          err = "internal: item memory overflow at step " + std::to_string(i);
+          code = -1;
+          return false;
+        }
+        for (int e = 0; e < n; ++e) owner[st.out + e] = st.out_tid;
+      }
+    }
+  }
+
+  // ---- per-element operand table for the small-rank engines
+  constexpr int kMaxStepBits = 16;
+  constexpr size_t kMaxOptab = (size_t)1 << 26;
+  size_t need = 0;
+  bool fits = true;
+  for (const Step& st : prog.steps) {
+    if (st.kind == ST_LEAF) continue;
+    if (st.r + st.ns > kMaxStepBits) fits = false;
+    else need += (size_t)st.m << (st.r + st.ns);
+  }
+  fits = fits && need <= kMaxOptab;
+  if (fits) {
+    prog.optab.reserve(need);
+    std::vector<int> bitpos(nvars, -1), from_s(nvars, 0);
+    for (Step& st : prog.steps) {
+      if (st.kind == ST_LEAF) continue;
+      st.ops = (int)prog.optab.size();
+      for (int j = 0; j < st.r; ++j) {
+        bitpos[st.out_vars[j]] = j;
+        from_s[st.out_vars[j]] = 0;
+      }
+      for (int j = 0; j < st.ns; ++j) {
+        bitpos[st.sum_vars[j]] = j;
+        from_s[st.sum_vars[j]] = 1;
+      }
+      for (int c = 0; c < (1 << st.r); ++c)
+        for (int s2 = 0; s2 < (1 << st.ns); ++s2)
+          for (const Operand& o : st.opnd) {
+            int off = 0;
+            for (size_t j = 0; j < o.vars.size(); ++j) {
+              int u = o.vars[j];
+              int val = from_s[u] ? (s2 >> bitpos[u]) & 1 : (c >> bitpos[u]) & 1;
+              off |= val << j;
+            }
+            prog.optab.push_back((o.is_const ? OP_CONST : 0u) | (uint32_t)(o.storage + off));
+          }
+    }
+    prog.has_optab = true;
+  }
+  (void)popc_bits;
   return true;
 }
 

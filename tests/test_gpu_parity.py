@@ -253,3 +253,125 @@ def test_config3_6x6x25_one_launch():
     m1 = np.mean((2.0 ** 36) * np.abs(got) ** 2)
     note("Porter-Thomas first moment", m1)
     assert abs(m1 - 1.0) < 0.2
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_graph_replay_matches_direct_launch(config2, cuda, engine):
+    """Captured runs replayed several times, with eager work in between, give
+    the direct launch's result bit for bit on every replay."""
+    torch = cuda
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=7, time_budget_s=0.2)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64, engine=engine)
+    n_s = 1 << 7
+    d_bits = torch.from_numpy(bits).cuda()
+    ws = p.workspace(64, n_s)
+    d_direct = torch.empty((64, 4), dtype=torch.float64, device="cuda")
+    q.qgm_amplitudes_device(p.h, d_bits, None, 0, n_s, ws, d_direct)
+    direct = d_direct.cpu().numpy()
+    d_part = torch.full((64, 4), float("nan"), dtype=torch.float64, device="cuda")
+    g = q.qgm_graph_create(p.h, d_bits, None, 0, n_s, ws, d_part, repeat=3)
+    try:
+        for rep in range(4):
+            d_part.fill_(float("nan"))
+            scratch = torch.randn(1 << 16, device="cuda") * 2.0  # unrelated eager work
+            torch.cuda.synchronize()
+            q.qgm_graph_launch(g)
+            torch.cuda.synchronize()
+            note("graph replay", rep, "engine", engine, float(scratch.sum()))
+            assert np.array_equal(d_part.cpu().numpy(), direct)
+    finally:
+        q.qgm_graph_free(g)
+    amp = direct[:, 0] + direct[:, 2] + 1j * (direct[:, 1] + direct[:, 3])
+    assert nerr(amp, ref, 25).max() <= C64_TOL
+
+
+def _rz_case(n, d, seed, n_bs=1):
+    text = generate_circuit(n, d, seed, rz=True)
+    _, npar = parse_header(text)
+    th = random_thetas(npar, seed + 2000)
+    bits = random_bitstrings(n * n, n_bs, seed + 1000)
+    return text, th, bits
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_gradient_vs_shift_rule_and_fd(engine):
+    text, th, bits = _rz_case(4, 10, 3)
+    x = bits[0]
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=2, time_budget_s=0.2)
+    p = q.Plan(c, sl, order, engine=engine, gradient=True)
+    note("gradient 4x4x10 RZ, params", len(th), "engine", engine, "stats", p.stats()["n_steps"])
+    amp, grad = p.amplitude_grad(x, th)
+    ref_amp = oracle.sv_amplitudes(text, [x], th)[0]
+    shift = oracle.sv_gradient_shift(text, x, th)
+    scale = max(abs(ref_amp), 2.0 ** -8)
+    assert abs(amp - ref_amp) / scale <= C128_TOL
+    assert np.max(np.abs(grad - shift)) / scale <= 1e-11
+    # central differences of the device amplitudes, h = 1e-4 (error ~ h^2/6 |alpha'''|)
+    plain = q.Plan(c, sl, order, engine=engine)
+    fd = oracle.fd_gradient(lambda pp: plain.amplitudes([x], pp)[0], th, h=1e-4)
+    assert np.max(np.abs(grad - fd)) / scale <= 1e-7
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_gradient_summed_over_slices_5x5x20(engine):
+    text, th, bits = _rz_case(5, 20, 1)
+    x = bits[0]
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.3)
+    p = q.Plan(c, sl, order, engine=engine, gradient=True)
+    note("gradient 5x5x20 RZ, k=6, params", len(th), "engine", engine)
+    amp, grad = p.amplitude_grad(x, th)
+    net = oracle.build_network(text, th)
+    ref_amp = oracle.ve_amplitude(text, x, params=th, net=net)
+    shift = []
+    for j in range(len(th)):
+        t2 = th.copy()
+        t2[j] += np.pi
+        shift.append(0.5 * oracle.ve_amplitude(text, x, params=t2))
+    shift = np.array(shift)
+    scale = max(abs(ref_amp), 2.0 ** -12.5)
+    assert abs(amp - ref_amp) / scale <= C128_TOL
+    assert np.max(np.abs(grad - shift)) / scale <= 1e-11
+
+
+def test_gradient_c64_and_device_entry(cuda):
+    torch = cuda
+    text, th, bits = _rz_case(4, 12, 7, n_bs=3)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64, gradient=True)
+    npar = len(th)
+    d_bits = torch.from_numpy(bits).cuda()
+    d_th = torch.from_numpy(th).cuda()
+    d_part = torch.empty((3, 4), dtype=torch.float64, device="cuda")
+    d_g = torch.empty((3, npar, 4), dtype=torch.float64, device="cuda")
+    q.qgm_gradients_device(p.h, d_bits, d_th, 0, 8, p.workspace(3), d_part, d_g)
+    g = d_g.cpu().numpy()
+    grads = g[..., 0] + g[..., 2] + 1j * (g[..., 1] + g[..., 3])
+    for i in range(3):
+        shift = oracle.sv_gradient_shift(text, bits[i], th)
+        ref = oracle.sv_amplitudes(text, [bits[i]], th)[0]
+        scale = max(abs(ref), 2.0 ** -8)
+        assert np.max(np.abs(grads[i] - shift)) / scale <= 10 * C64_TOL
+
+
+def test_autograd_function_gradcheck(cuda):
+    torch = cuda
+    text, th, bits = _rz_case(3, 8, 11)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=1, time_budget_s=0.1)
+    p = q.Plan(c, sl, order, gradient=True)
+    Fn = q.AmplitudeFn
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    note("gradcheck 3x3x8 RZ params", len(th))
+    assert torch.autograd.gradcheck(lambda t: Fn.apply(t, p, bits[0]), (theta,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    # |alpha|^2 backward against the shift rule
+    a = Fn.apply(theta, p, bits[0])
+    (a.abs() ** 2).backward()
+    ref = oracle.sv_amplitudes(text, [bits[0]], th)[0]
+    shift = oracle.sv_gradient_shift(text, bits[0], th)
+    want = 2.0 * np.real(np.conj(ref) * shift)
+    assert np.max(np.abs(theta.grad.numpy() - want)) <= 1e-12
