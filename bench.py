@@ -97,7 +97,22 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "interpreter", "generated"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the c128 and interpreter comparison runs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (PMC byte-counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        torch.cuda.set_device(0)
+        n = 1 << 28
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_dispatch": 4 * n, "copy_bytes_written_per_dispatch": 4 * n,
+                          "dispatches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the slice axis would shard across GPUs "
                                    "by contiguous slice ranges (see qgm_amplitudes_range)"}))

@@ -65,21 +65,25 @@ typedef struct {
 typedef struct {
   int32_t prec;          /* qgm_precision */
   int32_t profile;       /* 1 = record HIP events around each kernel of every run (qgm_plan_timing) */
-  size_t workspace_cap;  /* 0 = no cap; else plan_create fails with QGM_E_WORKSPACE when the
-                            per-item memory of the plan cannot fit in it */
+  size_t workspace_cap;  /* 0 = no cap (WIDE: 96 GiB of item tensors per pass); else plan_create
+                            fails with QGM_E_WORKSPACE when one work item's memory cannot fit */
   int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
   int32_t gradient;      /* 1 = also compile the reverse-mode steps for d alpha / d theta */
   int32_t reserved[6];
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
- * memory fits in registers and INTERPRETER otherwise.
+ * memory fits in registers, INTERPRETER when every step is small (rank +
+ * summed variables <= 16) and WIDE otherwise.
  * GENERATED: plan_create emits straight-line HIP for the plan (every operand
  *   offset is static) and compiles it for gfx950 with hiprtc; item tensors
  *   live in registers; slice sums are fused into the kernel.
  * INTERPRETER: one prebuilt persistent kernel walks a step table with a
- *   device work queue; item tensors live in LDS (or global scratch). */
-enum { QGM_ENGINE_AUTO = 0, QGM_ENGINE_INTERPRETER = 1, QGM_ENGINE_GENERATED = 2 };
+ *   device work queue; item tensors live in LDS (or global scratch).
+ * WIDE: one kernel per elimination step; item tensors live in HBM as
+ *   [element][64 items] rows (every access a contiguous row); groups of 64
+ *   items are processed in passes that fit workspace_cap (default 96 GiB). */
+enum { QGM_ENGINE_AUTO = 0, QGM_ENGINE_INTERPRETER = 1, QGM_ENGINE_GENERATED = 2, QGM_ENGINE_WIDE = 3 };
 
 typedef struct {
   int32_t n_steps;        /* elimination + leaf steps of the compiled program */
@@ -94,7 +98,7 @@ typedef struct {
   double bytes_item;      /* bytes read + written per slice if every intermediate made
                              one trip to memory, at 8 B per element */
   double cost;            /* sum over eliminations of 2^deg(v) (Section "Variable elimination") */
-  int32_t engine;         /* engine the plan runs with (QGM_ENGINE_INTERPRETER or _GENERATED) */
+  int32_t engine;         /* engine the plan runs with (INTERPRETER, GENERATED or WIDE) */
   int32_t pad0;
   double compile_s;       /* seconds spent generating and compiling the plan's kernel */
 } qgm_stats;

@@ -18,6 +18,7 @@ QGM_C64 = 1
 QGM_ENGINE_AUTO = 0
 QGM_ENGINE_INTERPRETER = 1
 QGM_ENGINE_GENERATED = 2
+QGM_ENGINE_WIDE = 3
 
 
 def _i32(seq):

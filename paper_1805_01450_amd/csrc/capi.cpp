@@ -36,6 +36,7 @@ struct qgm_plan {
   DevProgram dev;
   int engine = QGM_ENGINE_INTERPRETER;  // engine in use
   std::vector<char> code;                // generated kernel code object (engine GENERATED)
+  WideProgram wide;                      // descriptors (engine WIDE)
   double compile_s = 0;
   qgm_plan_opts opts;
   double cost = 0;
@@ -92,7 +93,7 @@ Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool g
 
 qgm_status ensure_device(qgm_plan* p) {
   std::string err;
-  int rc = dev_upload(p->prog, p->code, p->dev, err);
+  int rc = dev_upload(p->prog, p->code, p->engine == QGM_ENGINE_WIDE ? &p->wide : nullptr, p->dev, err);
   if (rc) return fail((qgm_status)rc, err);
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->dev.device)
@@ -104,6 +105,8 @@ qgm_status ensure_device(qgm_plan* p) {
 qgm_status layout_for(qgm_plan* p, int n_bs, uint64_t n_s, WsLayout& ws, LaunchCfg& cfg) {
   cfg.prec = p->opts.prec;
   cfg.generated = p->engine == QGM_ENGINE_GENERATED ? 1 : 0;
+  cfg.wide = p->engine == QGM_ENGINE_WIDE ? 1 : 0;
+  cfg.wide_budget = p->opts.workspace_cap ? p->opts.workspace_cap : ((size_t)96 << 30);
   cfg.n_qubits = p->net.n_qubits;
   cfg.n_bs = n_bs;
   cfg.s_begin = 0;
@@ -246,7 +249,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   o.prec = QGM_C128;
   if (opts) o = *opts;
   if (o.prec != QGM_C128 && o.prec != QGM_C64) return fail(QGM_E_UNSUPPORTED, "unknown precision");
-  if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_GENERATED) return fail(QGM_E_ARG, "unknown engine");
+  if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_WIDE) return fail(QGM_E_ARG, "unknown engine");
   auto* p = new qgm_plan();
   p->net = c->net;
   p->sliced = sv;
@@ -258,9 +261,9 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     delete p;
     return fail((qgm_status)code, err);
   }
-  if (!p->prog.has_optab) {
+  if (!p->prog.has_optab && (o.engine == QGM_ENGINE_INTERPRETER || o.engine == QGM_ENGINE_GENERATED)) {
     delete p;
-    return fail(QGM_E_UNSUPPORTED, "plan has a step of rank + summed variables > 16, beyond the per-item engines");
+    return fail(QGM_E_UNSUPPORTED, "plan has a step of rank + summed variables > 16: only the WIDE engine runs it");
   }
   if (o.workspace_cap) {
     const size_t el = o.prec == QGM_C128 ? 16 : 8;
@@ -278,14 +281,25 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   for (int v : ov) og.push_back(vov[v]);
   p->cost = order_cost(g, og, removed).cost;
   // Engine: the generated kernel keeps item tensors in registers, so it is
-  // chosen automatically only when the live item memory is small.
+  // chosen automatically only when the live item memory is small; plans
+  // with large steps run on the wide engine.
   const int reg_limit = o.prec == QGM_C128 ? 320 : 512;
   bool want_gen = o.engine == QGM_ENGINE_GENERATED ||
-                  (o.engine == QGM_ENGINE_AUTO && p->prog.item_elems <= reg_limit);
+                  (o.engine == QGM_ENGINE_AUTO && p->prog.has_optab && p->prog.item_elems <= reg_limit);
+  bool want_wide = o.engine == QGM_ENGINE_WIDE || (o.engine == QGM_ENGINE_AUTO && !p->prog.has_optab);
   p->engine = QGM_ENGINE_INTERPRETER;
+  if (want_wide) {
+    std::string werr;
+    if (!encode_wide(p->prog, p->wide, werr)) {
+      delete p;
+      return fail(QGM_E_UNSUPPORTED, werr);
+    }
+    p->engine = QGM_ENGINE_WIDE;
+    want_gen = false;
+  }
   if (want_gen) {
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = generate_chain_source(p->prog, o.prec);
+    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits);
     std::string jerr;
     bool ok = jit_compile(src, "qgm_chain.hip", p->code, jerr);
     if (const char* dir = std::getenv("QGM_DUMP_DIR")) {

@@ -116,7 +116,7 @@ class Gen {
 
 }  // namespace
 
-std::string generate_chain_source(const Program& prog, int prec) {
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits) {
   std::ostringstream head, o;
   const char* R = prec == 0 ? "double" : "float";
   head << "typedef " << R << " R;\n"
@@ -127,8 +127,9 @@ std::string generate_chain_source(const Program& prog, int prec) {
        << "static __device__ __forceinline__ C2 sel(bool t, C2 a1, C2 a0) { C2 c; c.x = t ? a1.x : a0.x; "
           "c.y = t ? a1.y : a0.y; return c; }\n"
 
-       << "static __device__ __forceinline__ void nsum(double& s, double& c, double x) { double t = s + x; "
-          "if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s; s = t; }\n"
+       << "static __device__ __forceinline__ void wave_sum(double& s, double& c) { for (int m = 1; m < 64; m <<= 1) "
+          "{ const double so = __shfl_xor(s, m); const double co = __shfl_xor(c, m); const double t = s + so; "
+          "const double bv = t - s; const double e = (s - (t - bv)) + (so - bv); s = t; c = (c + co) + e; } }\n"
        << "extern \"C\" __global__ void __launch_bounds__(64) qgm_chain(const double* __restrict__ rawd, "
           "const double* __restrict__ params, const unsigned char* __restrict__ bits, int n_qubits, "
           "unsigned long long n_bs, unsigned long long s_begin, unsigned long long n_s, unsigned long long n_items, "
@@ -141,9 +142,12 @@ std::string generate_chain_source(const Program& prog, int prec) {
        << "  const unsigned long long b = item / n_s;\n"
        << "  const unsigned long long sl = item - b * n_s;\n"
        << "  const unsigned long long s = s_begin + sl;\n"
-       << "  unsigned long long xb = 0;\n"
-       << "  for (int q = 0; q < n_qubits; ++q) xb |= (unsigned long long)(bits[b * n_qubits + q] & 1) << q;\n"
-       << "  (void)s; (void)xb;\n";
+       << "  const unsigned char* xrow = bits + b * (unsigned long long)n_qubits;\n"
+       << "  unsigned long long xb = 0;\n";
+  // the row length is a constant of the plan: independent loads, no loop
+  for (int q = 0; q < n_qubits; ++q)
+    head << "  xb |= (unsigned long long)(xrow[" << q << "] & 1) << " << q << ";\n";
+  head << "  (void)s; (void)xb; (void)xrow;\n";
   int n_params = 0;
   for (int k = 0; k < prog.n_raw; ++k) n_params = std::max(n_params, prog.raw_param[k] + 1);
   if (n_params > 0) {
@@ -211,20 +215,21 @@ std::string generate_chain_source(const Program& prog, int prec) {
         o << " m" << (st.out + c) << " = a; }\n";
     }
   }
+  // fused slice sum of the block's 64 slices: the compensated butterfly that
+  // the reduction kernels use for each chunk of 64 slices
   o << "  if (!fused) {\n"
     << "    if (valid) res[sl * n_bs + b] = amp;\n"
     << "    return;\n"
     << "  }\n"
-    << "  __shared__ double sh[128];\n"
-    << "  sh[2 * lane] = (double)amp.x;\n"
-    << "  sh[2 * lane + 1] = (double)amp.y;\n"
-    << "  __syncthreads();\n"
-    << "  if (lane < 2) {\n"
-    << "    double sum = 0.0, comp = 0.0;\n"
-    << "    for (int i = 0; i < 64; ++i) nsum(sum, comp, sh[2 * i + lane]);\n"
+    << "  double sr = (double)amp.x, si = (double)amp.y, cr = 0.0, ci = 0.0;\n"
+    << "  wave_sum(sr, cr);\n"
+    << "  wave_sum(si, ci);\n"
+    << "  if (lane == 0) {\n"
     << "    const unsigned long long chunk = item / 64ull;\n"
-    << "    part[4 * chunk + lane] = sum;\n"
-    << "    part[4 * chunk + 2 + lane] = comp;\n"
+    << "    part[4 * chunk + 0] = sr;\n"
+    << "    part[4 * chunk + 1] = si;\n"
+    << "    part[4 * chunk + 2] = cr;\n"
+    << "    part[4 * chunk + 3] = ci;\n"
     << "  }\n"
     << "}\n";
   return head.str() + o.str();

@@ -9,6 +9,15 @@
 
 namespace qgm {
 
+// Wide-engine descriptors on the device (plus the host copy of the step
+// records, read when launching).
+struct WideDev {
+  void* steps = nullptr;
+  void* ops = nullptr;
+  int n_steps = 0;
+  std::vector<int32_t> host_steps;
+};
+
 // Device-resident copy of a compiled program (owned by a plan).
 struct DevProgram {
   int device = -1;
@@ -23,6 +32,7 @@ struct DevProgram {
   int n_steps = 0, n_const_steps = 0;
   int n_cu = 0;
   size_t max_lds = 0;
+  WideDev wide;            // wide engine (empty otherwise)
   void* module = nullptr;  // hipModule_t of the generated chain kernel
   void* chain_fn = nullptr;  // hipFunction_t "qgm_chain"
 };
@@ -30,7 +40,9 @@ struct DevProgram {
 // Precision of the slice contraction: 0 = complex128, 1 = complex64.
 struct LaunchCfg {
   int prec;
-  int generated;        // 1 = generated chain kernel, 0 = interpreter
+  int generated;        // 1 = generated chain kernel
+  int wide;             // 1 = wide engine (one kernel per step, tensors in HBM)
+  size_t wide_budget;   // bytes of HBM the wide engine may use for item tensors
   int n_qubits;
   int n_bs;             // bitstrings
   uint64_t s_begin;     // first slice index
@@ -41,6 +53,7 @@ struct LaunchCfg {
 struct WsLayout {
   size_t cst, bits, res, gres, counter, chunks, scratch, total;
   int fused;            // generated kernel sums each block's 64 slices itself
+  int wide_groups;      // wide engine: 64-item groups resident per pass
   int use_lds;
   int grid;             // persistent workgroups (one wave each)
   size_t lds_bytes;     // dynamic LDS per workgroup
@@ -49,7 +62,8 @@ struct WsLayout {
 // All functions return 0 or a negative qgm status; `err` gets a message.
 // Uploads the program tables and, when `code` is not empty, loads the
 // generated kernel's code object on the current device.
-int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& dp, std::string& err);
+int dev_upload(const Program& prog, const std::vector<char>& code, const WideProgram* wide, DevProgram& dp,
+               std::string& err);
 void dev_free(DevProgram& dp);
 int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, WsLayout& ws, std::string& err);
 // Runs prologue, persistent chain and slice reduction on `stream`.  Device

@@ -19,6 +19,11 @@
 
 namespace qgm {
 
+template <typename R>
+int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const void* cst, void* mem,
+                      uint64_t group_elems, const uint64_t* packed, int n_bs, uint64_t s_begin, uint64_t n_s,
+                      uint64_t n_items, void* res, void* gres, bool const_steps, hipStream_t stream);
+
 namespace {
 
 struct DevStep {
@@ -213,35 +218,61 @@ __device__ __forceinline__ void neumaier(double& sum, double& comp, double x) {
   sum = t;
 }
 
-// Two-level order shared by every path: slices are taken in chunks of 64
-// (ascending s); each chunk is summed with compensation into (sum_c, comp_c);
-// the chunk sums are then added in ascending chunk order with compensation and
-// the compensations are accumulated alongside.
-template <typename R>
-__global__ void reduce_kernel(const cx<R>* __restrict__ res, int n_bs, uint64_t n_s, double* __restrict__ partial) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bs) return;
-  double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
-  for (uint64_t c0 = 0; c0 < n_s; c0 += 64) {
-    const uint64_t c1 = c0 + 64 < n_s ? c0 + 64 : n_s;
-    double cs[2] = {0, 0}, cc[2] = {0, 0};
-    for (uint64_t s = c0; s < c1; ++s) {
-      cx<R> v = res[s * (uint64_t)n_bs + b];
-      neumaier(cs[0], cc[0], (double)v.x);
-      neumaier(cs[1], cc[1], (double)v.y);
-    }
-    for (int j = 0; j < 2; ++j) {
-      neumaier(S[j], SC[j], cs[j]);
-      CC[j] += cc[j];
-    }
-  }
-  partial[4 * b + 0] = S[0];
-  partial[4 * b + 1] = S[1];
-  partial[4 * b + 2] = SC[0] + CC[0];
-  partial[4 * b + 3] = SC[1] + CC[1];
+// Knuth's TwoSum: s + e equals a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bv = s - a;
+  e = (a - (s - bv)) + (b - bv);
 }
 
-// Chunk partials [b][chunk][4] of the generated kernel -> per-bitstring partial.
+// Compensated butterfly over the 64 lanes of a wavefront (partners lane ^ 1,
+// ^ 2, ..., ^ 32).  Every lane ends with the same (sum, comp); sum + comp is
+// the total of the 64 inputs.  Addition is commutative and TwoSum's error is
+// exact, so partners compute identical values and the order is fixed.
+__device__ __forceinline__ void wave_sum(double& s, double& c) {
+  for (int m = 1; m < 64; m <<= 1) {
+    const double so = __shfl_xor(s, m);
+    const double co = __shfl_xor(c, m);
+    double t, e;
+    two_sum(s, so, t, e);
+    s = t;
+    c = (c + co) + e;
+  }
+}
+
+// Slice sums, one order for every path: slices are taken in chunks of 64
+// consecutive s (the last chunk padded with zeros); a chunk is summed by the
+// compensated butterfly into (sum_c, comp_c); the chunk sums are then added in
+// ascending chunk order with Neumaier's compensation and the chunk
+// compensations are accumulated alongside.  One 64-lane block per bitstring.
+template <typename R>
+__global__ void __launch_bounds__(64) reduce_kernel(const cx<R>* __restrict__ res, int n_bs, uint64_t n_s,
+                                                    double* __restrict__ partial) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
+  for (uint64_t c0 = 0; c0 < n_s; c0 += 64) {
+    double v[2] = {0, 0}, c[2] = {0, 0};
+    if (c0 + lane < n_s) {
+      cx<R> x = res[(c0 + lane) * (uint64_t)n_bs + b];
+      v[0] = (double)x.x;
+      v[1] = (double)x.y;
+    }
+    for (int k = 0; k < 2; ++k) {
+      wave_sum(v[k], c[k]);
+      neumaier(S[k], SC[k], v[k]);
+      CC[k] += c[k];
+    }
+  }
+  if (lane == 0) {
+    partial[4 * b + 0] = S[0];
+    partial[4 * b + 1] = S[1];
+    partial[4 * b + 2] = SC[0] + CC[0];
+    partial[4 * b + 3] = SC[1] + CC[1];
+  }
+}
+
+// Chunk partials [b][chunk][4] written by the generated kernel (same chunk
+// sums as above) -> per-bitstring partial.
 __global__ void combine_kernel(const double* __restrict__ chunks, int n_bs, uint64_t per_bs,
                                double* __restrict__ partial) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,37 +291,39 @@ __global__ void combine_kernel(const double* __restrict__ chunks, int n_bs, uint
   partial[4 * b + 3] = SC[1] + CC[1];
 }
 
-// d alpha / d theta_j per bitstring: the values of every gradient slot of
-// parameter j (slots ascending) are summed over the slices in the same
-// two-level compensated order as the amplitudes.
+// d alpha / d theta_j per bitstring: every gradient slot of parameter j
+// (slots ascending) is summed over the slices in the order used for the
+// amplitudes.  One 64-lane block per (bitstring, parameter).
 template <typename R>
-__global__ void grad_reduce_kernel(const cx<R>* __restrict__ gres, int n_bs, uint64_t n_s, int n_slots,
-                                   const int* __restrict__ slot_param, int n_params, double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_bs * n_params) return;
+__global__ void __launch_bounds__(64) grad_reduce_kernel(const cx<R>* __restrict__ gres, int n_bs, uint64_t n_s,
+                                                         int n_slots, const int* __restrict__ slot_param,
+                                                         int n_params, double* __restrict__ out) {
+  const int t = blockIdx.x, lane = threadIdx.x;
   const int b = t / n_params, j = t - b * n_params;
   double S[2] = {0, 0}, SC[2] = {0, 0}, CC[2] = {0, 0};
   for (int g = 0; g < n_slots; ++g) {
     if (slot_param[g] != j) continue;
     const cx<R>* base = gres + (uint64_t)g * n_s * (uint64_t)n_bs;
     for (uint64_t c0 = 0; c0 < n_s; c0 += 64) {
-      const uint64_t c1 = c0 + 64 < n_s ? c0 + 64 : n_s;
-      double cs[2] = {0, 0}, cc[2] = {0, 0};
-      for (uint64_t s = c0; s < c1; ++s) {
-        cx<R> v = base[s * (uint64_t)n_bs + b];
-        neumaier(cs[0], cc[0], (double)v.x);
-        neumaier(cs[1], cc[1], (double)v.y);
+      double v[2] = {0, 0}, c[2] = {0, 0};
+      if (c0 + lane < n_s) {
+        cx<R> x = base[(c0 + lane) * (uint64_t)n_bs + b];
+        v[0] = (double)x.x;
+        v[1] = (double)x.y;
       }
       for (int k = 0; k < 2; ++k) {
-        neumaier(S[k], SC[k], cs[k]);
-        CC[k] += cc[k];
+        wave_sum(v[k], c[k]);
+        neumaier(S[k], SC[k], v[k]);
+        CC[k] += c[k];
       }
     }
   }
-  out[4 * (size_t)t + 0] = S[0];
-  out[4 * (size_t)t + 1] = S[1];
-  out[4 * (size_t)t + 2] = SC[0] + CC[0];
-  out[4 * (size_t)t + 3] = SC[1] + CC[1];
+  if (lane == 0) {
+    out[4 * (size_t)t + 0] = S[0];
+    out[4 * (size_t)t + 1] = S[1];
+    out[4 * (size_t)t + 2] = SC[0] + CC[0];
+    out[4 * (size_t)t + 3] = SC[1] + CC[1];
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -307,8 +340,19 @@ int dev_query(int& n_cu, size_t& max_lds, std::string& err) {
   return 0;
 }
 
-int dev_upload(const Program& prog, const std::vector<char>& code, DevProgram& dp, std::string& err) {
+int dev_upload(const Program& prog, const std::vector<char>& code, const WideProgram* wide, DevProgram& dp,
+               std::string& err) {
   if (dp.steps) return 0;
+  if (wide) {
+    HIP_OK(hipMalloc(&dp.wide.steps, std::max<size_t>(wide->steps.size() * sizeof(int32_t), 16)));
+    HIP_OK(hipMalloc(&dp.wide.ops, std::max<size_t>(wide->ops.size() * sizeof(int32_t), 16)));
+    if (!wide->steps.empty())
+      HIP_OK(hipMemcpy(dp.wide.steps, wide->steps.data(), wide->steps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!wide->ops.empty())
+      HIP_OK(hipMemcpy(dp.wide.ops, wide->ops.data(), wide->ops.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    dp.wide.n_steps = wide->n_steps;
+    dp.wide.host_steps = wide->steps;
+  }
   if (!code.empty()) {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
@@ -359,6 +403,8 @@ void dev_free(DevProgram& dp) {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (dp.module) (void)hipModuleUnload((hipModule_t)dp.module);
+  if (dp.wide.steps) (void)hipFree(dp.wide.steps);
+  if (dp.wide.ops) (void)hipFree(dp.wide.ops);
   dp = DevProgram();
 }
 
@@ -370,7 +416,8 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   size_t lds = (size_t)prog.item_elems * kLanes * el;
   if (cfg.generated) lds = 0;
   // 64 bytes of headroom for the kernel's static LDS (the work-queue slot)
-  ws.use_lds = (!cfg.generated && lds + 64 <= dp.max_lds) ? 1 : 0;
+  if (cfg.wide) lds = 0;
+  ws.use_lds = (!cfg.generated && !cfg.wide && lds + 64 <= dp.max_lds) ? 1 : 0;
   ws.lds_bytes = ws.use_lds ? lds : 0;
   int per_cu = 8;
   if (ws.use_lds) {
@@ -407,7 +454,20 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   ws.chunks = off;
   off = align256(off + (size_t)std::max<uint64_t>(n_chunks, 1) * 4 * sizeof(double));
   ws.scratch = off;
-  if (!cfg.generated && !ws.use_lds) off = align256(off + (size_t)ws.grid * prog.item_elems * kLanes * el);
+  ws.wide_groups = 0;
+  if (cfg.wide) {
+    const uint64_t groups = std::max<uint64_t>(n_chunks, 1);
+    const size_t per_group = (size_t)prog.item_elems * kLanes * el;
+    uint64_t fit = cfg.wide_budget / std::max<size_t>(per_group, 1);
+    if (fit < 1) {
+      err = "one 64-item group needs " + std::to_string(per_group) + " bytes of item memory, over the budget";
+      return -5;
+    }
+    ws.wide_groups = (int)std::min<uint64_t>(groups, std::min<uint64_t>(fit, 65535));
+    off = align256(off + (size_t)ws.wide_groups * per_group);
+  } else if (!cfg.generated && !ws.use_lds) {
+    off = align256(off + (size_t)ws.grid * prog.item_elems * kLanes * el);
+  }
   ws.total = off;
   (void)err;
   return 0;
@@ -436,7 +496,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
   auto grad_reduce = [&]() {
     if (!grads) return;
     const int n = cfg.n_bs * cfg.n_params;
-    hipLaunchKernelGGL(grad_reduce_kernel<R>, dim3((n + 63) / 64), dim3(64), 0, stream, gres, cfg.n_bs, cfg.n_s,
+    hipLaunchKernelGGL(grad_reduce_kernel<R>, dim3(n), dim3(64), 0, stream, gres, cfg.n_bs, cfg.n_s,
                        prog.n_grad_slots, (const int*)dp.slot_param, cfg.n_params, d_grad_partial);
   };
   mark(0);
@@ -444,18 +504,37 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
   if (!cfg.generated || n_items == 0)
     hipLaunchKernelGGL(prologue_kernel<R>, dim3(1), dim3(256), 0, stream, (const double*)dp.raw, (const int*)dp.rawp,
                        (const int*)dp.rawb, (const int*)dp.rawd, prog.n_raw, d_params, (const DevStep*)dp.steps,
-                       dp.n_const_steps, (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs, cfg.n_qubits, packed,
-                       counter);
+                       cfg.wide ? 0 : dp.n_const_steps, (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs,
+                       cfg.n_qubits, packed, counter);
+  if (cfg.wide && wide_launch_steps<R>(dp.wide, 0, 0, cst, nullptr, 0, packed, cfg.n_bs, cfg.s_begin, cfg.n_s,
+                                       n_items, res, gres, true, stream)) {
+    err = "wide constant steps: launch failed";
+    return -6;
+  }
   mark(1);
   if (n_items == 0) {
     mark(2);
-    hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
     grad_reduce();
     mark(3);
     HIP_OK(hipGetLastError());
     return 0;
   }
-  if (cfg.generated) {
+  if (cfg.wide) {
+    const uint64_t n_groups = (n_items + kLanes - 1) / kLanes;
+    for (uint64_t g0 = 0; g0 < n_groups; g0 += (uint64_t)ws.wide_groups) {
+      const int ng = (int)std::min<uint64_t>((uint64_t)ws.wide_groups, n_groups - g0);
+      if (wide_launch_steps<R>(dp.wide, (int)g0, ng, cst, scr, (uint64_t)prog.item_elems, packed, cfg.n_bs,
+                               cfg.s_begin, cfg.n_s, n_items, res, gres, false, stream)) {
+        err = "wide steps: launch failed";
+        return -6;
+      }
+    }
+    mark(2);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    grad_reduce();
+    mark(3);
+  } else if (cfg.generated) {
     const uint64_t n_blocks = (n_items + kLanes - 1) / kLanes;
     const uint64_t per_bs = cfg.n_s / kLanes;
     // With one block per bitstring the block partial is the final partial.
@@ -474,7 +553,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
                                  args, nullptr));
     mark(2);
     if (!ws.fused)
-      hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+      hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
     else if (per_bs > 1)
       hipLaunchKernelGGL(combine_kernel, red_grid, dim3(64), 0, stream, chunks, cfg.n_bs, per_bs, d_partial);
     grad_reduce();
@@ -490,7 +569,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
                          first, dp.n_steps, (const DevLeaf*)dp.leaves, (const uint32_t*)dp.optab, cst, packed,
                          cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res, gres, scr, prog.item_elems);
     mark(2);
-    hipLaunchKernelGGL(reduce_kernel<R>, red_grid, dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
     grad_reduce();
     mark(3);
   }
@@ -504,6 +583,10 @@ int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, con
             const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream_, double* d_partial,
             double* d_grad_partial, void* const* events, std::string& err) {
   if (cfg.n_bs == 0) return 0;
+  if (cfg.wide && !dp.wide.steps) {
+    err = "wide engine descriptors not loaded";
+    return -6;
+  }
   if (cfg.generated && !dp.chain_fn) {
     err = "generated kernel not loaded";
     return -6;

@@ -143,9 +143,26 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                      Program& prog, std::string& err, int& code, bool gradient = false);
 
+// ------------------------------------------------------------ wide engine
+// Descriptors for plans whose tensors are too large for registers or LDS.
+// Item tensors live in HBM as [element][64 items] rows; every step is one
+// kernel.  Leaves are read in place from the gate tables.
+enum WideOpKind { WOP_ITEM = 0, WOP_CONST = 1, WOP_LEAF = 2 };
+constexpr int kWideOpInts = 64;  // per operand: see encode_wide
+constexpr int kWideMaxOut = 32, kWideMaxSum = 16;
+
+struct WideProgram {
+  std::vector<int32_t> steps;  // 8 ints per step: kind, out, r, ns, m, grad_slot, op_begin, is_const
+  std::vector<int32_t> ops;    // kWideOpInts ints per operand
+  int n_steps = 0;
+};
+
+// Builds the wide descriptors; false (with err) if a step exceeds the limits.
+bool encode_wide(const Program& prog, WideProgram& wide, std::string& err);
+
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.
-std::string generate_chain_source(const Program& prog, int prec);
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits);
 // hiprtc compilation of `src` for gfx950 into a code object.
 bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
 

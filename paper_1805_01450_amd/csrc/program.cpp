@@ -15,6 +15,7 @@
 // Tensors that depend on no fixed variable are the same for every item and
 // are computed once per call ("constant" steps).
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 
@@ -276,9 +277,10 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   };
   // Append a product-sum step; returns the index of the new tensor (or -1
   // for FINAL / GRAD steps, which write outside item memory).
-  auto emit = [&](int kind, const std::vector<int>& in, const std::vector<int>& out_vars,
-                  const std::vector<int>& sum_vars, bool make_const, int grad_slot, int extra_const,
-                  int n_extra) -> int {
+  std::vector<int> elim_created;  // every tensor made by an ELIM step, in creation order
+  auto emit_one = [&](int kind, const std::vector<int>& in, const std::vector<int>& out_vars,
+                      const std::vector<int>& sum_vars, bool make_const, int grad_slot, int extra_const,
+                      int n_extra) -> int {
     Step st;
     st.kind = kind;
     st.out_vars = out_vars;
@@ -313,6 +315,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       for (int i : in) nt.grad |= T[i].grad;
       T.push_back(nt);
       id = (int)T.size() - 1;
+      elim_created.push_back(id);
     }
     // the output buffer is placed after inputs are read: a step's inputs and
     // output never share memory because their lifetimes overlap at the step
@@ -332,10 +335,32 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     return id;
   };
 
+  // A step that sums many variables into a small output has little
+  // parallelism across output elements; it is split into a partial-sum step
+  // that keeps some summed variables as outputs and a plain sum over them
+  // (repeated while the remaining sum is still large).
+  constexpr int kSplitSum = 8, kKeepSum = 6, kSplitRank = 14;
+  std::function<int(int, const std::vector<int>&, const std::vector<int>&, const std::vector<int>&, bool, int, int,
+                    int)>
+      emit;
+  emit = [&](int kind, const std::vector<int>& in, const std::vector<int>& out_vars, const std::vector<int>& sum_vars,
+             bool make_const, int grad_slot, int extra_const, int n_extra) -> int {
+    const int ns = (int)sum_vars.size(), r = (int)out_vars.size();
+    if (ns <= kSplitSum || in.empty()) return emit_one(kind, in, out_vars, sum_vars, make_const, grad_slot,
+                                                       extra_const, n_extra);
+    const int h = std::max(1, std::min(ns - kKeepSum, std::max(1, kSplitRank - r)));
+    std::vector<int> keep(sum_vars.end() - h, sum_vars.end());
+    std::vector<int> inner(sum_vars.begin(), sum_vars.end() - h);
+    std::vector<int> part_out = out_vars;
+    part_out.insert(part_out.end(), keep.begin(), keep.end());
+    int part = emit_one(ST_ELIM, in, part_out, inner, make_const, -1, 0, 0);
+    return emit(kind, {part}, out_vars, keep, make_const, grad_slot, extra_const, n_extra);
+  };
+
   // ---- forward: variable elimination along the order
   std::vector<char> done(nvars, 0);
   int n_two = 0;
-  std::vector<int> fwd_steps;  // tensor ids produced by forward ELIM steps, in order
+
   for (int v : order) {
     if (done[v]) continue;
     std::vector<int> tv;
@@ -365,8 +390,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
     bool all_const = !gradient;
     for (int i : tv) all_const = all_const && T[i].is_const;
-    int id = emit(ST_ELIM, tv, out, S, all_const, -1, 0, 0);
-    fwd_steps.push_back(id);
+    emit(ST_ELIM, tv, out, S, all_const, -1, 0, 0);
     for (int i : tv) {
       for (int u : T[i].vars) count[u]--;
       T[i].alive = 0;
@@ -387,6 +411,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     rest.push_back((int)i);
   }
   emit(ST_FINAL, rest, {}, {}, false, -1, two_tab, n_two);
+  const std::vector<int> fwd_steps = elim_created;  // forward tensors, creation order
 
   // ---- reverse mode (gradient programs)
   if (gradient) {

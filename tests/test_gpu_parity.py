@@ -41,7 +41,7 @@ def cuda():
     return torch
 
 
-ENGINES = [q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED]
+ENGINES = [q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED, q.QGM_ENGINE_WIDE]
 
 
 def run(text, bits, k=0, prec=q.QGM_C128, params=None, seed=0, engine=q.QGM_ENGINE_AUTO):
@@ -375,3 +375,67 @@ def test_autograd_function_gradcheck(cuda):
     shift = oracle.sv_gradient_shift(text, bits[0], th)
     want = 2.0 * np.real(np.conj(ref) * shift)
     assert np.max(np.abs(theta.grad.numpy() - want)) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def config4():
+    """7x7x30 with every T replaced by RZ(theta), k = 6 (64 slices = one group)."""
+    text, th, bits = _rz_case(7, 30, 0)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=2.0)
+    return text, th, bits[0], c, sl, order
+
+
+def test_config4_7x7x30_slices_vs_oracle(config4):
+    text, th, x, c, sl, order = config4
+    p = q.Plan(c, sl, order)
+    st = p.stats()
+    note("7x7x30 RZ k=6 stats", {k: st[k] for k in ("engine", "max_rank", "item_elems", "n_steps")})
+    assert st["engine"] == q.QGM_ENGINE_WIDE
+    net = oracle.build_network(text, th)
+    for s in (0, 37):
+        part = p.amplitudes_range([x], th, s, s + 1)[0]
+        got = part[0] + part[2] + 1j * (part[1] + part[3])
+        ref = oracle.ve_slice_values(text, x, sliced=sl, params=th, slices=[s], net=net)[0]
+        note("slice", s, "device", got, "oracle", ref)
+        assert abs(got - ref) <= 1e-12 * max(abs(ref), 2.0 ** -24.5)
+
+
+def test_config4_gradient_vs_device_shift_and_fd(config4):
+    """Adjoint d alpha / d theta for all angles vs the parameter-shift rule and
+    central differences (h = 1e-4, FP64), both evaluated on the device path
+    whose slices are pinned to the oracle above."""
+    text, th, x, c, sl, order = config4
+    g = q.Plan(c, sl, order, gradient=True)
+    note("7x7x30 gradient stats", {k: g.stats()[k] for k in ("engine", "item_elems", "n_steps")})
+    amp, grad = g.amplitude_grad(x, th)
+    p = q.Plan(c, sl, order)
+    assert abs(p.amplitudes([x], th)[0] - amp) <= 1e-12 * abs(amp)
+    scale = max(abs(amp), 2.0 ** -24.5)
+    rng = np.random.default_rng(0)
+    subset = sorted(rng.choice(len(th), 16, replace=False))
+    shift = []
+    for j in range(len(th)):
+        t2 = th.copy()
+        t2[j] += np.pi
+        shift.append(0.5 * p.amplitudes([x], t2)[0])
+    shift = np.array(shift)
+    note("params", len(th), "max |adjoint - shift| / scale", np.max(np.abs(grad - shift)) / scale)
+    assert np.max(np.abs(grad - shift)) / scale <= 1e-11
+    fd = oracle.fd_gradient(lambda pp: p.amplitudes([x], pp)[0], th, h=1e-4, which=subset)
+    assert np.max(np.abs(grad[subset] - fd)) / scale <= 1e-7
+
+
+def test_wide_engine_multiple_groups_and_passes(config2):
+    """640 bitstrings x 2^3 slices = 80 groups of 64 items, in passes of 7 groups."""
+    text, _, _ = config2
+    bits = random_bitstrings(25, 640, 4242)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2)
+    gen = q.Plan(c, sl, order, engine=q.QGM_ENGINE_GENERATED).amplitudes(bits)
+    st = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE).stats()
+    cap = 7 * st["item_elems"] * 64 * 16 + 100000
+    wide = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE, workspace_cap=cap).amplitudes(bits)
+    assert np.max(np.abs(wide - gen) / np.maximum(np.abs(gen), 2.0 ** -12.5)) <= C128_TOL
+    ref = np.array([oracle.ve_amplitude(text, bits[i]) for i in range(0, 640, 80)])
+    assert nerr(wide[::80], ref, 25).max() <= C128_TOL

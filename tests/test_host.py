@@ -129,8 +129,21 @@ def test_plan_stats():
     assert st["flops_item"] > 0 and st["item_elems"] >= 1
 
 
-def test_large_rank_step_refused_by_item_program():
+def test_large_rank_plan_runs_on_wide_engine_only():
     c, sl, order = _plan(7, 30, 0, 5)
-    with pytest.raises(q.QgmError) as e:
-        q.Plan(c, sl, order)
-    assert e.value.status in (-7,)
+    st = q.Plan(c, sl, order).stats()
+    assert st["engine"] == q.QGM_ENGINE_WIDE and st["max_rank"] > 16
+    for eng in (q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED):
+        with pytest.raises(q.QgmError) as e:
+            q.Plan(c, sl, order, engine=eng)
+        assert e.value.status == -7
+
+
+def test_gradient_plans_split_large_sums():
+    """Reverse steps that sum many variables are split (no step sums > 8)."""
+    text = generate_circuit(7, 30, 0, rz=True)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=1.0)
+    p = q.Plan(c, sl, order, gradient=True)
+    assert p.stats()["engine"] == q.QGM_ENGINE_WIDE
+    assert p.stats()["n_steps"] > q.Plan(c, sl, order).stats()["n_steps"]
