@@ -354,7 +354,9 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     std::vector<int> part_out = out_vars;
     part_out.insert(part_out.end(), keep.begin(), keep.end());
     int part = emit_one(ST_ELIM, in, part_out, inner, make_const, -1, 0, 0);
-    return emit(kind, {part}, out_vars, keep, make_const, grad_slot, extra_const, n_extra);
+    int id = emit(kind, {part}, out_vars, keep, make_const, grad_slot, extra_const, n_extra);
+    T[part].alive = 0;  // consumed by the sum step just emitted
+    return id;
   };
 
   // ---- forward: variable elimination along the order

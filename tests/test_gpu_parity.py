@@ -439,3 +439,26 @@ def test_wide_engine_multiple_groups_and_passes(config2):
     assert np.max(np.abs(wide - gen) / np.maximum(np.abs(gen), 2.0 ** -12.5)) <= C128_TOL
     ref = np.array([oracle.ve_amplitude(text, bits[i]) for i in range(0, 640, 80)])
     assert nerr(wide[::80], ref, 25).max() <= C128_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [(q.QGM_C128, C128_TOL), (q.QGM_C64, C64_TOL)])
+def test_config5_8x8x40_slices_vs_oracle(prec, tol):
+    """8x8x40, k = 20 (max rank <= 22): single slices through the wide engine
+    against the oracle's elimination of the same slice.  Slice values are
+    normalised by the typical slice size 2^{-N/2} / 2^{k/2}."""
+    text = generate_circuit(8, 40, 0)
+    x = random_bitstrings(64, 1, 1000)[0]
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=20, time_budget_s=5.0)
+    p = q.Plan(c, sl, order, prec=prec)
+    st = p.stats()
+    note("8x8x40 k=20 prec", prec, {k: st[k] for k in ("engine", "max_rank", "item_elems", "n_steps")})
+    assert st["engine"] == q.QGM_ENGINE_WIDE
+    net = oracle.build_network(text)
+    scale = 2.0 ** -32 / 2.0 ** 10
+    for s in (0, 12345, (1 << 20) - 1):
+        part = p.amplitudes_range([x], None, s, s + 1)[0]
+        got = part[0] + part[2] + 1j * (part[1] + part[3])
+        ref = oracle.ve_slice_values(text, x, sliced=sl, slices=[s], net=net)[0]
+        note("slice", s, "device", got, "oracle", ref)
+        assert abs(got - ref) / max(abs(ref), scale) <= tol

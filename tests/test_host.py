@@ -147,3 +147,12 @@ def test_gradient_plans_split_large_sums():
     p = q.Plan(c, sl, order, gradient=True)
     assert p.stats()["engine"] == q.QGM_ENGINE_WIDE
     assert p.stats()["n_steps"] > q.Plan(c, sl, order).stats()["n_steps"]
+
+
+@pytest.mark.parametrize("k", [13, 20])
+def test_8x8x40_plans_compile(k):
+    c = q.Circuit(generate_circuit(8, 40, 0))
+    sl, order = c.plan_slices(k_req=k, time_budget_s=2.0)
+    for grad in (False,):
+        st = q.Plan(c, sl, order, prec=q.QGM_C64, gradient=grad).stats()
+        assert st["engine"] == q.QGM_ENGINE_WIDE and st["k"] == k
