@@ -151,8 +151,10 @@ def main():
             if name == "c64":
                 raise
             continue  # comparison engine cannot run this plan (e.g. interpreter on large ranks)
+        waves = plan.autotune(n_bs, n_s) if plan.stats()["engine"] == q.QGM_ENGINE_GENERATED else 1
         r = timed(q, torch, plan, d_bits, d_part, n_s, args.steps, args.warmup, stream)
         r["plan"] = plan
+        r["waves"] = waves
         results[name] = r
 
     import oracle
@@ -199,6 +201,7 @@ def main():
                       "kernel_ms": r["ms_chain"], "bytes_per_launch": bytes_launch,
                       "flops_per_launch": flops_launch, "tflops": achieved}),
         "engine": {1: "interpreter", 2: "generated", 3: "wide"}[st["engine"]],
+        "waves_per_block": r["waves"],
         "timing": "timed region = one HIP graph replay of `steps` captured runs (events on the launch stream); "
                   "kernel_ms = HIP events around each kernel over the warm-up runs",
         "gpu_ms_per_step": r["gpu_ms_step"],

@@ -99,7 +99,7 @@ typedef struct {
                              one trip to memory, at 8 B per element */
   double cost;            /* sum over eliminations of 2^deg(v) (Section "Variable elimination") */
   int32_t engine;         /* engine the plan runs with (INTERPRETER, GENERATED or WIDE) */
-  int32_t pad0;
+  int32_t waves;          /* GENERATED: wavefronts per block the item tree is cut across */
   double compile_s;       /* seconds spent generating and compiling the plan's kernel */
 } qgm_stats;
 
@@ -193,6 +193,18 @@ qgm_status qgm_graph_create(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_
                             double* d_partial, int32_t repeat, qgm_graph** out);
 qgm_status qgm_graph_launch(qgm_graph* g, void* hip_stream);
 void qgm_graph_free(qgm_graph* g);
+
+/* Autotuner of the GENERATED engine: the item tree of a plan can be cut
+ * across 1, 2, 4 or 8 wavefronts of a block (the cut is the launch shape of
+ * the generated kernel).  Each feasible variant is generated, compiled,
+ * timed on the device for a batch of n_bs bitstrings x n_slices slices (all
+ * bits 0, angles 0, 3 warm-up and 10 timed runs with HIP events on `stream`),
+ * and the fastest one is kept for the plan.  *waves_out gets the chosen
+ * count.  Other engines: no-op, *waves_out = 1.  The workspace must hold
+ * qgm_workspace_size(p, n_bs, n_slices) bytes; its contents are overwritten.
+ * Errors: QGM_E_ARG, QGM_E_WORKSPACE, QGM_E_HIP. */
+qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void* d_workspace, size_t ws_bytes,
+                             void* hip_stream, int32_t* waves_out);
 
 /* Kernel durations of the runs made since the last reset by a plan created
  * with opts.profile = 1: ms[0] prologue (tables, constant steps), ms[1]

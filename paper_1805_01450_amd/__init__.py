@@ -188,6 +188,13 @@ def qgm_plan_timing(p, reset: bool = True):
     return (ms[0], ms[1], ms[2]), n.value
 
 
+def qgm_plan_autotune(p, n_bs: int, n_slices: int, workspace, stream=None) -> int:
+    """Time the generated kernel's wavefront cuts on the device; keeps the fastest. Returns the wave count."""
+    w = C.c_int32()
+    check(lib.qgm_plan_autotune(p, n_bs, n_slices, _ptr(workspace), workspace.numel(), _stream(stream), C.byref(w)))
+    return w.value
+
+
 def qgm_plan_free(p) -> None:
     lib.qgm_plan_free(p)
 
@@ -271,6 +278,10 @@ class Plan:
         bs = np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8))
         ws = self.workspace(bs.shape[0], s_end - s_begin)
         return qgm_amplitudes_range(self.h, bs, params, s_begin, s_end, ws, stream)
+
+    def autotune(self, n_bs: int, n_slices: int | None = None, stream=None) -> int:
+        n_slices = (1 << self.k) if n_slices is None else n_slices
+        return qgm_plan_autotune(self.h, n_bs, n_slices, self.workspace(n_bs, n_slices), stream)
 
     def amplitude_grad(self, bitstring, params, stream=None):
         """(alpha, d alpha / d theta) for one bitstring; needs gradient=True."""

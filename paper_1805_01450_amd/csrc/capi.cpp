@@ -299,7 +299,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   }
   if (want_gen) {
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits);
+    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits, &p->dev.chain_waves);
     std::string jerr;
     bool ok = jit_compile(src, "qgm_chain.hip", p->code, jerr);
     if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
@@ -343,6 +343,7 @@ qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
   s.cost = p->cost;
   s.engine = p->engine;
   s.compile_s = p->compile_s;
+  s.waves = p->dev.chain_waves;
   *out = s;
   return QGM_OK;
 }
@@ -612,6 +613,95 @@ qgm_status qgm_amplitude_grad(qgm_plan* p, const uint8_t* bitstring, const doubl
     dalpha[2 * j + 1] = gpart[4 * j + 1] + gpart[4 * j + 3];
   }
   return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void* d_ws, size_t ws_bytes,
+                             void* stream_, int32_t* waves_out) {
+  GUARD_BEGIN
+  if (!p || !waves_out || n_bs < 1 || n_slices < 1 || !d_ws) return fail(QGM_E_ARG, "bad argument");
+  *waves_out = 1;
+  if (p->engine != QGM_ENGINE_GENERATED) return QGM_OK;
+  if (n_slices > (1ull << p->sliced.size())) return fail(QGM_E_ARG, "more slices than the plan has");
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(p->mu);
+  qgm_status s = ensure_device(p);
+  if (s) return s;
+  WsLayout ws;
+  LaunchCfg cfg;
+  if ((s = layout_for(p, n_bs, n_slices, ws, cfg))) return s;
+  Staging st = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0);
+  if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace smaller than qgm_workspace_size");
+  char* base = (char*)d_ws;
+  if (hipMemsetAsync(base + st.bits, 0, st.partial - st.bits, stream) != hipSuccess)
+    return fail(QGM_E_HIP, "hipMemsetAsync failed");
+  const uint8_t* d_bits = (const uint8_t*)(base + st.bits);
+  const double* d_params = p->net.n_params > 0 ? (const double*)(base + st.params) : nullptr;
+  double* d_part = (double*)(base + st.partial);
+  double* d_gpart = p->prog.n_grad_slots > 0 ? (double*)(base + st.gpartial) : nullptr;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(QGM_E_HIP, "hipEventCreate failed");
+  struct Variant {
+    std::vector<char> code;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int waves = 1;
+    float ms = 0;
+  };
+  // the current kernel is one candidate
+  Variant best;
+  best.code = p->code;
+  best.mod = (hipModule_t)p->dev.module;
+  best.fn = (hipFunction_t)p->dev.chain_fn;
+  best.waves = p->dev.chain_waves;
+  auto time_current = [&](float& ms) -> qgm_status {
+    std::string err;
+    for (int r = 0; r < 13; ++r) {
+      if (r == 3 && hipEventRecord(e0, stream) != hipSuccess) return fail(QGM_E_HIP, "hipEventRecord failed");
+      int rc = dev_run(p->prog, p->dev, cfg, ws, d_bits, d_params, d_ws, stream, d_part, d_gpart, nullptr, err);
+      if (rc) return fail((qgm_status)rc, err);
+    }
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return fail(QGM_E_HIP, "event timing failed");
+    return QGM_OK;
+  };
+  if ((s = time_current(best.ms))) return s;
+  for (int w : {1, 2, 4, 8}) {
+    if (w == best.waves) continue;
+    int got = 0;
+    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w);
+    if (got != w) continue;  // this cut is not possible for the plan
+    Variant v;
+    std::string jerr;
+    if (!jit_compile(src, "qgm_chain.hip", v.code, jerr)) continue;
+    if (hipModuleLoadData(&v.mod, v.code.data()) != hipSuccess) continue;
+    if (hipModuleGetFunction(&v.fn, v.mod, "qgm_chain") != hipSuccess) {
+      (void)hipModuleUnload(v.mod);
+      continue;
+    }
+    v.waves = w;
+    p->dev.module = v.mod;
+    p->dev.chain_fn = v.fn;
+    p->dev.chain_waves = w;
+    s = time_current(v.ms);
+    if (s || v.ms >= best.ms) {
+      (void)hipModuleUnload(v.mod);
+    } else {
+      if (best.mod) (void)hipModuleUnload(best.mod);
+      best = v;
+    }
+    p->dev.module = best.mod;
+    p->dev.chain_fn = best.fn;
+    p->dev.chain_waves = best.waves;
+    if (s) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->code = best.code;
+  *waves_out = best.waves;
+  return s;
   GUARD_END
 }
 

@@ -35,6 +35,7 @@ struct DevProgram {
   WideDev wide;            // wide engine (empty otherwise)
   void* module = nullptr;  // hipModule_t of the generated chain kernel
   void* chain_fn = nullptr;  // hipFunction_t "qgm_chain"
+  int chain_waves = 1;       // wavefronts per block of the generated kernel
 };
 
 // Precision of the slice contraction: 0 = complex128, 1 = complex64.

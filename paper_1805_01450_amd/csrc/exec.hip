@@ -549,8 +549,8 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
     void* a_part = part;
     int a_fused = ws.fused;
     void* args[] = {&a_raw, &a_par, &a_bits, &a_nq, &a_nbs, &a_sb, &a_ns, &a_ni, &a_res, &a_gres, &a_part, &a_fused};
-    HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes, 1, 1, 0, stream,
-                                 args, nullptr));
+    HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes * dp.chain_waves, 1,
+                                 1, 0, stream, args, nullptr));
     mark(2);
     if (!ws.fused)
       hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);

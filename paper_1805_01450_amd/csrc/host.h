@@ -162,7 +162,10 @@ bool encode_wide(const Program& prog, WideProgram& wide, std::string& err);
 
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits);
+// *waves_out gets the wavefronts per block (the item tree may be cut across
+// several wavefronts that run the same 64 items).
+// force_waves > 0 requests that many wavefronts (0 = cost model).
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0);
 // hiprtc compilation of `src` for gfx950 into a code object.
 bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
 

