@@ -142,7 +142,8 @@ def main():
            "generated": q.QGM_ENGINE_GENERATED}[args.engine]
     runs = [("c64", q.QGM_C64, eng)]
     if not args.no_extra:
-        runs += [("c128", q.QGM_C128, q.QGM_ENGINE_AUTO), ("c64_interp", q.QGM_C64, q.QGM_ENGINE_INTERPRETER)]
+        runs += [("bf16x3", q.QGM_BF16X3, eng), ("c128", q.QGM_C128, q.QGM_ENGINE_AUTO),
+                 ("c64_interp", q.QGM_C64, q.QGM_ENGINE_INTERPRETER)]
     results = {}
     for name, prec, engine in runs:
         try:
@@ -214,6 +215,10 @@ def main():
         line["per_slice_ms"] = per_slice_ms
         line["slices_timed"] = n_items
         line["projected_full_sum_s"] = per_slice_ms * 1e-3 * (1 << k) * n_bs
+    if "bf16x3" in results:
+        line["bf16x3_value"] = n_items / (results["bf16x3"]["wall"] / args.steps)
+        line["amplitude_error_bf16x3"] = nerr(results["bf16x3"]["amps"])
+        line["bf16x3_mfma_frac"] = 0.0
     if "c128" in results:
         line["c128_value"] = n_items / (results["c128"]["wall"] / args.steps)
         line["amplitude_error_c128"] = nerr(results["c128"]["amps"])

@@ -51,8 +51,10 @@ typedef enum {
 } qgm_status;
 
 typedef enum {
-  QGM_C128 = 0, /* complex128 contraction */
-  QGM_C64 = 1   /* complex64 contraction, FP32 accumulation */
+  QGM_C128 = 0,  /* complex128 contraction */
+  QGM_C64 = 1,   /* complex64 contraction, FP32 accumulation */
+  QGM_BF16X3 = 2 /* complex64 storage; every real product from bf16 splits x = xh + xl (round to
+                    nearest even): xh*yh + xh*yl + xl*yh, accumulated in FP32 */
 } qgm_precision;
 
 typedef struct qgm_circuit qgm_circuit;

@@ -15,6 +15,7 @@ from ._lib import DECLARED, LIB_PATH, PlanOpts, QgmError, Stats, VarInfo, check,
 
 QGM_C128 = 0
 QGM_C64 = 1
+QGM_BF16X3 = 2
 QGM_ENGINE_AUTO = 0
 QGM_ENGINE_INTERPRETER = 1
 QGM_ENGINE_GENERATED = 2

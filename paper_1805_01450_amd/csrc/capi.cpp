@@ -248,7 +248,8 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   qgm_plan_opts o{};
   o.prec = QGM_C128;
   if (opts) o = *opts;
-  if (o.prec != QGM_C128 && o.prec != QGM_C64) return fail(QGM_E_UNSUPPORTED, "unknown precision");
+  if (o.prec != QGM_C128 && o.prec != QGM_C64 && o.prec != QGM_BF16X3)
+    return fail(QGM_E_UNSUPPORTED, "unknown precision");
   if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_WIDE) return fail(QGM_E_ARG, "unknown engine");
   auto* p = new qgm_plan();
   p->net = c->net;

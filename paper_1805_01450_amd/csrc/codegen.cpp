@@ -245,12 +245,21 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
   std::ostringstream head, o;
   const char* R = prec == 0 ? "double" : "float";
   const Cut cut = cut_tree(prog, 4, prec == 0 ? 16 : 8, force_waves);
+  // BF16x3: products from bf16 hi/lo splits with FP32 accumulation
+  const std::string mul = prec == 2
+      ? std::string("static __device__ __forceinline__ float bh(float x) { unsigned u = __float_as_uint(x); "
+                    "u += 0x7FFFu + ((u >> 16) & 1u); return __uint_as_float(u & 0xFFFF0000u); }\n"
+                    "static __device__ __forceinline__ float m3(float a, float b) { const float ah = bh(a), "
+                    "al = bh(a - ah), bh_ = bh(b), bl = bh(b - bh_); return ah * bh_ + (ah * bl + al * bh_); }\n"
+                    "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = m3(a.x, b.x) - m3(a.y, b.y); "
+                    "c.y = m3(a.x, b.y) + m3(a.y, b.x); return c; }\n")
+      : std::string("static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = a.x * b.x - a.y * b.y; "
+                    "c.y = a.x * b.y + a.y * b.x; return c; }\n");
   const int W = cut.waves;
   if (waves_out) *waves_out = W;
   head << "typedef " << R << " R;\n"
        << "struct C2 { R x, y; };\n"
-       << "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = a.x * b.x - a.y * b.y; "
-          "c.y = a.x * b.y + a.y * b.x; return c; }\n"
+       << mul
        << "static __device__ __forceinline__ C2 cad(C2 a, C2 b) { C2 c; c.x = a.x + b.x; c.y = a.y + b.y; return c; }\n"
        << "static __device__ __forceinline__ C2 sel(bool t, C2 a1, C2 a0) { C2 c; c.x = t ? a1.x : a0.x; "
           "c.y = t ? a1.y : a0.y; return c; }\n"

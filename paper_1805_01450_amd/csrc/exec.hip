@@ -15,6 +15,7 @@
 #include <cstring>
 #include <string>
 
+#include "bfx3.h"
 #include "exec.h"
 
 namespace qgm {
@@ -422,14 +423,17 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   int per_cu = 8;
   if (ws.use_lds) {
     int occ = 0;
-    hipError_t e = cfg.prec == 0
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<double, true>, 64, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<float, true>, 64, lds);
+    hipError_t e = cfg.prec == 0   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<double, true>, 64, lds)
+                   : cfg.prec == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<bfx3, true>, 64, lds)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, chain_kernel<float, true>, 64, lds);
     if (e != hipSuccess || occ <= 0) occ = (int)std::max<size_t>(1, dp.max_lds / std::max<size_t>(lds, 1));
     per_cu = std::min(occ, 8);
     if (lds > 65536) {
       if (cfg.prec == 0)
         (void)hipFuncSetAttribute((const void*)chain_kernel<double, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      else if (cfg.prec == 2)
+        (void)hipFuncSetAttribute((const void*)chain_kernel<bfx3, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       else
         (void)hipFuncSetAttribute((const void*)chain_kernel<float, true>,
@@ -592,6 +596,9 @@ int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, con
     return -6;
   }
   hipStream_t stream = (hipStream_t)stream_;
+  if (cfg.prec == 2)
+    return run_typed<bfx3>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, d_grad_partial, events,
+                           err);
   if (cfg.prec == 0)
     return run_typed<double>(prog, dp, cfg, ws, d_bits, d_params, (char*)d_ws, stream, d_partial, d_grad_partial,
                              events, err);

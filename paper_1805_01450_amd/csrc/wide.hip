@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "bfx3.h"
 #include "exec.h"
 
 namespace qgm {
@@ -178,6 +179,8 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
 
 template int wide_launch_steps<float>(const WideDev&, int, int, const void*, void*, uint64_t, const uint64_t*, int,
                                       uint64_t, uint64_t, uint64_t, void*, void*, bool, hipStream_t);
+template int wide_launch_steps<bfx3>(const WideDev&, int, int, const void*, void*, uint64_t, const uint64_t*, int,
+                                     uint64_t, uint64_t, uint64_t, void*, void*, bool, hipStream_t);
 template int wide_launch_steps<double>(const WideDev&, int, int, const void*, void*, uint64_t, const uint64_t*, int,
                                        uint64_t, uint64_t, uint64_t, void*, void*, bool, hipStream_t);
 

@@ -21,6 +21,11 @@ pytestmark = pytest.mark.gpu
 
 C128_TOL = 1e-12
 C64_TOL = 2e-4
+# BF16x3: each real product keeps ~16 significant bits (x = xh + xl with the
+# xl*yl term dropped): relative error <= ~3 * 2^-17 per product; over a few
+# hundred dependent operations (worst-case linear growth) and the slice-sum
+# cancellation 2^{k/2} this bounds the normalised amplitude error by ~2e-2.
+BF16X3_TOL = 2e-2
 
 
 def nerr(a, ref, n_qubits):
@@ -477,3 +482,16 @@ def test_autotune_keeps_results(config2):
     for w in (2, 4):
         # every forced cut that the tree allows gives the same amplitudes
         pass
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_bf16x3_config2(config2, engine):
+    text, bits, ref = config2
+    note("BF16x3 5x5x20 k=6 engine", engine)
+    got, p = run(text, bits, k=6, prec=q.QGM_BF16X3, engine=engine)
+    e = nerr(got, ref, 25)
+    c64, _ = run(text, bits, k=6, prec=q.QGM_C64, engine=engine)
+    e64 = nerr(c64, ref, 25)
+    note("max normalised error bf16x3", e.max(), "c64", e64.max())
+    assert e.max() <= BF16X3_TOL
+    assert e.max() > e64.max()  # the split products are coarser than FP32 products
