@@ -37,6 +37,8 @@ struct qgm_plan {
   int engine = QGM_ENGINE_INTERPRETER;  // engine in use
   std::vector<char> code;                // generated kernel code object (engine GENERATED)
   WideProgram wide;                      // descriptors (engine WIDE)
+  std::vector<char> wide_code;           // generated per-step kernels (engine WIDE)
+  std::vector<WideKernel> wide_kernels;
   double compile_s = 0;
   qgm_plan_opts opts;
   double cost = 0;
@@ -93,7 +95,8 @@ Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool g
 
 qgm_status ensure_device(qgm_plan* p) {
   std::string err;
-  int rc = dev_upload(p->prog, p->code, p->engine == QGM_ENGINE_WIDE ? &p->wide : nullptr, p->dev, err);
+  int rc = dev_upload(p->prog, p->code, p->engine == QGM_ENGINE_WIDE ? &p->wide : nullptr, p->dev, err,
+                      &p->wide_code, &p->wide_kernels);
   if (rc) return fail((qgm_status)rc, err);
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->dev.device)
@@ -297,6 +300,17 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     }
     p->engine = QGM_ENGINE_WIDE;
     want_gen = false;
+    // per-step generated kernels; the prebuilt step kernel stays the fallback
+    if (!std::getenv("QGM_WIDE_PREBUILT")) {
+      auto t0 = std::chrono::steady_clock::now();
+      std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels);
+      std::string jerr;
+      if (!jit_compile(src, "qgm_wide.hip", p->wide_code, jerr)) {
+        p->wide_code.clear();
+        p->wide_kernels.clear();
+      }
+      p->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
   }
   if (want_gen) {
     auto t0 = std::chrono::steady_clock::now();

@@ -16,6 +16,16 @@ struct WideDev {
   void* ops = nullptr;
   int n_steps = 0;
   std::vector<int32_t> host_steps;
+  void* module = nullptr;                 // generated per-step kernels (hipModule_t), or null
+  std::vector<void*> fn;                  // per step: hipFunction_t or null (prebuilt kernel)
+  std::vector<unsigned long long> tiles;  // per step: wavefront tiles of the generated kernel
+  // constant steps: runs of small steps in one single-block launch (indices
+  // in const_list[first, first + count)), large steps alone (first = step)
+  struct ConstLaunch {
+    int block, first, count;
+  };
+  std::vector<ConstLaunch> const_plan;
+  void* const_list = nullptr;
 };
 
 // Device-resident copy of a compiled program (owned by a plan).
@@ -64,7 +74,8 @@ struct WsLayout {
 // Uploads the program tables and, when `code` is not empty, loads the
 // generated kernel's code object on the current device.
 int dev_upload(const Program& prog, const std::vector<char>& code, const WideProgram* wide, DevProgram& dp,
-               std::string& err);
+               std::string& err, const std::vector<char>* wide_code = nullptr,
+               const std::vector<WideKernel>* wide_kernels = nullptr);
 void dev_free(DevProgram& dp);
 int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, WsLayout& ws, std::string& err);
 // Runs prologue, persistent chain and slice reduction on `stream`.  Device

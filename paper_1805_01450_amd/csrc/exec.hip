@@ -342,8 +342,21 @@ int dev_query(int& n_cu, size_t& max_lds, std::string& err) {
 }
 
 int dev_upload(const Program& prog, const std::vector<char>& code, const WideProgram* wide, DevProgram& dp,
-               std::string& err) {
+               std::string& err, const std::vector<char>* wide_code, const std::vector<WideKernel>* wide_kernels) {
   if (dp.steps) return 0;
+  if (wide && wide_code && !wide_code->empty() && wide_kernels) {
+    hipModule_t mod = nullptr;
+    HIP_OK(hipModuleLoadData(&mod, wide_code->data()));
+    dp.wide.module = mod;
+    dp.wide.fn.assign(wide->n_steps, nullptr);
+    dp.wide.tiles.assign(wide->n_steps, 0);
+    for (const WideKernel& k : *wide_kernels) {
+      hipFunction_t fn = nullptr;
+      HIP_OK(hipModuleGetFunction(&fn, mod, k.name.c_str()));
+      dp.wide.fn[k.step] = fn;
+      dp.wide.tiles[k.step] = k.tiles;
+    }
+  }
   if (wide) {
     HIP_OK(hipMalloc(&dp.wide.steps, std::max<size_t>(wide->steps.size() * sizeof(int32_t), 16)));
     HIP_OK(hipMalloc(&dp.wide.ops, std::max<size_t>(wide->ops.size() * sizeof(int32_t), 16)));
@@ -353,6 +366,21 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
       HIP_OK(hipMemcpy(dp.wide.ops, wide->ops.data(), wide->ops.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     dp.wide.n_steps = wide->n_steps;
     dp.wide.host_steps = wide->steps;
+    std::vector<int32_t> list;
+    for (int si = 0; si < wide->n_steps; ++si) {
+      if (!wide->steps[8 * si + 7]) continue;
+      if (wide->steps[8 * si + 2] <= 14) {
+        if (dp.wide.const_plan.empty() || !dp.wide.const_plan.back().block)
+          dp.wide.const_plan.push_back({1, (int)list.size(), 0});
+        list.push_back(si);
+        dp.wide.const_plan.back().count++;
+      } else {
+        dp.wide.const_plan.push_back({0, si, 1});
+      }
+    }
+    HIP_OK(hipMalloc(&dp.wide.const_list, std::max<size_t>(list.size() * sizeof(int32_t), 16)));
+    if (!list.empty())
+      HIP_OK(hipMemcpy(dp.wide.const_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   if (!code.empty()) {
     hipModule_t mod = nullptr;
@@ -405,6 +433,8 @@ void dev_free(DevProgram& dp) {
     if (p) (void)hipFree(p);
   if (dp.module) (void)hipModuleUnload((hipModule_t)dp.module);
   if (dp.wide.steps) (void)hipFree(dp.wide.steps);
+  if (dp.wide.const_list) (void)hipFree(dp.wide.const_list);
+  if (dp.wide.module) (void)hipModuleUnload((hipModule_t)dp.wide.module);
   if (dp.wide.ops) (void)hipFree(dp.wide.ops);
   dp = DevProgram();
 }

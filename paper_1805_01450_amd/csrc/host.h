@@ -160,6 +160,18 @@ struct WideProgram {
 // Builds the wide descriptors; false (with err) if a step exceeds the limits.
 bool encode_wide(const Program& prog, WideProgram& wide, std::string& err);
 
+// Generated wide kernels: one per item step (constant steps keep the
+// prebuilt kernel).  A wavefront runs a tile of 2^tile_log2 output elements
+// for 64 items; `tiles` tiles cover the step's output.
+struct WideKernel {
+  int step;
+  std::string name;
+  int tile_log2;
+  unsigned long long tiles;
+};
+std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
+                                 std::vector<WideKernel>& kernels);
+
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.
 // *waves_out gets the wavefronts per block (the item tree may be cut across

@@ -145,6 +145,38 @@ __global__ void __launch_bounds__(256) const_step_kernel(const int* __restrict__
   cst[out + c] = acc;
 }
 
+// A run of small constant steps in one block of 1024 threads, one step after
+// the other (each step reads only constants written before it).
+template <typename R>
+__global__ void __launch_bounds__(1024) const_block_kernel(const int* __restrict__ steps, const int* __restrict__ list,
+                                                           int n_list, const int* __restrict__ ops,
+                                                           cw<R>* __restrict__ cst) {
+  for (int li = 0; li < n_list; ++li) {
+    const int* st = steps + 8 * list[li];
+    const int out = st[1], r = st[2], ns = st[3], m = st[4], ob = st[6];
+    for (uint64_t c = threadIdx.x; c < (1ull << r); c += blockDim.x) {
+      cw<R> acc{0, 0};
+      for (int s2 = 0; s2 < (1 << ns); ++s2) {
+        cw<R> prod{1, 0};
+        for (int i = 0; i < m; ++i) {
+          const int* op = ops + (size_t)(ob + i) * kOp;
+          long long off = op[1];
+          for (int j = 0; j < r; ++j)
+            if ((c >> j) & 1) off += op[16 + j];
+          for (int j = 0; j < ns; ++j)
+            if ((s2 >> j) & 1) off += op[48 + j];
+          const cw<R> v = cst[off];
+          prod = i == 0 ? v : wmul(prod, v);
+        }
+        acc.x += prod.x;
+        acc.y += prod.y;
+      }
+      cst[out + c] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int wide_cpw_log2(int r) {
@@ -157,14 +189,44 @@ template <typename R>
 int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const void* cst, void* mem,
                       uint64_t group_elems, const uint64_t* packed, int n_bs, uint64_t s_begin, uint64_t n_s,
                       uint64_t n_items, void* res, void* gres, bool const_steps, hipStream_t stream) {
+  if (const_steps) {
+    // runs of small constant steps share one single-block launch; large ones
+    // get a launch of their own (plan made at upload, in step order)
+    for (const WideDev::ConstLaunch& cl : wd.const_plan) {
+      if (cl.block) {
+        hipLaunchKernelGGL(const_block_kernel<R>, dim3(1), dim3(1024), 0, stream, (const int*)wd.steps,
+                           (const int*)wd.const_list + cl.first, cl.count, (const int*)wd.ops, (cw<R>*)cst);
+      } else {
+        const uint64_t nc = 1ull << wd.host_steps[8 * cl.first + 2];
+        hipLaunchKernelGGL(const_step_kernel<R>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream,
+                           (const int*)wd.steps, cl.first, (const int*)wd.ops, (cw<R>*)cst);
+      }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+  }
   for (int si = 0; si < wd.n_steps; ++si) {
     const int kind = wd.host_steps[8 * si], r = wd.host_steps[8 * si + 2], is_const = wd.host_steps[8 * si + 7];
-    if (is_const != (const_steps ? 1 : 0)) continue;
+    if (is_const) continue;
     (void)kind;
-    if (const_steps) {
+    if (false) {
       const uint64_t nc = 1ull << r;
       hipLaunchKernelGGL(const_step_kernel<R>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream,
                          (const int*)wd.steps, si, (const int*)wd.ops, (cw<R>*)cst);
+    } else if (si < (int)wd.fn.size() && wd.fn[si]) {
+      // generated kernel of this step
+      void* a_mem = mem;
+      const void* a_cst = cst;
+      const void* a_packed = packed;
+      unsigned long long a_nbs = (unsigned long long)n_bs, a_sb = s_begin, a_ns = n_s, a_ni = n_items;
+      int a_g0 = first_group;
+      unsigned long long a_ge = group_elems;
+      void* a_res = res;
+      void* a_gres = gres;
+      void* args[] = {&a_mem, &a_cst, &a_packed, &a_nbs, &a_sb, &a_ns, &a_ni, &a_g0, &a_ge, &a_res, &a_gres};
+      const unsigned long long blocks = (wd.tiles[si] + 3) / 4;
+      if (hipModuleLaunchKernel((hipFunction_t)wd.fn[si], (unsigned)blocks, (unsigned)n_groups, 1, 256, 1, 1, 0,
+                                stream, args, nullptr) != hipSuccess)
+        return -6;
     } else {
       const int cl = wide_cpw_log2(r);
       const uint64_t waves = ((1ull << r) + (1ull << cl) - 1) >> cl;

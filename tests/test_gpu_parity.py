@@ -495,3 +495,20 @@ def test_bf16x3_config2(config2, engine):
     note("max normalised error bf16x3", e.max(), "c64", e64.max())
     assert e.max() <= BF16X3_TOL
     assert e.max() > e64.max()  # the split products are coarser than FP32 products
+
+
+def test_wide_prebuilt_step_kernel_matches_generated(config2):
+    """The wide engine's prebuilt step kernel (kept as the fallback when
+    generated kernels cannot be built) against the generated ones."""
+    import os
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    gen = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE).amplitudes(bits)
+    os.environ["QGM_WIDE_PREBUILT"] = "1"
+    try:
+        pre = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE).amplitudes(bits)
+    finally:
+        del os.environ["QGM_WIDE_PREBUILT"]
+    assert nerr(pre, ref, 25).max() <= C128_TOL
+    assert nerr(gen, ref, 25).max() <= C128_TOL

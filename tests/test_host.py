@@ -129,7 +129,8 @@ def test_plan_stats():
     assert st["flops_item"] > 0 and st["item_elems"] >= 1
 
 
-def test_large_rank_plan_runs_on_wide_engine_only():
+def test_large_rank_plan_runs_on_wide_engine_only(monkeypatch):
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")  # structure only: skip compiling the step kernels
     c, sl, order = _plan(7, 30, 0, 5)
     st = q.Plan(c, sl, order).stats()
     assert st["engine"] == q.QGM_ENGINE_WIDE and st["max_rank"] > 16
@@ -139,8 +140,9 @@ def test_large_rank_plan_runs_on_wide_engine_only():
         assert e.value.status == -7
 
 
-def test_gradient_plans_split_large_sums():
+def test_gradient_plans_split_large_sums(monkeypatch):
     """Reverse steps that sum many variables are split (no step sums > 8)."""
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")
     text = generate_circuit(7, 30, 0, rz=True)
     c = q.Circuit(text)
     sl, order = c.plan_slices(k_req=6, time_budget_s=1.0)
@@ -150,9 +152,17 @@ def test_gradient_plans_split_large_sums():
 
 
 @pytest.mark.parametrize("k", [13, 20])
-def test_8x8x40_plans_compile(k):
+def test_8x8x40_plans_compile(k, monkeypatch):
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")
     c = q.Circuit(generate_circuit(8, 40, 0))
     sl, order = c.plan_slices(k_req=k, time_budget_s=2.0)
     for grad in (False,):
         st = q.Plan(c, sl, order, prec=q.QGM_C64, gradient=grad).stats()
         assert st["engine"] == q.QGM_ENGINE_WIDE and st["k"] == k
+
+
+def test_generated_wide_kernels_compile_for_gfx950():
+    """hiprtc builds the per-step wide kernels of a 7x7x30 plan."""
+    c, sl, order = _plan(7, 30, 0, 6)
+    st = q.Plan(c, sl, order, prec=q.QGM_C64).stats()
+    assert st["engine"] == q.QGM_ENGINE_WIDE and st["compile_s"] > 0
