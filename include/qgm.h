@@ -138,6 +138,16 @@ void qgm_circuit_free(qgm_circuit* c);
 qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                            uint64_t seed, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                            int32_t* n_order_out);
+/* As qgm_plan_slices, with flags:
+ *   QGM_PLAN_REORDER: recompute the ordering after every removal, as the
+ *     paper's Discussion suggests, instead of keeping the first ordering;
+ *   QGM_PLAN_BYTES: choose the final ordering among the restarts by the
+ *     memory traffic of the compiled program (each step's inputs and output,
+ *     fused eliminations as compiled) instead of the sum of 2^deg(v). */
+enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2 };
+qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
+                              uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
+                              int32_t* n_order_out);
 /* Cost (sum of 2^deg(v)) and width (max deg(v)) of eliminating `order` after
  * removing the sliced vertices (Section "Variable elimination", cost model).
  * Errors: QGM_E_SLICE, QGM_E_ORDER as for qgm_plan_create. */

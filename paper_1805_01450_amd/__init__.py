@@ -59,12 +59,18 @@ def qgm_circuit_free(c) -> None:
     lib.qgm_circuit_free(c)
 
 
-def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0):
+QGM_PLAN_REORDER = 1
+QGM_PLAN_BYTES = 2
+
+
+def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0,
+                    flags: int = 0):
     _, nv, _ = qgm_circuit_info(c)
     sl = (C.c_int32 * 40)()
     order = (C.c_int32 * max(1, nv))()
     k, n = C.c_int32(), C.c_int32()
-    check(lib.qgm_plan_slices(c, k_req, target_rank, float(time_budget_s), seed, sl, C.byref(k), order, C.byref(n)))
+    check(lib.qgm_plan_slices_ex(c, k_req, target_rank, float(time_budget_s), seed, flags, sl, C.byref(k), order,
+                                 C.byref(n)))
     return list(sl[: k.value]), list(order[: n.value])
 
 
@@ -230,8 +236,8 @@ class Circuit:
     def graph(self):
         return qgm_circuit_graph(self.h)
 
-    def plan_slices(self, k_req=-1, target_rank=0, time_budget_s=1.0, seed=0):
-        return qgm_plan_slices(self.h, k_req, target_rank, time_budget_s, seed)
+    def plan_slices(self, k_req=-1, target_rank=0, time_budget_s=1.0, seed=0, flags=0):
+        return qgm_plan_slices(self.h, k_req, target_rank, time_budget_s, seed, flags)
 
     def __del__(self):
         h, self.h = getattr(self, "h", None), None

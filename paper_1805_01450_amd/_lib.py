@@ -55,6 +55,7 @@ def _load():
         "qgm_circuit_graph": (i32, [P, pi32, i32, pi32]),
         "qgm_circuit_free": (None, [P]),
         "qgm_plan_slices": (i32, [P, i32, i32, dbl, u64, pi32, pi32, pi32, pi32]),
+        "qgm_plan_slices_ex": (i32, [P, i32, i32, dbl, u64, i32, pi32, pi32, pi32, pi32]),
         "qgm_order_cost": (i32, [P, pi32, i32, pi32, i32, pd, pi32]),
         "qgm_plan_create": (i32, [P, pi32, i32, pi32, i32, C.POINTER(PlanOpts), C.POINTER(P)]),
         "qgm_plan_stats": (i32, [P, C.POINTER(Stats)]),
@@ -82,7 +83,7 @@ def _load():
 
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
-            "qgm_plan_slices", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
+            "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
             "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_autotune", "qgm_plan_free",
             "qgm_last_error", "qgm_amplitude")

@@ -203,12 +203,19 @@ void qgm_circuit_free(qgm_circuit* c) { delete c; }
 qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                            uint64_t seed, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                            int32_t* n_order_out) {
+  return qgm_plan_slices_ex(c, k_req, target_rank, time_budget_s, seed, 0, sliced_out, k_out, order_out,
+                            n_order_out);
+}
+
+qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
+                              uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
+                              int32_t* n_order_out) {
   GUARD_BEGIN
   if (!c || !sliced_out || !k_out || !order_out || !n_order_out) return fail(QGM_E_ARG, "null argument");
   if (k_req > 40) return fail(QGM_E_ARG, "k_req > 40");
   if (!(time_budget_s >= 0)) return fail(QGM_E_ARG, "negative time budget");
   std::vector<int> sl, ord;
-  plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord);
+  plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord, flags);
   for (size_t i = 0; i < sl.size(); ++i) sliced_out[i] = sl[i];
   *k_out = (int32_t)sl.size();
   for (size_t i = 0; i < ord.size(); ++i) order_out[i] = ord[i];

@@ -132,6 +132,75 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
     }
     o << "}\n";
   }
+  // constant steps (no fixed variable): one thread per output element,
+  // strides as constants.  Runs of small steps share a single-block kernel
+  // (a barrier between steps); large steps get a grid of their own.
+  auto const_body = [&](int si, const std::string& c_expr) {
+    const int32_t* sr = &wide.steps[8 * si];
+    const int out = sr[1], r = sr[2], ns = sr[3], m = sr[4], ob = sr[6];
+    for (int i = 0; i < m; ++i) {
+      const int32_t* rc = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+      o << "    const long long o" << i << " = " << rc[1] << "ll";
+      for (int j = 0; j < r; ++j)
+        if (rc[16 + j]) o << " + (long long)((" << c_expr << " >> " << j << ") & 1ull) * " << rc[16 + j] << "ll";
+      o << ";\n";
+    }
+    o << "    C2 a;\n";
+    for (int s2 = 0; s2 < (1 << ns); ++s2) {
+      std::string cur = m == 0 ? "C2{(R)1, (R)0}" : "";
+      for (int i = 0; i < m; ++i) {
+        const int32_t* rc = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+        long long off = 0;
+        for (int j = 0; j < ns; ++j)
+          if ((s2 >> j) & 1) off += rc[48 + j];
+        const std::string v = "cst[o" + std::to_string(i) + " + " + std::to_string(off) + "ll]";
+        cur = i == 0 ? v : "cm(" + cur + ", " + v + ")";
+      }
+      o << "    " << (s2 == 0 ? "a = " + cur : "a = cad(a, " + cur + ")") << ";\n";
+    }
+    o << "    cst[" << out << "ll + (long long)" << c_expr << "] = a;\n";
+  };
+  std::vector<int> run;
+  auto flush_run = [&]() {
+    if (run.empty()) return;
+    WideKernel k;
+    k.step = run.front();
+    k.name = "qcb" + std::to_string(run.front());
+    k.tile_log2 = -1;
+    k.tiles = 1;
+    k.const_steps = run;
+    kernels.push_back(k);
+    o << "extern \"C\" __global__ void __launch_bounds__(1024) " << k.name << "(C2* __restrict__ cst) {\n";
+    for (int si : run) {
+      const int r = wide.steps[8 * si + 2];
+      o << "  for (unsigned long long c = threadIdx.x; c < " << (1ull << r) << "ull; c += 1024ull) {\n";
+      const_body(si, "c");
+      o << "  }\n  __syncthreads();\n";
+    }
+    o << "}\n";
+    run.clear();
+  };
+  for (int si = 0; si < wide.n_steps; ++si) {
+    if (!wide.steps[8 * si + 7]) continue;
+    const int r = wide.steps[8 * si + 2];
+    if (r <= 14) {
+      run.push_back(si);
+      continue;
+    }
+    flush_run();
+    WideKernel k;
+    k.step = si;
+    k.name = "qc" + std::to_string(si);
+    k.tile_log2 = -2;
+    k.tiles = 1ull << r;
+    kernels.push_back(k);
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << k.name << "(C2* __restrict__ cst) {\n"
+      << "  const unsigned long long c = (unsigned long long)blockIdx.x * 256ull + threadIdx.x;\n"
+      << "  if (c >= " << (1ull << r) << "ull) return;\n  {\n";
+    const_body(si, "c");
+    o << "  }\n}\n";
+  }
+  flush_run();
   (void)lit;
   (void)prog;
   return o.str();

@@ -23,6 +23,8 @@ struct WideDev {
   // in const_list[first, first + count)), large steps alone (first = step)
   struct ConstLaunch {
     int block, first, count;
+    void* fn;  // generated kernel (hipFunction_t) or null for the prebuilt ones
+    unsigned long long elems;
   };
   std::vector<ConstLaunch> const_plan;
   void* const_list = nullptr;

@@ -353,8 +353,13 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
     for (const WideKernel& k : *wide_kernels) {
       hipFunction_t fn = nullptr;
       HIP_OK(hipModuleGetFunction(&fn, mod, k.name.c_str()));
-      dp.wide.fn[k.step] = fn;
-      dp.wide.tiles[k.step] = k.tiles;
+      if (k.tile_log2 >= 0) {
+        dp.wide.fn[k.step] = fn;
+        dp.wide.tiles[k.step] = k.tiles;
+      } else {
+        // generated constant-step kernels, in step order
+        dp.wide.const_plan.push_back({k.tile_log2 == -1 ? 1 : 0, k.step, (int)k.const_steps.size(), fn, k.tiles});
+      }
     }
   }
   if (wide) {
@@ -367,15 +372,17 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
     dp.wide.n_steps = wide->n_steps;
     dp.wide.host_steps = wide->steps;
     std::vector<int32_t> list;
-    for (int si = 0; si < wide->n_steps; ++si) {
-      if (!wide->steps[8 * si + 7]) continue;
-      if (wide->steps[8 * si + 2] <= 14) {
-        if (dp.wide.const_plan.empty() || !dp.wide.const_plan.back().block)
-          dp.wide.const_plan.push_back({1, (int)list.size(), 0});
-        list.push_back(si);
-        dp.wide.const_plan.back().count++;
-      } else {
-        dp.wide.const_plan.push_back({0, si, 1});
+    if (dp.wide.const_plan.empty()) {  // no generated constant kernels: prebuilt ones
+      for (int si = 0; si < wide->n_steps; ++si) {
+        if (!wide->steps[8 * si + 7]) continue;
+        if (wide->steps[8 * si + 2] <= 14) {
+          if (dp.wide.const_plan.empty() || !dp.wide.const_plan.back().block)
+            dp.wide.const_plan.push_back({1, (int)list.size(), 0, nullptr, 0});
+          list.push_back(si);
+          dp.wide.const_plan.back().count++;
+        } else {
+          dp.wide.const_plan.push_back({0, si, 1, nullptr, 0});
+        }
       }
     }
     HIP_OK(hipMalloc(&dp.wide.const_list, std::max<size_t>(list.size() * sizeof(int32_t), 16)));

@@ -66,8 +66,10 @@ struct OrderCost {
 };
 OrderCost order_cost(const Graph& g, const std::vector<int>& order, const std::vector<char>& removed);
 std::vector<int> min_fill_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, int randomize);
+// flags bit 0: recompute the ordering after every removal (instead of
+// keeping the first ordering throughout).
 bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
-                 std::vector<int>& sliced_vars, std::vector<int>& order_vars);
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags = 0);
 
 // ------------------------------------------------------------------ program
 // Operand reference of a fused elimination step.
@@ -164,10 +166,11 @@ bool encode_wide(const Program& prog, WideProgram& wide, std::string& err);
 // prebuilt kernel).  A wavefront runs a tile of 2^tile_log2 output elements
 // for 64 items; `tiles` tiles cover the step's output.
 struct WideKernel {
-  int step;
+  int step;                     // item step, or first constant step
   std::string name;
-  int tile_log2;
-  unsigned long long tiles;
+  int tile_log2;                // >= 0 item step; -1 run of small constant steps; -2 large constant step
+  unsigned long long tiles;     // item step: wavefront tiles; large constant step: output elements
+  std::vector<int> const_steps; // run of small constant steps (tile_log2 == -1)
 };
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
                                  std::vector<WideKernel>& kernels);

@@ -187,13 +187,101 @@ std::vector<int> min_fill_order(const Graph& g0, const std::vector<char>& remove
 
 namespace qgm {
 
+// Work of the compiled program for a plan, without building it: tensors are
+// bitsets over graph vertices; eliminating v fuses T_v into one step that
+// also sums every variable occurring only in T_v (as the compiler does).
+// Returns bytes (inputs + output of every step, 8 B per element) and flops.
+struct SimCost {
+  double bytes = 0, flops = 0;
+};
+
+static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, const std::vector<char>& removed,
+                        const std::vector<int>& order) {
+  const int words = (n + 63) / 64 + 1;
+  std::vector<std::vector<uint64_t>> tens;
+  for (const Factor& f : net.factors) {
+    std::vector<uint64_t> b(words, 0);
+    int cnt = 0;
+    for (int j = 0; j < f.nv; ++j) {
+      int v = vov[f.var[j]];
+      if (v >= 0 && !removed[v]) {
+        b[v >> 6] |= 1ull << (v & 63);
+        ++cnt;
+      }
+    }
+    if (cnt) tens.push_back(b);
+  }
+  std::vector<char> alive(tens.size(), 1);
+  std::vector<int> count(n, 0);
+  for (auto& b : tens)
+    for (int v = 0; v < n; ++v)
+      if ((b[v >> 6] >> (v & 63)) & 1) count[v]++;
+  std::vector<char> done(n, 0);
+  SimCost c;
+  auto pc = [&](const std::vector<uint64_t>& b) {
+    int k = 0;
+    for (uint64_t w : b) k += __builtin_popcountll(w);
+    return k;
+  };
+  for (int v : order) {
+    if (removed[v] || done[v]) continue;
+    std::vector<int> tv;
+    std::vector<uint64_t> un(words, 0);
+    for (size_t i = 0; i < tens.size(); ++i)
+      if (alive[i] && ((tens[i][v >> 6] >> (v & 63)) & 1)) {
+        tv.push_back((int)i);
+        for (int w = 0; w < words; ++w) un[w] |= tens[i][w];
+      }
+    if (tv.empty()) {
+      done[v] = 1;
+      continue;
+    }
+    std::vector<int> cin;
+    std::vector<uint64_t> out = un, sum(words, 0);
+    double in_elems = 0;
+    for (int i : tv) in_elems += std::ldexp(1.0, pc(tens[i]));
+    for (int w = 0; w < words; ++w) {
+      uint64_t bits = un[w];
+      while (bits) {
+        int u = w * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        int inside = 0;
+        for (int i : tv) inside += (tens[i][u >> 6] >> (u & 63)) & 1;
+        if (u == v || inside == count[u]) {
+          sum[u >> 6] |= 1ull << (u & 63);
+          out[u >> 6] &= ~(1ull << (u & 63));
+        }
+      }
+    }
+    const int r = pc(out), ns = pc(sum), m = (int)tv.size();
+    c.flops += std::ldexp(1.0, r + ns) * (6.0 * (m - 1) + 2.0);
+    c.bytes += 8.0 * (in_elems + std::ldexp(1.0, r));
+    for (int i : tv) {
+      alive[i] = 0;
+      for (int u = 0; u < n; ++u)
+        if ((tens[i][u >> 6] >> (u & 63)) & 1) count[u]--;
+    }
+    for (int u = 0; u < n; ++u) {
+      if ((sum[u >> 6] >> (u & 63)) & 1) done[u] = 1;
+      if ((out[u >> 6] >> (u & 63)) & 1) count[u]++;
+    }
+    tens.push_back(out);
+    alive.push_back(1);
+  }
+  return c;
+}
+
 // Best of several min-fill orderings (deterministic first, then randomised
 // tie-breaking) until the time budget is spent.
 static std::vector<int> best_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, double budget_s,
-                                   OrderCost* out_cost) {
+                                   OrderCost* out_cost, const Network* net = nullptr,
+                                   const std::vector<int>* vov = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> best = min_fill_order(g, removed, seed, 0);
   OrderCost bc = order_cost(g, best, removed);
+  // with the network at hand, candidates are compared by the compiled
+  // program's memory traffic, which sets the run time of large plans
+  double best_bytes = net ? simulate(*net, *vov, g.n, removed, best).bytes : 0.0;
   // At most kMaxRestarts restarts, so small graphs give the same ordering on
   // every run; large graphs may stop earlier on the time budget.
   const int kMaxRestarts = 128;
@@ -202,7 +290,14 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
     if (el >= budget_s) break;
     std::vector<int> o = min_fill_order(g, removed, seed + 0x9e3779b97f4a7c15ull * it, 1);
     OrderCost c = order_cost(g, o, removed);
-    if (c.cost < bc.cost || (c.cost == bc.cost && c.width < bc.width)) {
+    if (net) {
+      const double b = simulate(*net, *vov, g.n, removed, o).bytes;
+      if (b < best_bytes) {
+        best.swap(o);
+        bc = c;
+        best_bytes = b;
+      }
+    } else if (c.cost < bc.cost || (c.cost == bc.cost && c.width < bc.width)) {
       best.swap(o);
       bc = c;
     }
@@ -216,7 +311,8 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
 // then lower vertex id).  Candidates are the `n_cand` highest-degree
 // vertices of the graph with the previous picks removed.
 bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
-                 std::vector<int>& sliced_vars, std::vector<int>& order_vars) {
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags) {
+  const bool reorder_each = (flags & 1) != 0;
   std::vector<int> vov;
   Graph g = model_graph(net, vov);
   std::vector<char> removed(g.n, 0);
@@ -254,9 +350,20 @@ bool plan_slices(const Network& net, int k_req, int target_rank, double time_bud
     removed[best_v] = 1;
     picks.push_back(best_v);
     cur = best_c;
+    if (reorder_each) {
+      // a fresh ordering of the reduced graph guides the next removal
+      const double per_pick = time_budget_s * 0.4 / std::max(1, kmax);
+      OrderCost c1;
+      std::vector<int> o1 = best_order(g, removed, seed + 31 * picks.size(), per_pick, &c1);
+      if (c1.cost < cur.cost || (c1.cost == cur.cost && c1.width < cur.width)) {
+        order0 = o1;
+        cur = c1;
+      }
+    }
   }
   double b1 = k_req == 0 ? 0.0 : time_budget_s * 0.6;
-  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr);
+  std::vector<int> order1 = (flags & 2) ? best_order(g, removed, seed + 17, b1, nullptr, &net, &vov)
+                                        : best_order(g, removed, seed + 17, b1, nullptr);
   sliced_vars.clear();
   for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
   order_vars.clear();

@@ -193,7 +193,14 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
     // runs of small constant steps share one single-block launch; large ones
     // get a launch of their own (plan made at upload, in step order)
     for (const WideDev::ConstLaunch& cl : wd.const_plan) {
-      if (cl.block) {
+      if (cl.fn) {
+        void* a_cst = const_cast<void*>(cst);
+        void* args[] = {&a_cst};
+        const unsigned blocks = cl.block ? 1u : (unsigned)((cl.elems + 255) / 256);
+        if (hipModuleLaunchKernel((hipFunction_t)cl.fn, blocks, 1, 1, cl.block ? 1024 : 256, 1, 1, 0, stream, args,
+                                  nullptr) != hipSuccess)
+          return -6;
+      } else if (cl.block) {
         hipLaunchKernelGGL(const_block_kernel<R>, dim3(1), dim3(1024), 0, stream, (const int*)wd.steps,
                            (const int*)wd.const_list + cl.first, cl.count, (const int*)wd.ops, (cw<R>*)cst);
       } else {

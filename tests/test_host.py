@@ -166,3 +166,28 @@ def test_generated_wide_kernels_compile_for_gfx950():
     c, sl, order = _plan(7, 30, 0, 6)
     st = q.Plan(c, sl, order, prec=q.QGM_C64).stats()
     assert st["engine"] == q.QGM_ENGINE_WIDE and st["compile_s"] > 0
+
+
+def test_planner_reorder_flag_gives_valid_plans():
+    c = q.Circuit(generate_circuit(6, 25, 0))
+    free = [v for v, _, _, out in c.vars() if not out]
+    for flags in (0, q.QGM_PLAN_REORDER, q.QGM_PLAN_BYTES, q.QGM_PLAN_REORDER | q.QGM_PLAN_BYTES):
+        sl, order = c.plan_slices(k_req=8, time_budget_s=0.5, flags=flags)
+        assert len(sl) == 8 and sorted(order) == sorted(set(free) - set(sl))
+        cost, width = q.qgm_order_cost(c.h, sl, order)
+        assert width <= 8
+
+
+def test_generated_source_shapes():
+    """The generated kernel of a small plan is cut across wavefronts only for
+    amplitude programs (gradient programs are not trees)."""
+    text = generate_circuit(5, 20, 0)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    amp = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED).stats()
+    assert amp["engine"] == q.QGM_ENGINE_GENERATED and amp["waves"] in (1, 2, 4)
+    rz = generate_circuit(4, 10, 3, rz=True)
+    c2 = q.Circuit(rz)
+    sl2, order2 = c2.plan_slices(k_req=2, time_budget_s=0.2)
+    g = q.Plan(c2, sl2, order2, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED, gradient=True).stats()
+    assert g["waves"] == 1
