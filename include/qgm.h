@@ -71,7 +71,10 @@ typedef struct {
                             fails with QGM_E_WORKSPACE when one work item's memory cannot fit */
   int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
   int32_t gradient;      /* 1 = also compile the reverse-mode steps for d alpha / d theta */
-  int32_t reserved[6];
+  int32_t waves;         /* GENERATED: wavefronts per block to cut the item tree across
+                            (1, 2, 4 or 8; fewer when the tree or the LDS budget does not
+                            allow it); 0 = chosen by the cost model */
+  int32_t reserved[5];
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
@@ -103,6 +106,9 @@ typedef struct {
   int32_t engine;         /* engine the plan runs with (INTERPRETER, GENERATED or WIDE) */
   int32_t waves;          /* GENERATED: wavefronts per block the item tree is cut across */
   double compile_s;       /* seconds spent generating and compiling the plan's kernel */
+  int32_t launches;       /* kernel launches of the item steps per pass: WIDE with
+                             generated kernels, one per level of mutually independent
+                             steps; otherwise the item steps' kernel count */
 } qgm_stats;
 
 /* Circuit text v1, one gate per line, '#' starts a comment:
@@ -143,8 +149,11 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *     paper's Discussion suggests, instead of keeping the first ordering;
  *   QGM_PLAN_BYTES: choose the final ordering among the restarts by the
  *     memory traffic of the compiled program (each step's inputs and output,
- *     fused eliminations as compiled) instead of the sum of 2^deg(v). */
-enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2 };
+ *     fused eliminations as compiled) instead of the sum of 2^deg(v);
+ *   QGM_PLAN_LATENCY: choose it by the time of one item on four wavefronts,
+ *     max(4 x critical path, total) in flops of the compiled steps, for
+ *     batches too small to fill the GPU (takes precedence over BYTES). */
+enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2, QGM_PLAN_LATENCY = 4 };
 qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                               uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                               int32_t* n_order_out);

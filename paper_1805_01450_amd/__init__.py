@@ -61,6 +61,7 @@ def qgm_circuit_free(c) -> None:
 
 QGM_PLAN_REORDER = 1
 QGM_PLAN_BYTES = 2
+QGM_PLAN_LATENCY = 4
 
 
 def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0,
@@ -81,12 +82,13 @@ def qgm_order_cost(c, sliced, order):
 
 
 def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
-                    engine: int = QGM_ENGINE_AUTO, gradient: bool = False):
+                    engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0):
     opts = PlanOpts()
     opts.prec = prec
     opts.profile = 1 if profile else 0
     opts.engine = engine
     opts.gradient = 1 if gradient else 0
+    opts.waves = waves
     opts.workspace_cap = workspace_cap
     h = C.c_void_p()
     check(lib.qgm_plan_create(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(opts), C.byref(h)))
@@ -252,14 +254,14 @@ class Plan:
     """Owning wrapper of a qgm_plan handle plus a cached device workspace."""
 
     def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
-                 profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False):
+                 profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0):
         self.circuit = circuit
         self.sliced = list(sliced)
         self.order = list(order)
         self.prec = prec
         self.gradient = gradient
         self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine,
-                                 gradient)
+                                 gradient, waves)
         self._ws = None
 
     @property

@@ -24,14 +24,16 @@ class VarInfo(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("profile", C.c_int32), ("workspace_cap", C.c_size_t),
-                ("engine", C.c_int32), ("gradient", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("engine", C.c_int32), ("gradient", C.c_int32), ("waves", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n_steps", C.c_int32), ("n_const_steps", C.c_int32), ("max_rank", C.c_int32),
                 ("item_elems", C.c_int32), ("n_leaves", C.c_int32), ("k", C.c_int32),
                 ("flops_item", C.c_double), ("flops_const", C.c_double), ("bytes_item", C.c_double),
-                ("cost", C.c_double), ("engine", C.c_int32), ("waves", C.c_int32), ("compile_s", C.c_double)]
+                ("cost", C.c_double), ("engine", C.c_int32), ("waves", C.c_int32), ("compile_s", C.c_double),
+                ("launches", C.c_int32)]
 
 
 def _load():

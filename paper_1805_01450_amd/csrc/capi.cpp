@@ -261,6 +261,8 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   if (o.prec != QGM_C128 && o.prec != QGM_C64 && o.prec != QGM_BF16X3)
     return fail(QGM_E_UNSUPPORTED, "unknown precision");
   if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_WIDE) return fail(QGM_E_ARG, "unknown engine");
+  if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8)
+    return fail(QGM_E_ARG, "waves must be 0, 1, 2, 4 or 8");
   auto* p = new qgm_plan();
   p->net = c->net;
   p->sliced = sv;
@@ -321,7 +323,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   }
   if (want_gen) {
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits, &p->dev.chain_waves);
+    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits, &p->dev.chain_waves, o.waves);
     std::string jerr;
     bool ok = jit_compile(src, "qgm_chain.hip", p->code, jerr);
     if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
@@ -366,6 +368,13 @@ qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
   s.engine = p->engine;
   s.compile_s = p->compile_s;
   s.waves = p->dev.chain_waves;
+  s.launches = 1;
+  if (p->engine == QGM_ENGINE_WIDE) {
+    int lv = 0, item_steps = 0;
+    for (const WideKernel& k : p->wide_kernels) lv += k.kind == 0;
+    for (int si = 0; si < p->wide.n_steps; ++si) item_steps += !p->wide.steps[8 * si + 7];
+    s.launches = lv > 0 ? lv : item_steps;
+  }
   *out = s;
   return QGM_OK;
 }
@@ -690,11 +699,15 @@ qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void*
     return QGM_OK;
   };
   if ((s = time_current(best.ms))) return s;
-  for (int w : {1, 2, 4, 8}) {
-    if (w == best.waves) continue;
+  // wavefront counts and exchange-cost estimates of the schedule
+  std::vector<std::pair<int, double>> grid{{1, 0.0}};
+  for (int w : {2, 4, 8})
+    for (double comm : {300.0, kDefaultExchangeCost, 3000.0}) grid.push_back({w, comm});
+  for (auto [w, comm] : grid) {
+    if (w == best.waves && (w == 1 || comm == kDefaultExchangeCost)) continue;  // the current kernel
     int got = 0;
-    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w);
-    if (got != w) continue;  // this cut is not possible for the plan
+    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w, comm);
+    if (got != w) continue;  // no schedule on w wavefronts fits for the plan
     Variant v;
     std::string jerr;
     if (!jit_compile(src, "qgm_chain.hip", v.code, jerr)) continue;

@@ -16,9 +16,13 @@ struct WideDev {
   void* ops = nullptr;
   int n_steps = 0;
   std::vector<int32_t> host_steps;
-  void* module = nullptr;                 // generated per-step kernels (hipModule_t), or null
-  std::vector<void*> fn;                  // per step: hipFunction_t or null (prebuilt kernel)
-  std::vector<unsigned long long> tiles;  // per step: wavefront tiles of the generated kernel
+  void* module = nullptr;  // generated kernels (hipModule_t), or null: prebuilt per-step kernels
+  // generated item kernels, one per level of independent steps, in order
+  struct Level {
+    void* fn;                   // hipFunction_t
+    unsigned long long blocks;  // 256-thread blocks per 64-item group
+  };
+  std::vector<Level> levels;
   // constant steps: runs of small steps in one single-block launch (indices
   // in const_list[first, first + count)), large steps alone (first = step)
   struct ConstLaunch {

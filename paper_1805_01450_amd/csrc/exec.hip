@@ -348,18 +348,13 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
     hipModule_t mod = nullptr;
     HIP_OK(hipModuleLoadData(&mod, wide_code->data()));
     dp.wide.module = mod;
-    dp.wide.fn.assign(wide->n_steps, nullptr);
-    dp.wide.tiles.assign(wide->n_steps, 0);
     for (const WideKernel& k : *wide_kernels) {
       hipFunction_t fn = nullptr;
       HIP_OK(hipModuleGetFunction(&fn, mod, k.name.c_str()));
-      if (k.tile_log2 >= 0) {
-        dp.wide.fn[k.step] = fn;
-        dp.wide.tiles[k.step] = k.tiles;
-      } else {
-        // generated constant-step kernels, in step order
-        dp.wide.const_plan.push_back({k.tile_log2 == -1 ? 1 : 0, k.step, (int)k.const_steps.size(), fn, k.tiles});
-      }
+      if (k.kind == 0)
+        dp.wide.levels.push_back({fn, k.blocks});
+      else  // generated constant-step kernels, in step order
+        dp.wide.const_plan.push_back({k.kind == 1 ? 1 : 0, k.steps.front(), (int)k.steps.size(), fn, k.blocks});
     }
   }
   if (wide) {
@@ -589,7 +584,9 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
     void* a_gres = gres;
     void* a_part = part;
     int a_fused = ws.fused;
-    void* args[] = {&a_raw, &a_par, &a_bits, &a_nq, &a_nbs, &a_sb, &a_ns, &a_ni, &a_res, &a_gres, &a_part, &a_fused};
+    int a_log2 = (cfg.n_s & (cfg.n_s - 1)) == 0 ? __builtin_ctzll(cfg.n_s) : -1;
+    void* args[] = {&a_bits, &a_ns, &a_sb, &a_ni, &a_nbs, &a_nq, &a_fused, &a_log2, &a_par, &a_res, &a_gres, &a_part,
+                    &a_raw};
     HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes * dp.chain_waves, 1,
                                  1, 0, stream, args, nullptr));
     mark(2);

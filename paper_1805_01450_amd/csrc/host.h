@@ -162,15 +162,16 @@ struct WideProgram {
 // Builds the wide descriptors; false (with err) if a step exceeds the limits.
 bool encode_wide(const Program& prog, WideProgram& wide, std::string& err);
 
-// Generated wide kernels: one per item step (constant steps keep the
-// prebuilt kernel).  A wavefront runs a tile of 2^tile_log2 output elements
-// for 64 items; `tiles` tiles cover the step's output.
+// Generated wide kernels.  kind 0: one level of mutually independent item
+// steps (blocks of 256 threads per 64-item group, each block running four
+// wavefront tiles of one step); kind 1: a run of small constant steps in one
+// block of 1024 threads; kind 2: one large constant step, `blocks` = its
+// output elements (one thread each).
 struct WideKernel {
-  int step;                     // item step, or first constant step
+  int kind;
   std::string name;
-  int tile_log2;                // >= 0 item step; -1 run of small constant steps; -2 large constant step
-  unsigned long long tiles;     // item step: wavefront tiles; large constant step: output elements
-  std::vector<int> const_steps; // run of small constant steps (tile_log2 == -1)
+  unsigned long long blocks;
+  std::vector<int> steps;
 };
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
                                  std::vector<WideKernel>& kernels);
@@ -180,7 +181,11 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
 // *waves_out gets the wavefronts per block (the item tree may be cut across
 // several wavefronts that run the same 64 items).
 // force_waves > 0 requests that many wavefronts (0 = cost model).
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0);
+// comm: estimated cost, in flops, of one tensor crossing wavefronts through
+// LDS (0 = kDefaultExchangeCost); the autotuner tries several.
+constexpr double kDefaultExchangeCost = 1000.0;
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0,
+                                  double comm = 0);
 // hiprtc compilation of `src` for gfx950 into a code object.
 bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
 

@@ -17,8 +17,12 @@ bool jit_compile(const std::string& src, const char* name, std::vector<char>& co
   // gfx950 only; packed FP32 instructions disabled as for the prebuilt kernels.
   // -fno-honor-nans / -fno-signed-zeros let multiplications by literal 0 and
   // +-1 fold away; no reassociation is enabled, so no other arithmetic moves.
+  // The leading kernel arguments are preloaded into SGPRs at wave launch
+  // (gfx950 kernarg preload; the code object keeps a loading prologue for
+  // firmware without it), which saves a dependent scalar load per wave.
   const char* opts[] = {"--offload-arch=gfx950", "-O3", "-fno-honor-nans", "-fno-signed-zeros",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-mllvm", "-amdgpu-kernarg-preload-count=14"};
   hiprtcResult r = hiprtcCompileProgram(p, (int)(sizeof(opts) / sizeof(opts[0])), opts);
   if (r != HIPRTC_SUCCESS) {
     size_t n = 0;

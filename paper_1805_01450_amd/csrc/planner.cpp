@@ -190,9 +190,12 @@ namespace qgm {
 // Work of the compiled program for a plan, without building it: tensors are
 // bitsets over graph vertices; eliminating v fuses T_v into one step that
 // also sums every variable occurring only in T_v (as the compiler does).
-// Returns bytes (inputs + output of every step, 8 B per element) and flops.
+// Returns bytes (inputs + output of every step, 8 B per element), flops and
+// the critical path: the largest flop count along a chain of dependent
+// steps, the time of one item when its steps run on unboundedly many
+// wavefronts.
 struct SimCost {
-  double bytes = 0, flops = 0;
+  double bytes = 0, flops = 0, cp = 0;
 };
 
 static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, const std::vector<char>& removed,
@@ -211,6 +214,7 @@ static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, 
     }
     if (cnt) tens.push_back(b);
   }
+  std::vector<double> fin(tens.size(), 0.0);  // flops along the longest chain ending at each tensor
   std::vector<char> alive(tens.size(), 1);
   std::vector<int> count(n, 0);
   for (auto& b : tens)
@@ -254,7 +258,12 @@ static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, 
       }
     }
     const int r = pc(out), ns = pc(sum), m = (int)tv.size();
-    c.flops += std::ldexp(1.0, r + ns) * (6.0 * (m - 1) + 2.0);
+    const double f = std::ldexp(1.0, r + ns) * (6.0 * (m - 1) + 2.0);
+    c.flops += f;
+    double f0 = 0;
+    for (int i : tv) f0 = std::max(f0, fin[i]);
+    fin.push_back(f0 + f);
+    c.cp = std::max(c.cp, fin.back());
     c.bytes += 8.0 * (in_elems + std::ldexp(1.0, r));
     for (int i : tv) {
       alive[i] = 0;
@@ -272,16 +281,25 @@ static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, 
 }
 
 // Best of several min-fill orderings (deterministic first, then randomised
-// tie-breaking) until the time budget is spent.
+// tie-breaking) until the time budget is spent.  Objectives: OBJ_COST, the
+// sum of 2^deg(v); OBJ_BYTES, the compiled program's memory traffic (which
+// sets the run time of large plans); OBJ_LATENCY, max(4 x critical path,
+// flops), the time of one item on four wavefronts (for batches too small to
+// fill the GPU), ties broken by flops.
+enum { OBJ_COST = 0, OBJ_BYTES = 1, OBJ_LATENCY = 2 };
 static std::vector<int> best_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, double budget_s,
-                                   OrderCost* out_cost, const Network* net = nullptr,
+                                   OrderCost* out_cost, int objective = OBJ_COST, const Network* net = nullptr,
                                    const std::vector<int>* vov = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> best = min_fill_order(g, removed, seed, 0);
   OrderCost bc = order_cost(g, best, removed);
-  // with the network at hand, candidates are compared by the compiled
-  // program's memory traffic, which sets the run time of large plans
-  double best_bytes = net ? simulate(*net, *vov, g.n, removed, best).bytes : 0.0;
+  auto score = [&](const std::vector<int>& o) -> std::pair<double, double> {
+    if (objective == OBJ_COST) return {0.0, 0.0};
+    const SimCost sc = simulate(*net, *vov, g.n, removed, o);
+    if (objective == OBJ_BYTES) return {sc.bytes, 0.0};
+    return {std::max(4.0 * sc.cp, sc.flops), sc.flops};
+  };
+  std::pair<double, double> best_score = score(best);
   // At most kMaxRestarts restarts, so small graphs give the same ordering on
   // every run; large graphs may stop earlier on the time budget.
   const int kMaxRestarts = 128;
@@ -290,12 +308,12 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
     if (el >= budget_s) break;
     std::vector<int> o = min_fill_order(g, removed, seed + 0x9e3779b97f4a7c15ull * it, 1);
     OrderCost c = order_cost(g, o, removed);
-    if (net) {
-      const double b = simulate(*net, *vov, g.n, removed, o).bytes;
-      if (b < best_bytes) {
+    if (objective != OBJ_COST) {
+      const std::pair<double, double> sc = score(o);
+      if (sc < best_score) {
         best.swap(o);
         bc = c;
-        best_bytes = b;
+        best_score = sc;
       }
     } else if (c.cost < bc.cost || (c.cost == bc.cost && c.width < bc.width)) {
       best.swap(o);
@@ -362,8 +380,8 @@ bool plan_slices(const Network& net, int k_req, int target_rank, double time_bud
     }
   }
   double b1 = k_req == 0 ? 0.0 : time_budget_s * 0.6;
-  std::vector<int> order1 = (flags & 2) ? best_order(g, removed, seed + 17, b1, nullptr, &net, &vov)
-                                        : best_order(g, removed, seed + 17, b1, nullptr);
+  const int objective = (flags & 4) ? OBJ_LATENCY : (flags & 2) ? OBJ_BYTES : OBJ_COST;
+  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr, objective, &net, &vov);
   sliced_vars.clear();
   for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
   order_vars.clear();

@@ -211,37 +211,31 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
     }
     return hipGetLastError() == hipSuccess ? 0 : -6;
   }
-  for (int si = 0; si < wd.n_steps; ++si) {
-    const int kind = wd.host_steps[8 * si], r = wd.host_steps[8 * si + 2], is_const = wd.host_steps[8 * si + 7];
-    if (is_const) continue;
-    (void)kind;
-    if (false) {
-      const uint64_t nc = 1ull << r;
-      hipLaunchKernelGGL(const_step_kernel<R>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream,
-                         (const int*)wd.steps, si, (const int*)wd.ops, (cw<R>*)cst);
-    } else if (si < (int)wd.fn.size() && wd.fn[si]) {
-      // generated kernel of this step
-      void* a_mem = mem;
-      const void* a_cst = cst;
-      const void* a_packed = packed;
-      unsigned long long a_nbs = (unsigned long long)n_bs, a_sb = s_begin, a_ns = n_s, a_ni = n_items;
-      int a_g0 = first_group;
-      unsigned long long a_ge = group_elems;
-      void* a_res = res;
-      void* a_gres = gres;
-      void* args[] = {&a_mem, &a_cst, &a_packed, &a_nbs, &a_sb, &a_ns, &a_ni, &a_g0, &a_ge, &a_res, &a_gres};
-      const unsigned long long blocks = (wd.tiles[si] + 3) / 4;
-      if (hipModuleLaunchKernel((hipFunction_t)wd.fn[si], (unsigned)blocks, (unsigned)n_groups, 1, 256, 1, 1, 0,
-                                stream, args, nullptr) != hipSuccess)
+  if (!wd.levels.empty()) {
+    // generated kernels: one launch per level of independent steps
+    void* a_mem = mem;
+    const void* a_cst = cst;
+    const void* a_packed = packed;
+    unsigned long long a_ge = group_elems, a_sb = s_begin, a_ns = n_s, a_ni = n_items, a_nbs = (unsigned)n_bs;
+    int a_g0 = first_group;
+    int a_log2 = (n_s & (n_s - 1)) == 0 ? __builtin_ctzll(n_s) : -1;
+    void* a_res = res;
+    void* a_gres = gres;
+    void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
+    for (const WideDev::Level& lv : wd.levels)
+      if (hipModuleLaunchKernel((hipFunction_t)lv.fn, (unsigned)lv.blocks, (unsigned)n_groups, 1, 256, 1, 1, 0, stream,
+                                args, nullptr) != hipSuccess)
         return -6;
-    } else {
-      const int cl = wide_cpw_log2(r);
-      const uint64_t waves = ((1ull << r) + (1ull << cl) - 1) >> cl;
-      hipLaunchKernelGGL(wide_step_kernel<R>, dim3((unsigned)((waves + 3) / 4), (unsigned)n_groups), dim3(256), 0,
-                         stream, (const int*)wd.steps, si, (const int*)wd.ops, (const cw<R>*)cst, (cw<R>*)mem,
-                         group_elems, first_group, packed, n_bs, s_begin, n_s, n_items, (cw<R>*)res, (cw<R>*)gres,
-                         cl);
-    }
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+  }
+  for (int si = 0; si < wd.n_steps; ++si) {
+    const int r = wd.host_steps[8 * si + 2], is_const = wd.host_steps[8 * si + 7];
+    if (is_const) continue;
+    const int cl = wide_cpw_log2(r);
+    const uint64_t waves = ((1ull << r) + (1ull << cl) - 1) >> cl;
+    hipLaunchKernelGGL(wide_step_kernel<R>, dim3((unsigned)((waves + 3) / 4), (unsigned)n_groups), dim3(256), 0,
+                       stream, (const int*)wd.steps, si, (const int*)wd.ops, (const cw<R>*)cst, (cw<R>*)mem,
+                       group_elems, first_group, packed, n_bs, s_begin, n_s, n_items, (cw<R>*)res, (cw<R>*)gres, cl);
   }
   return hipGetLastError() == hipSuccess ? 0 : -6;
 }

@@ -479,9 +479,25 @@ def test_autotune_keeps_results(config2):
         note("autotune prec", prec, "chose waves", w, "stats waves", p.stats()["waves"])
         assert w in (1, 2, 4, 8) and p.stats()["waves"] == w
         assert nerr(p.amplitudes(bits), ref, 25).max() <= tol
-    for w in (2, 4):
-        # every forced cut that the tree allows gives the same amplitudes
-        pass
+
+
+@pytest.mark.parametrize("flags", [0, q.QGM_PLAN_LATENCY])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("prec,tol", [(q.QGM_C64, C64_TOL), (q.QGM_C128, C128_TOL), (q.QGM_BF16X3, BF16X3_TOL)])
+def test_multiwave_schedules(config2, waves, prec, tol, flags):
+    """The generated kernel with its item tree list-scheduled on 1, 2, 4 or 8
+    wavefronts (tensors crossing wavefronts through LDS) against the oracle;
+    a schedule whose exchange does not fit in LDS falls back to fewer."""
+    text, bits, ref = config2
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.5, flags=flags)
+    p = q.Plan(c, sl, order, prec=prec, engine=q.QGM_ENGINE_GENERATED, waves=waves)
+    got_w = p.stats()["waves"]
+    note("5x5x20 planner flags", flags, "prec", prec, "waves asked", waves, "got", got_w)
+    assert got_w <= waves
+    got = p.amplitudes(bits)
+    assert np.all(np.isfinite(got))  # a wait that gave up would flag the block with NaN
+    assert nerr(got, ref, 25).max() <= tol
 
 
 @pytest.mark.parametrize("engine", ENGINES)

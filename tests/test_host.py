@@ -178,6 +178,16 @@ def test_planner_reorder_flag_gives_valid_plans():
         assert width <= 8
 
 
+def test_multiwave_schedules_exist():
+    """List schedules of the 5x5x20 item tree on 2, 4 and 8 wavefronts pass
+    the plan-time simulation of their waits and fit in LDS (complex64)."""
+    c = q.Circuit(generate_circuit(5, 20, 0))
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=q.QGM_PLAN_LATENCY)
+    for w in (2, 4, 8):
+        st = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED, waves=w).stats()
+        assert st["waves"] == w
+
+
 def test_generated_source_shapes():
     """The generated kernel of a small plan is cut across wavefronts only for
     amplitude programs (gradient programs are not trees)."""
@@ -185,7 +195,7 @@ def test_generated_source_shapes():
     c = q.Circuit(text)
     sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
     amp = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED).stats()
-    assert amp["engine"] == q.QGM_ENGINE_GENERATED and amp["waves"] in (1, 2, 4)
+    assert amp["engine"] == q.QGM_ENGINE_GENERATED and amp["waves"] in (1, 2, 4, 8)
     rz = generate_circuit(4, 10, 3, rz=True)
     c2 = q.Circuit(rz)
     sl2, order2 = c2.plan_slices(k_req=2, time_budget_s=0.2)
