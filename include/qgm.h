@@ -72,8 +72,8 @@ typedef struct {
   int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
   int32_t gradient;      /* 1 = also compile the reverse-mode steps for d alpha / d theta */
   int32_t waves;         /* GENERATED: wavefronts per block to cut the item tree across
-                            (1, 2, 4 or 8; fewer when the tree or the LDS budget does not
-                            allow it); 0 = chosen by the cost model */
+                            (1, 2, 4 or 8; fewer when the exchange does not fit in LDS or
+                            the program is not a tree); 0 = chosen by the cost model */
   int32_t reserved[5];
 } qgm_plan_opts;
 

@@ -699,15 +699,11 @@ qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void*
     return QGM_OK;
   };
   if ((s = time_current(best.ms))) return s;
-  // wavefront counts and exchange-cost estimates of the schedule
-  std::vector<std::pair<int, double>> grid{{1, 0.0}};
-  for (int w : {2, 4, 8})
-    for (double comm : {300.0, kDefaultExchangeCost, 3000.0}) grid.push_back({w, comm});
-  for (auto [w, comm] : grid) {
-    if (w == best.waves && (w == 1 || comm == kDefaultExchangeCost)) continue;  // the current kernel
+  for (int w : {1, 2, 4, 8}) {
+    if (w == best.waves) continue;  // the current kernel
     int got = 0;
-    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w, comm);
-    if (got != w) continue;  // no schedule on w wavefronts fits for the plan
+    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w);
+    if (got != w) continue;  // no cut on w wavefronts fits for the plan
     Variant v;
     std::string jerr;
     if (!jit_compile(src, "qgm_chain.hip", v.code, jerr)) continue;

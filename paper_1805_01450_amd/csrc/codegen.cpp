@@ -16,13 +16,14 @@
 //     same literals, just before their first use, so those without angles
 //     fold at compile time.
 //   * In every product of an item step an item tensor comes first.
-//   * Amplitude programs form a tree (every tensor has one consumer).  Its
-//     steps are list-scheduled onto the wavefronts of a block, which work on
-//     the same 64 items; a tensor consumed on another wavefront crosses
-//     through LDS with a release/acquire publish counter per wavefront.
+//   * Amplitude programs form a tree (every tensor has one consumer).  The
+//     tree is cut into pieces that run on different wavefronts of the block
+//     for the same 64 items; the piece roots go through LDS to the wavefront
+//     that runs the top of the tree after a barrier.
 //   * When the block's 64 items are 64 consecutive slices of one bitstring
 //     the block sums them (FP64, compensated butterfly) into one partial.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <functional>
 #include <map>
@@ -131,257 +132,220 @@ class Branch {
   int next_const = 0;
 };
 
-// Multi-wavefront schedule of the item steps.  Every step runs on one
-// wavefront of the block for the block's 64 items.  A tensor consumed on
-// another wavefront goes through LDS: the producer writes it, then raises its
-// publish counter (release); the consumer waits until the counter reaches
-// the tensor's publish number (acquire) and reads it.  Each wavefront runs
-// its steps in the order they were scheduled, which is a topological order
-// of the whole program, so every wait is for a step that precedes the
-// waiting one in that order; schedules are also checked by simulating the
-// waits before any code is emitted.
+// Multi-wavefront schedule of the item steps (amplitude programs are trees:
+// every tensor has one consumer).  The tree is cut into pieces (subtrees)
+// that run on the wavefronts of the block for the same 64 items; the piece
+// roots go to LDS, one block barrier follows, and one wavefront runs the
+// steps above the cut (the top) reading them.  Point-to-point exchange
+// through LDS flags, and list schedules with many exchanges, measured slower
+// than this single barrier on gfx950 for these trees.
 struct Sched {
   int waves = 1;
   std::vector<int> wave_of;           // per step index (item steps); -1 otherwise
   std::vector<std::vector<int>> seq;  // per wavefront: step indices in execution order
-  struct Xch {
-    int slot, wave, number;           // LDS element offset, producer, publish number (1-based)
-  };
-  std::map<int, Xch> xch;             // exchanged tensor id -> LDS slot and publish number
+  std::vector<char> top;              // per step: runs after the barrier on top_wave
+  int top_wave = 0;
+  std::map<int, int> xch;             // piece root tensor id -> LDS element offset
   int lds_elems = 0;
   double makespan = 0;
 };
 
-// Earliest-start list scheduling: steps in order of decreasing bottom level
-// (the longest cost path from the step to the end of the program); each goes
-// to the wavefront where it can start first, counting a fixed latency plus a
-// per-element cost for operands that cross wavefronts.
-Sched schedule_waves(const Program& prog, int W, double comm, double per_elem, size_t max_lds_elems) {
+// Estimated VALU instructions of one item step as generated: a product term
+// with an exact-zero gate entry vanishes, a factor +-1 or +-i is free, a
+// real or imaginary constant costs 2, any other factor 4 (a complex multiply
+// is two multiplies and two fused multiply-adds), each added term 2; a leaf
+// costs two selects per element whose alternatives differ.
+double step_cost(const Program& prog, const Step& st) {
+  auto raw_kind = [&](int k) -> int {  // 0 zero, 1 unit, 2 real/imaginary, 3 general
+    if (k >= prog.n_raw || prog.raw_param[k] >= 0) return 3;
+    const double re = prog.raw[2 * k], im = prog.raw[2 * k + 1];
+    if (re == 0 && im == 0) return 0;
+    if ((std::fabs(re) == 1 && im == 0) || (re == 0 && std::fabs(im) == 1)) return 1;
+    if (re == 0 || im == 0) return 2;
+    return 3;
+  };
+  if (st.kind == ST_LEAF) {
+    const Leaf& L = prog.leaves[st.leaf];
+    double c = 0;
+    if (L.ndep == 0) return 0;
+    for (int e = 0; e < (1 << st.r); ++e) {
+      const int base = L.table + ((e & 1) ? L.free_stride[0] : 0) + ((e & 2) ? L.free_stride[1] : 0);
+      const int alt = base + L.dep_stride[0] + (L.ndep > 1 ? L.dep_stride[1] : 0);
+      c += (prog.raw[2 * base] != prog.raw[2 * alt] || prog.raw[2 * base + 1] != prog.raw[2 * alt + 1]) ? 2.0 : 0.0;
+      if (L.ndep > 1) c += 2.0;
+    }
+    return c;
+  }
+  std::map<int, int> bitpos, from_s;
+  for (int j = 0; j < st.r; ++j) {
+    bitpos[st.out_vars[j]] = j;
+    from_s[st.out_vars[j]] = 0;
+  }
+  for (int j = 0; j < st.ns; ++j) {
+    bitpos[st.sum_vars[j]] = j;
+    from_s[st.sum_vars[j]] = 1;
+  }
+  double c = 0;
+  for (int o = 0; o < (1 << st.r); ++o) {
+    int terms = 0;
+    for (int sm = 0; sm < (1 << st.ns); ++sm) {
+      double t = 0;
+      bool zero = false;
+      int n_item = 0;
+      for (const Operand& op : st.opnd) {
+        int e = 0;
+        for (size_t j = 0; j < op.vars.size(); ++j) {
+          const int u = op.vars[j];
+          e |= (from_s[u] ? (sm >> bitpos[u]) & 1 : (o >> bitpos[u]) & 1) << j;
+        }
+        if (!op.is_const) {
+          if (n_item++) t += 4;
+          continue;
+        }
+        const int kind = raw_kind(op.storage + e);
+        if (kind == 0) zero = true;
+        t += kind == 3 ? 4 : kind == 2 ? 2 : 0;
+      }
+      if (zero) continue;
+      c += t;
+      ++terms;
+    }
+    c += 2.0 * std::max(0, terms - 1);
+  }
+  return c;
+}
+
+// Cut on W wavefronts: the largest subtrees are split until every piece is
+// at most total / W; pieces (leaves excepted) are packed onto the
+// wavefronts, largest first onto the least loaded; the top runs on the
+// least loaded one after the barrier, with the leaves it reads.  Returns
+// waves = 0 when the program is not a tree.
+Sched schedule_cut(const Program& prog, int W) {
   Sched sc;
   const int n = (int)prog.steps.size();
-  sc.wave_of.assign(n, -1);
+  std::vector<double> cost(n, 0), sub(n, 0);
+  std::vector<std::vector<int>> preds(n);
+  std::vector<int> succ(n, -1);
   std::map<int, int> producer;
-  std::vector<std::vector<int>> preds(n), succs(n);
-  std::vector<double> cost(n, 0), bl(n, 0);
+  int root = -1;
   for (int i = prog.n_const_steps; i < n; ++i) {
     const Step& st = prog.steps[i];
+    if (st.kind == ST_GRAD) return sc;
+    if (st.kind == ST_FINAL) root = i;
     if (st.kind == ST_LEAF || st.kind == ST_ELIM) producer[st.out_tid] = i;
-    cost[i] = st.kind == ST_LEAF ? (double)(1 << st.r) * 2 : st.flops;
+    cost[i] = step_cost(prog, st);
+    sub[i] = cost[i];
     for (const Operand& op : st.opnd)
       if (!op.is_const) {
         const int p = producer.at(op.tid);
+        if (succ[p] >= 0) return sc;  // a tensor with two consumers: not a tree
+        succ[p] = i;
         preds[i].push_back(p);
-        succs[p].push_back(i);
+        sub[i] += sub[p];
       }
   }
-  for (int i = n - 1; i >= prog.n_const_steps; --i) {
-    double m = 0;
-    for (int s : succs[i]) m = std::max(m, bl[s]);
-    bl[i] = cost[i] + m;
-  }
-  std::vector<int> pending(n, 0);
-  std::vector<int> ready;
-  for (int i = prog.n_const_steps; i < n; ++i) {
-    pending[i] = (int)preds[i].size();
-    if (!pending[i]) ready.push_back(i);
-  }
-  std::vector<double> fin(n, 0), free_at(W, 0);
+  if (root < 0) return sc;
   sc.waves = W;
+  sc.wave_of.assign(n, -1);
   sc.seq.assign(W, {});
-  std::vector<int> n_pub(W, 0);
-  while (!ready.empty()) {
-    auto it = std::max_element(ready.begin(), ready.end(), [&](int a, int b) {
-      return bl[a] < bl[b] || (bl[a] == bl[b] && a > b);
-    });
-    const int i = *it;
-    ready.erase(it);
-    int best_w = -1;
-    double best_start = 0, best_local = 0;
-    for (int w = 0; w < W; ++w) {
-      double start = free_at[w], xtra = 0, local = 0;
-      for (int p : preds[i]) {
-        if (sc.wave_of[p] == w) {
-          start = std::max(start, fin[p]);
-          local += cost[p];
-        } else {
-          const double e = (double)(1 << prog.steps[p].r);
-          start = std::max(start, fin[p] + comm + per_elem * e);
-          xtra += per_elem * e;
-        }
-      }
-      start += xtra;
-      if (best_w < 0 || start < best_start || (start == best_start && local > best_local)) {
-        best_w = w;
-        best_start = start;
-        best_local = local;
-      }
-    }
-    sc.wave_of[i] = best_w;
-    sc.seq[best_w].push_back(i);
-    fin[i] = best_start + cost[i];
-    free_at[best_w] = fin[i];
-    sc.makespan = std::max(sc.makespan, fin[i]);
-    for (int p : preds[i])
-      if (sc.wave_of[p] != best_w && !sc.xch.count(prog.steps[p].out_tid))
-        sc.xch[prog.steps[p].out_tid] = {-1, sc.wave_of[p], 0};
-    for (int s : succs[i])
-      if (--pending[s] == 0) ready.push_back(s);
-  }
-  // publish numbers follow each producer's execution order
-  for (int w = 0; w < W; ++w)
-    for (int i : sc.seq[w]) {
-      const Step& st = prog.steps[i];
-      auto x = sc.xch.find(st.out_tid);
-      if ((st.kind == ST_LEAF || st.kind == ST_ELIM) && x != sc.xch.end()) x->second.number = ++n_pub[w];
-    }
-  (void)max_lds_elems;
-  return sc;
-}
-
-// Simulates the wavefronts' waits and assigns the LDS slots.  Returns false
-// unless every wavefront runs to the end (no wait can block for ever) and
-// every operand is available where it is read (produced earlier on the same
-// wavefront, or published by another).  Slots are reused: a tensor may take
-// the slot of one already read when that read happens before the write in
-// every execution, which vector clocks over the publish/wait edges decide
-// (the clock of a wavefront counts the steps of each wavefront known to be
-// complete; a wait merges in the clock the producer had when publishing).
-bool finalize_schedule(const Program& prog, Sched& sc) {
-  const int W = sc.waves;
-  std::map<int, int> producer;
-  for (int i = prog.n_const_steps; i < (int)prog.steps.size(); ++i) {
-    const Step& st = prog.steps[i];
-    if (st.kind == ST_LEAF || st.kind == ST_ELIM) producer[st.out_tid] = i;
-  }
-  std::vector<size_t> pos(W, 0);
-  std::vector<int> published(W, 0);
-  std::vector<char> done(prog.steps.size(), 0);
-  std::vector<std::vector<int>> vc(W, std::vector<int>(W, 0));
-  std::vector<std::vector<std::vector<int>>> pub_vc(W);  // per wave, per publish: clock
-  std::vector<std::map<int, int>> waited(W);            // as the emitted code: max number waited
-  struct Slot {
-    int offset, size, tid;  // tid: current occupant
-  };
-  std::vector<Slot> slots;
-  std::map<int, std::pair<int, int>> read_at;  // tensor id -> (wave, position) of its read
-  sc.lds_elems = 0;
-  size_t left = 0;
-  for (int w = 0; w < W; ++w) left += sc.seq[w].size();
+  sc.top.assign(n, 0);
+  const double target = sub[root] / W;
+  std::vector<int> front{root};
   for (;;) {
-    bool moved = false;
-    for (int w = 0; w < W; ++w) {
-      while (pos[w] < sc.seq[w].size()) {
-        const int i = sc.seq[w][pos[w]];
-        const Step& st = prog.steps[i];
-        bool ok = true;
-        for (const Operand& op : st.opnd) {
-          if (op.is_const) continue;
-          const int p = producer.at(op.tid);
-          if (sc.wave_of[p] == w) {
-            if (!done[p]) return false;  // same wavefront: must come earlier
-          } else {
-            auto x = sc.xch.find(op.tid);
-            if (x == sc.xch.end() || x->second.wave != sc.wave_of[p]) return false;
-            if (published[x->second.wave] < x->second.number) ok = false;
-          }
-        }
-        if (!ok) break;
-        // the waits and reads of this step
-        for (const Operand& op : st.opnd) {
-          if (op.is_const) continue;
-          auto x = sc.xch.find(op.tid);
-          if (x == sc.xch.end() || x->second.wave == w) continue;
-          const int q = x->second.wave, nmb = x->second.number;
-          if (waited[w][q] < nmb) {
-            waited[w][q] = nmb;
-            for (int v = 0; v < W; ++v) vc[w][v] = std::max(vc[w][v], pub_vc[q][nmb - 1][v]);
-          }
-          read_at[op.tid] = {w, (int)pos[w]};
-        }
-        done[i] = 1;
-        vc[w][w] = (int)pos[w] + 1;
-        if ((st.kind == ST_LEAF || st.kind == ST_ELIM) && sc.xch.count(st.out_tid)) {
-          Sched::Xch& x = sc.xch.at(st.out_tid);
-          if (x.number != published[w] + 1) return false;
-          // the smallest slot large enough whose occupant's read happened
-          // before this write
-          const int size = 1 << st.r;
-          int chosen = -1;
-          for (size_t k = 0; k < slots.size(); ++k) {
-            if (slots[k].size < size || (chosen >= 0 && slots[k].size >= slots[chosen].size)) continue;
-            auto r = read_at.find(slots[k].tid);
-            if (r == read_at.end()) continue;
-            if (vc[w][r->second.first] >= r->second.second + 1) chosen = (int)k;
-          }
-          if (chosen < 0) {
-            slots.push_back({sc.lds_elems, size, st.out_tid});
-            sc.lds_elems += size;
-            chosen = (int)slots.size() - 1;
-          }
-          slots[chosen].tid = st.out_tid;
-          x.slot = slots[chosen].offset;
-          published[w]++;
-          pub_vc[w].push_back(vc[w]);
-        }
-        ++pos[w];
-        --left;
-        moved = true;
-      }
-    }
-    if (!left) return true;
-    if (!moved) return false;  // every unfinished wavefront waits
+    auto it = std::max_element(front.begin(), front.end(), [&](int a, int b) { return sub[a] < sub[b]; });
+    const int f = *it;
+    if (sub[f] <= 1.05 * target || preds[f].empty()) break;
+    front.erase(it);
+    sc.top[f] = 1;
+    for (int p : preds[f]) front.push_back(p);
   }
+  std::sort(front.begin(), front.end(), [&](int a, int b) { return sub[a] > sub[b]; });
+  std::vector<double> bins(W, 0);
+  std::vector<int> piece_wave(n, -1);
+  for (int f : front) {
+    if (prog.steps[f].kind == ST_LEAF) continue;
+    const int b = (int)(std::min_element(bins.begin(), bins.end()) - bins.begin());
+    bins[b] += sub[f];
+    piece_wave[f] = b;
+  }
+  sc.top_wave = (int)(std::min_element(bins.begin(), bins.end()) - bins.begin());
+  for (int f : front)
+    if (prog.steps[f].kind == ST_LEAF) sc.top[f] = 1;  // leaves under the cut are read by the top itself
+  for (int i = n - 1; i >= prog.n_const_steps; --i) {
+    if (sc.top[i]) {
+      sc.wave_of[i] = sc.top_wave;
+      continue;
+    }
+    sc.wave_of[i] = piece_wave[i] >= 0 ? piece_wave[i] : sc.wave_of[succ[i]];
+  }
+  for (int i = prog.n_const_steps; i < n; ++i)
+    if (!sc.top[i]) sc.seq[sc.wave_of[i]].push_back(i);
+  for (int i = prog.n_const_steps; i < n; ++i)
+    if (sc.top[i]) sc.seq[sc.top_wave].push_back(i);
+  // LDS slots of the piece roots
+  for (int i = prog.n_const_steps; i < n; ++i) {
+    if (sc.top[i]) continue;
+    if (succ[i] >= 0 && sc.top[succ[i]]) {
+      sc.xch[prog.steps[i].out_tid] = sc.lds_elems;
+      sc.lds_elems += 1 << prog.steps[i].r;
+    }
+  }
+  // estimated time: slowest wavefront's pieces (plus root writes), one
+  // exchange latency, the root reads and the top
+  const double kBarrier = 200.0, kPerElem = 2.0;
+  double bar = 0, topc = 0;
+  for (int w = 0; w < W; ++w) {
+    double c = 0;
+    for (int i : sc.seq[w]) {
+      if (sc.top[i]) {
+        topc += cost[i];
+        continue;
+      }
+      c += cost[i];
+      if (sc.xch.count(prog.steps[i].out_tid)) c += kPerElem * (double)(1 << prog.steps[i].r);
+    }
+    bar = std::max(bar, c);
+  }
+  sc.makespan = bar + kBarrier + kPerElem * sc.lds_elems + topc;
+  return sc;
 }
 
 // Wavefront count: force_waves when given (falling back to fewer when the
 // exchange does not fit in LDS), else the count with the shortest estimated
-// time that clearly beats the next smaller one.
-Sched choose_schedule(const Program& prog, size_t elem_bytes, int force_waves, double comm0) {
+// time that beats the next smaller one by 10 %.
+Sched choose_schedule(const Program& prog, size_t elem_bytes, int force_waves) {
   Sched one;
   one.waves = 1;
   one.wave_of.assign(prog.steps.size(), -1);
   one.seq.assign(1, {});
+  one.top.assign(prog.steps.size(), 0);
   for (int i = prog.n_const_steps; i < (int)prog.steps.size(); ++i) {
     one.wave_of[i] = 0;
     one.seq[0].push_back(i);
+    one.makespan += step_cost(prog, prog.steps[i]);
   }
-  // gradient programs are not trees (a tensor may feed several steps)
-  for (const Step& st : prog.steps)
-    if (st.kind == ST_GRAD) return one;
+  if (force_waves == 1) return one;
   // exchange slots in LDS, 64 lanes per element (gfx950 gives a block up to
   // 160 KiB; multi-wavefront schedules are for batches of few blocks, where
   // blocks per CU do not matter)
   const size_t kMaxExchangeBytes = 128 * 1024;
   const size_t max_elems = kMaxExchangeBytes / (64 * elem_bytes);
-  double total = 0;
-  for (int i = prog.n_const_steps; i < (int)prog.steps.size(); ++i) {
-    const Step& st = prog.steps[i];
-    total += st.kind == ST_LEAF ? (double)(1 << st.r) * 2 : st.flops;
-  }
   Sched best = one;
-  best.makespan = total;
   const int lo = force_waves > 1 ? force_waves : 2, hi = force_waves > 1 ? force_waves : 8;
   for (int w = lo; w <= hi; w *= 2) {
-    // exchange latency and per-element cost in flops; a higher latency
-    // estimate trades parallelism for fewer exchanges when LDS is short
-    for (double comm : {comm0, 2.5 * comm0, 6.0 * comm0}) {
-      Sched sc = schedule_waves(prog, w, comm, 4.0, max_elems);
-      if (!finalize_schedule(prog, sc) || (size_t)sc.lds_elems > max_elems) continue;
-      if (force_waves > 1 ? (best.waves != w || sc.makespan < best.makespan) : sc.makespan < 0.85 * best.makespan)
-        best = sc;
-      break;
-    }
+    Sched sc = schedule_cut(prog, w);
+    if (sc.waves != w || (size_t)sc.lds_elems > max_elems) continue;
+    if (force_waves > 1 || sc.makespan < 0.9 * best.makespan) best = sc;
   }
   return best;
 }
 
 }  // namespace
 
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves,
-                                  double comm) {
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves) {
   std::ostringstream head, o;
   const char* R = prec == 0 ? "double" : "float";
-  const Sched sch = choose_schedule(prog, prec == 0 ? 16 : 8, force_waves, comm > 0 ? comm : kDefaultExchangeCost);
+  const Sched sch = choose_schedule(prog, prec == 0 ? 16 : 8, force_waves);
   // BF16x3: products from bf16 hi/lo splits with FP32 accumulation
   const std::string mul = prec == 2
       ? std::string("static __device__ __forceinline__ float bh(float x) { unsigned u = __float_as_uint(x); "
@@ -427,13 +391,6 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
           "const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false); "
           "a = __longlong_as_double(((long long)h[0] << 32) | l[0]); "
           "b = __longlong_as_double(((long long)h[1] << 32) | l[1]); }\n"
-       // cross-wavefront exchange: publish counters in LDS; a wait gives up
-       // (and flags the block's result as NaN) after about a second
-       << "static __device__ __forceinline__ void xwait(unsigned* c, unsigned n, unsigned* err) { unsigned it = 0; "
-          "while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < n) "
-          "if (++it > (1u << 24)) { *err = 1u; break; } }\n"
-       << "static __device__ __forceinline__ void xpub(unsigned* c, unsigned n) { "
-          "__hip_atomic_store(c, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }\n"
        << "static __device__ __forceinline__ void wave_sum(double& s, double& c) {\n"
           "  two_add(s, c, dppd<0xB1>(s), dppd<0xB1>(c));\n"    // quad_perm [1,0,3,2]: lane ^ 1
           "  two_add(s, c, dppd<0x4E>(s), dppd<0x4E>(c));\n"    // quad_perm [2,3,0,1]: lane ^ 2
@@ -494,14 +451,8 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
   const std::string pack_bits =
       "  if (fused) {\n    asm volatile(\"\" : \"+v\"(xlane));\n"
       "    xb = __ballot(lane < n_qubits && (xlane & 1u));\n  }\n";
-  // LDS exchange of the multi-wavefront schedule: slots, per-wavefront
-  // publish counters (zeroed before the barrier below), error flag
-  if (W > 1)
-    head << "  __shared__ C2 xch[" << std::max(1, sch.lds_elems) << "][64];\n"
-         << "  __shared__ unsigned xcnt[" << W << "];\n"
-         << "  __shared__ unsigned xerr;\n"
-         << "  if (lane == 0) xcnt[wave] = 0u;\n"
-         << "  if (threadIdx.x == 0) xerr = 0u;\n";
+  // LDS slots of the piece roots of the multi-wavefront schedule
+  if (W > 1) head << "  __shared__ C2 xch[" << std::max(1, sch.lds_elems) << "][64];\n";
   int n_params = 0;
   for (int k = 0; k < prog.n_raw; ++k) n_params = std::max(n_params, prog.raw_param[k] + 1);
   if (n_params > 0) {
@@ -518,7 +469,7 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
          << "    ptab[4 * j + 3] = C2{(R)(-0.5 * sn), (R)(0.5 * cs)};\n"
          << "  }\n";
   }
-  if (n_params > 0 || W > 1) head << "  __syncthreads();\n";
+  if (n_params > 0) head << "  __syncthreads();\n";
 
   auto emit_step = [&](Branch& br, const Step& st) {
     if (st.kind == ST_LEAF) {
@@ -591,7 +542,6 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
       packed = true;
     }
   };
-  int final_wave = 0;
   if (W == 1) {
     Branch br(prog, o);
     for (int i : seq) {
@@ -603,35 +553,37 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
       o << "  if (wave == " << w << ") {\n";
       Branch br(prog, o);
       packed = false;
-      std::map<int, int> waited;  // producer wavefront -> publish number already waited for
       for (int i : sch.seq[w]) {
+        if (sch.top[i]) continue;
         const Step& st = prog.steps[i];
         need_bits(i);
-        // operands from other wavefronts: wait for their publication, read once
-        for (const Operand& op : st.opnd) {
-          if (op.is_const) continue;
-          auto x = sch.xch.find(op.tid);
-          if (x == sch.xch.end() || x->second.wave == w) continue;
-          if (waited[x->second.wave] < x->second.number) {
-            o << "  xwait(&xcnt[" << x->second.wave << "], " << x->second.number << "u, &xerr);\n";
-            waited[x->second.wave] = x->second.number;
-          }
-          for (int e = 0; e < (1 << op.vars.size()); ++e)
-            o << "  const C2 " << tvar(op.tid, e) << " = xch[" << x->second.slot + e << "][lane];\n";
-        }
         emit_step(br, st);
-        if (st.kind == ST_FINAL) final_wave = w;
         auto x = sch.xch.find(st.out_tid);
-        if ((st.kind == ST_LEAF || st.kind == ST_ELIM) && x != sch.xch.end()) {
+        if (x != sch.xch.end())
           for (int e = 0; e < (1 << st.r); ++e)
-            o << "  xch[" << x->second.slot + e << "][lane] = " << tvar(st.out_tid, e) << ";\n";
-          o << "  xpub(&xcnt[" << w << "], " << x->second.number << "u);\n";
-        }
+            o << "  xch[" << x->second + e << "][lane] = " << tvar(st.out_tid, e) << ";\n";
       }
+      // the top wavefront continues after the barrier and needs the row there
+      if (!packed && w == sch.top_wave) o << pack_bits;
       o << "  }\n";
     }
-    o << "  if (wave != " << final_wave << ") return;\n"
-      << "  if (xerr) amp.x = amp.y = __builtin_nanf(\"\");\n";
+    o << "  __syncthreads();\n"
+      << "  if (wave != " << sch.top_wave << ") return;\n";
+    Branch br(prog, o);
+    std::set<int> loaded;
+    for (int i : sch.seq[sch.top_wave]) {
+      if (!sch.top[i]) continue;
+      const Step& st = prog.steps[i];
+      for (const Operand& op : st.opnd) {
+        if (op.is_const || loaded.count(op.tid)) continue;
+        auto x = sch.xch.find(op.tid);
+        if (x == sch.xch.end()) continue;
+        loaded.insert(op.tid);
+        for (int e = 0; e < (1 << op.vars.size()); ++e)
+          o << "  const C2 " << tvar(op.tid, e) << " = xch[" << x->second + e << "][lane];\n";
+      }
+      emit_step(br, st);
+    }
   }
   // fused slice sum of the block's 64 slices: the compensated butterfly that
   // the reduction kernels use for each chunk of 64 slices

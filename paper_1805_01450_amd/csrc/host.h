@@ -181,11 +181,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
 // *waves_out gets the wavefronts per block (the item tree may be cut across
 // several wavefronts that run the same 64 items).
 // force_waves > 0 requests that many wavefronts (0 = cost model).
-// comm: estimated cost, in flops, of one tensor crossing wavefronts through
-// LDS (0 = kDefaultExchangeCost); the autotuner tries several.
-constexpr double kDefaultExchangeCost = 1000.0;
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0,
-                                  double comm = 0);
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0);
 // hiprtc compilation of `src` for gfx950 into a code object.
 bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
 

@@ -183,7 +183,7 @@ def test_multiwave_schedules_exist():
     the plan-time simulation of their waits and fit in LDS (complex64)."""
     c = q.Circuit(generate_circuit(5, 20, 0))
     sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=q.QGM_PLAN_LATENCY)
-    for w in (2, 4, 8):
+    for w in (1, 2, 4, 8):
         st = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED, waves=w).stats()
         assert st["waves"] == w
 
