@@ -301,6 +301,30 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
                   (o.engine == QGM_ENGINE_AUTO && p->prog.has_optab && p->prog.item_elems <= reg_limit);
   bool want_wide = o.engine == QGM_ENGINE_WIDE || (o.engine == QGM_ENGINE_AUTO && !p->prog.has_optab);
   p->engine = QGM_ENGINE_INTERPRETER;
+  if (want_wide && !o.gradient) {
+    // the wide engine loads constants from memory: their factors are
+    // combined per step first (a different grouping of the same products)
+    Program combined;
+    if (compile_program(p->net, sv, ov, combined, err, code, false, true)) p->prog = std::move(combined);
+  }
+  if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
+    // debugging aid: the compiled step list, one step per line
+    if (FILE* f = std::fopen((std::string(dir) + "/qgm_program_" + std::to_string((uintptr_t)p) + ".txt").c_str(), "w")) {
+      for (size_t i = 0; i < p->prog.steps.size(); ++i) {
+        const Step& st = p->prog.steps[i];
+        std::fprintf(f, "%zu kind %d const %d r %d ns %d m %d out_tid %d |", i, st.kind, st.is_const, st.r, st.ns, st.m,
+                     st.out_tid);
+        for (int v : st.out_vars) std::fprintf(f, " o%d", v);
+        for (int v : st.sum_vars) std::fprintf(f, " s%d", v);
+        for (const Operand& op : st.opnd) {
+          std::fprintf(f, " | %s%d:", op.is_const ? "c" : "t", op.tid);
+          for (int v : op.vars) std::fprintf(f, " %d", v);
+        }
+        std::fprintf(f, "\n");
+      }
+      std::fclose(f);
+    }
+  }
   if (want_wide) {
     std::string werr;
     if (!encode_wide(p->prog, p->wide, werr)) {
@@ -313,6 +337,13 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     if (!std::getenv("QGM_WIDE_PREBUILT")) {
       auto t0 = std::chrono::steady_clock::now();
       std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels);
+      if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
+        // debugging aid: keep the generated source
+        if (FILE* f = std::fopen((std::string(dir) + "/qgm_wide_" + std::to_string((uintptr_t)p) + ".hip").c_str(), "w")) {
+          std::fwrite(src.data(), 1, src.size(), f);
+          std::fclose(f);
+        }
+      }
       std::string jerr;
       if (!jit_compile(src, "qgm_wide.hip", p->wide_code, jerr)) {
         p->wide_code.clear();

@@ -116,10 +116,37 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       if (level[si] != lev) continue;
       const int32_t* sr = &wide.steps[8 * si];
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
-      // tile width: unrolled loads per wavefront stay moderate, tiles stay many
-      int L = std::min(r, 4);
-      while (L > 0 && ((m << (L + ns)) > 192)) --L;
-      while (L > 0 && r - L < 12 && (1 << (r - L)) < 2048) --L;
+      std::vector<const int32_t*> rec(m);
+      for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+      // Iteration order of the output bits: those that fewer item operands
+      // depend on come first (inside the tile, then across neighbouring
+      // wavefronts), so an operand row is reused within a tile or soon after
+      // by the next tiles while it is still in cache; the bits every large
+      // operand shares vary slowest.  perm[k] is the output bit at position k.
+      std::vector<int> perm(r), weight(r, 0);
+      for (int j = 0; j < r; ++j) {
+        perm[j] = j;
+        for (int i = 0; i < m; ++i) weight[j] += rec[i][0] == WOP_ITEM && rec[i][16 + j] != 0;
+      }
+      std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return weight[x] < weight[y]; });
+      // Tile: the first L bits of perm.  A wavefront keeps 2^L accumulators
+      // (64 items each) and, per summed index, loads each operand row the
+      // tile needs once: a register-blocked contraction.  L grows while the
+      // accumulators and the rows per summed index stay within budget and
+      // enough tiles remain to fill the GPU.
+      auto rows_for = [&](int L) {
+        int n = 0;
+        for (int i = 0; i < m; ++i) {
+          int d = 0;
+          for (int k2 = 0; k2 < L; ++k2) d += rec[i][16 + perm[k2]] != 0;
+          n += 1 << d;
+        }
+        return n;
+      };
+      const int max_acc = prec == 0 ? 32 : 64, max_rows = 40;
+      int L = 0;
+      while (L < r && (2 << L) <= max_acc && rows_for(L + 1) <= max_rows && (r - L - 1 >= 13 || (1 << (r - L - 1)) >= 2048))
+        ++L;
       const unsigned long long tiles = 1ull << (r - L);
       const unsigned long long nb = (tiles + 3) / 4;
       k.steps.push_back(si);
@@ -129,16 +156,21 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
         << "  if (t >= " << tiles << "ull) return;\n";
       k.blocks += nb;
       // per-operand base offsets from the tile index
-      std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) {
-        rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
         o << "  const long long o" << i << " = " << rec[i][1] << "ll";
-        for (int j = L; j < r; ++j)
-          if (rec[i][16 + j]) o << " + (long long)((t >> " << (j - L) << ") & 1ull) * " << rec[i][16 + j] << "ll";
+        for (int k2 = L; k2 < r; ++k2)
+          if (rec[i][16 + perm[k2]])
+            o << " + (long long)((t >> " << (k2 - L) << ") & 1ull) * " << rec[i][16 + perm[k2]] << "ll";
         if (rec[i][0] == WOP_LEAF)
           for (int d = 0; d < rec[i][2]; ++d)
             o << " + (long long)(((" << (rec[i][3 + d] ? "s" : "xb") << " >> " << rec[i][5 + d] << ") & 1ull) * "
               << rec[i][7 + d] << "ll)";
+        o << ";\n";
+      }
+      if (kind == ST_ELIM) {
+        o << "  const long long ob = " << out << "ll";
+        for (int k2 = L; k2 < r; ++k2)
+          o << " + (long long)((t >> " << (k2 - L) << ") & 1ull) * " << (1ll << perm[k2]) << "ll";
         o << ";\n";
       }
       // item operands first in every product
@@ -147,37 +179,59 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
         if (rec[i][0] == WOP_ITEM) order.push_back(i);
       for (int i = 0; i < m; ++i)
         if (rec[i][0] != WOP_ITEM) order.push_back(i);
-      for (int lo = 0; lo < (1 << L); ++lo) {
-        o << "  {\n    C2 a;\n";
-        // per summed index: the operand loads, then their product
-        for (int s2 = 0; s2 < (1 << ns); ++s2) {
-          o << "    {\n";
-          for (int i : order) {
-            long long off = 0;
-            for (int j = 0; j < L; ++j)
-              if ((lo >> j) & 1) off += rec[i][16 + j];
-            for (int j = 0; j < ns; ++j)
-              if ((s2 >> j) & 1) off += rec[i][48 + j];
-            o << "      const C2 v" << i << " = ";
-            if (rec[i][0] == WOP_ITEM)
-              o << "gm[(o" << i << " + " << off << "ll) * 64ll + lane];\n";
-            else
-              o << "cst[o" << i << " + " << off << "ll];\n";
-          }
-          std::string cur = m == 0 ? "C2{(R)1, (R)0}" : "";
-          for (size_t q = 0; q < order.size(); ++q) {
-            const std::string v = "v" + std::to_string(order[q]);
-            cur = q == 0 ? v : "cm(" + cur + ", " + v + ")";
-          }
-          o << "      " << (s2 == 0 ? "a = " + cur : "a = cad(a, " + cur + ")") << ";\n    }\n";
+      // tile bits each operand depends on, and its row index for output lo
+      std::vector<std::vector<int>> dep(m);
+      for (int i = 0; i < m; ++i)
+        for (int k2 = 0; k2 < L; ++k2)
+          if (rec[i][16 + perm[k2]]) dep[i].push_back(k2);
+      auto row_of = [&](int i, int lo) {
+        int e = 0;
+        for (size_t d = 0; d < dep[i].size(); ++d) e |= ((lo >> dep[i][d]) & 1) << d;
+        return e;
+      };
+      for (int lo = 0; lo < (1 << L); ++lo) o << "  C2 a" << lo << " = C2{(R)0, (R)0};\n";
+      // summed index: a loop (two iterations per pass) unless short
+      const int nsum = 1 << ns;
+      if (nsum > 4) o << "  #pragma unroll 2\n";
+      o << "  for (int q = 0; q < " << nsum << "; ++q) {\n";
+      for (int i = 0; i < m; ++i) {
+        o << "    const long long p" << i << " = o" << i;
+        for (int j = 0; j < ns; ++j)
+          if (rec[i][48 + j]) o << " + (long long)((q >> " << j << ") & 1) * " << rec[i][48 + j] << "ll";
+        o << ";\n";
+      }
+      for (int i : order)
+        for (int e = 0; e < (1 << dep[i].size()); ++e) {
+          long long off = 0;
+          for (size_t d = 0; d < dep[i].size(); ++d)
+            if ((e >> d) & 1) off += rec[i][16 + perm[dep[i][d]]];
+          o << "    const C2 v" << i << "_" << e << " = ";
+          if (rec[i][0] == WOP_ITEM)
+            o << "gm[(p" << i << " + " << off << "ll) * 64ll + lane];\n";
+          else
+            o << "cst[p" << i << " + " << off << "ll];\n";
         }
-        if (kind == ST_ELIM)
-          o << "    gm[(" << out << "ll + ((long long)t << " << L << ") + " << lo << "ll) * 64ll + lane] = a;\n";
-        else if (kind == ST_FINAL)
-          o << "    if (valid) res[sl * n_bs + b] = a;\n";
-        else
-          o << "    if (valid) gres[(" << slot << "ull * n_s + sl) * n_bs + b] = a;\n";
-        o << "  }\n";
+      for (int lo = 0; lo < (1 << L); ++lo) {
+        std::string cur = m == 0 ? "C2{(R)1, (R)0}" : "";
+        for (size_t q2 = 0; q2 < order.size(); ++q2) {
+          const int i = order[q2];
+          const std::string v = "v" + std::to_string(i) + "_" + std::to_string(row_of(i, lo));
+          cur = q2 == 0 ? v : "cm(" + cur + ", " + v + ")";
+        }
+        o << "    a" << lo << " = cad(a" << lo << ", " << cur << ");\n";
+      }
+      o << "  }\n";
+      for (int lo = 0; lo < (1 << L); ++lo) {
+        if (kind == ST_ELIM) {
+          long long lo_off = 0;
+          for (int j = 0; j < L; ++j)
+            if ((lo >> j) & 1) lo_off += 1ll << perm[j];
+          o << "  gm[(ob + " << lo_off << "ll) * 64ll + lane] = a" << lo << ";\n";
+        } else if (kind == ST_FINAL) {
+          o << "  if (valid) res[sl * n_bs + b] = a" << lo << ";\n";
+        } else {
+          o << "  if (valid) gres[(" << slot << "ull * n_s + sl) * n_bs + b] = a" << lo << ";\n";
+        }
       }
       o << "  return;\n  }\n";
     }

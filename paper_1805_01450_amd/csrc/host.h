@@ -142,8 +142,11 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
 // for every RZ gate (and disables constant hoisting).  encode = true builds
 // the per-element operand table when every step is small enough (rank +
 // summed variables <= 16); otherwise has_optab stays false.
+// combine_consts = true first multiplies the constant factors of each
+// elimination step into one constant tensor (constant step, once per call):
+// for engines that load constants from memory rather than folding literals.
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code, bool gradient = false);
+                     Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false);
 
 // ------------------------------------------------------------ wide engine
 // Descriptors for plans whose tensors are too large for registers or LDS.

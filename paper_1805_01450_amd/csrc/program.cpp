@@ -137,7 +137,7 @@ int popc_bits(int x) { return __builtin_popcount((unsigned)x); }
 }  // namespace
 
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code, bool gradient) {
+                     Program& prog, std::string& err, int& code, bool gradient, bool combine_consts) {
   prog = Program();
   if (!validate_plan(net, sliced, order, err, code)) return false;
   const int nvars = (int)net.vars.size();
@@ -340,6 +340,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   // that keeps some summed variables as outputs and a plain sum over them
   // (repeated while the remaining sum is still large).
   constexpr int kSplitSum = 8, kKeepSum = 6, kSplitRank = 14;
+  constexpr int kMaxCombinedRank = 20;  // largest constant tensor made by combining constant factors
   std::function<int(int, const std::vector<int>&, const std::vector<int>&, const std::vector<int>&, bool, int, int,
                     int)>
       emit;
@@ -392,6 +393,45 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
     bool all_const = !gradient;
     for (int i : tv) all_const = all_const && T[i].is_const;
+    if (combine_consts && !gradient && !all_const) {
+      // Constant factors of the step (gate tables and constant
+      // intermediates) are first multiplied into one constant tensor, summing
+      // the variables that occur only in them, by a constant step that runs
+      // once per call; the item step then multiplies by one constant operand
+      // instead of several (the same product, grouped differently).
+      std::vector<int> ct, rest_tv;
+      for (int i : tv) (T[i].is_const && T[i].leaf < 0 ? ct : rest_tv).push_back(i);
+      if (ct.size() >= 2) {
+        std::vector<char> in_rest(nvars, 0), in_ct(nvars, 0);
+        for (int i : rest_tv)
+          for (int u : T[i].vars) in_rest[u] = 1;
+        std::vector<int> c_out, c_sum;
+        for (int i : ct)
+          for (int u : T[i].vars) {
+            if (in_ct[u]) continue;
+            in_ct[u] = 1;
+            const bool summed = std::find(S.begin(), S.end(), u) != S.end();
+            (summed && !in_rest[u] ? c_sum : c_out).push_back(u);
+          }
+        if ((int)c_out.size() <= kMaxCombinedRank) {
+          std::sort(c_out.begin(), c_out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+          std::sort(c_sum.begin(), c_sum.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+          const int k = emit(ST_ELIM, ct, c_out, c_sum, true, -1, 0, 0);
+          for (int i : ct) {
+            for (int u : T[i].vars) count[u]--;
+            T[i].alive = 0;
+          }
+          for (int u : c_out) count[u]++;
+          for (int u : c_sum) done[u] = 1;
+          std::vector<int> S2;
+          for (int u : S)
+            if (std::find(c_sum.begin(), c_sum.end(), u) == c_sum.end()) S2.push_back(u);
+          S.swap(S2);
+          rest_tv.push_back(k);
+          tv.swap(rest_tv);
+        }
+      }
+    }
     emit(ST_ELIM, tv, out, S, all_const, -1, 0, 0);
     for (int i : tv) {
       for (int u : T[i].vars) count[u]--;
