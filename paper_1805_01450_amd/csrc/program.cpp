@@ -374,23 +374,51 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       n_two++;
       continue;
     }
-    std::vector<int> vv;
-    std::vector<int> cnt_in(nvars, 0);
-    for (int i : tv)
-      for (int u : T[i].vars) {
-        if (cnt_in[u] == 0) vv.push_back(u);
-        cnt_in[u]++;
+    // summed: variables all of whose tensors are in tv (v among them)
+    std::vector<int> S, out;
+    auto split_vars = [&]() {
+      std::vector<int> vv;
+      std::vector<int> cnt_in(nvars, 0);
+      for (int i : tv)
+        for (int u : T[i].vars) {
+          if (cnt_in[u] == 0) vv.push_back(u);
+          cnt_in[u]++;
+        }
+      S.clear();
+      out.clear();
+      for (int u : vv) (cnt_in[u] == count[u] ? S : out).push_back(u);
+      std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+      std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+    };
+    split_vars();
+    if (combine_consts && !gradient) {
+      // A large step also takes over the eliminations that follow it in the
+      // order while each touches its output and, besides, only small tensors
+      // (constants, leaves, rank <= 2) over variables the step already
+      // spans: those variables are summed here, and the large intermediates
+      // between the steps are never written (the sums are regrouped).
+      constexpr int kFuseMinSpan = 16, kFuseMaxSum = 8;
+      for (size_t oi = (size_t)pos[v] + 1; oi < order.size(); ++oi) {
+        const int u = order[oi];
+        if (done[u]) continue;
+        if ((int)(out.size() + S.size()) < kFuseMinSpan || (int)S.size() >= kFuseMaxSum) break;
+        if (std::find(out.begin(), out.end(), u) == out.end()) break;
+        std::vector<int> tu;
+        bool ok = true;
+        for (size_t i = 0; i < T.size() && ok; ++i) {
+          if (!T[i].alive || std::find(tv.begin(), tv.end(), (int)i) != tv.end()) continue;
+          if (std::find(T[i].vars.begin(), T[i].vars.end(), u) == T[i].vars.end()) continue;
+          ok = T[i].is_const || T[i].leaf >= 0 || T[i].vars.size() <= 2;
+          for (int w : T[i].vars)
+            ok = ok && (std::find(out.begin(), out.end(), w) != out.end() ||
+                        std::find(S.begin(), S.end(), w) != S.end());
+          tu.push_back((int)i);
+        }
+        if (!ok) break;
+        tv.insert(tv.end(), tu.begin(), tu.end());
+        split_vars();
       }
-    std::vector<int> S{v}, out;
-    for (int u : vv) {
-      if (u == v) continue;
-      if (cnt_in[u] == count[u])
-        S.push_back(u);
-      else
-        out.push_back(u);
     }
-    std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
-    std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
     bool all_const = !gradient;
     for (int i : tv) all_const = all_const && T[i].is_const;
     if (combine_consts && !gradient && !all_const) {
