@@ -400,7 +400,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       constexpr int kFuseMinSpan = 16, kFuseMaxSum = 8;
       for (size_t oi = (size_t)pos[v] + 1; oi < order.size(); ++oi) {
         const int u = order[oi];
-        if (done[u]) continue;
+        if (done[u] || std::find(S.begin(), S.end(), u) != S.end()) continue;
         if ((int)(out.size() + S.size()) < kFuseMinSpan || (int)S.size() >= kFuseMaxSum) break;
         if (std::find(out.begin(), out.end(), u) == out.end()) break;
         std::vector<int> tu;
@@ -458,6 +458,51 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
           rest_tv.push_back(k);
           tv.swap(rest_tv);
         }
+      }
+      // Pairwise pre-contraction of a large step: while it has more than
+      // two operands, the pair whose variables together span the fewest
+      // (two or more fewer than the step) is multiplied first, summing the
+      // variables only the two carry; each factor taken out this way costs
+      // the size of the pair's span instead of the step's full span.
+      const int full = (int)(out.size() + S.size());
+      while (full >= 16 && tv.size() > 2) {
+        int ba = -1, bb = -1, bspan = 1 << 30;
+        for (size_t x = 0; x < tv.size(); ++x)
+          for (size_t y = x + 1; y < tv.size(); ++y) {
+            std::vector<int> un = T[tv[x]].vars;
+            for (int w : T[tv[y]].vars)
+              if (std::find(un.begin(), un.end(), w) == un.end()) un.push_back(w);
+            if ((int)un.size() < bspan) {
+              bspan = (int)un.size();
+              ba = tv[x];
+              bb = tv[y];
+            }
+          }
+        if (bspan > full - 2) break;
+        std::vector<int> p_out, p_sum;
+        std::vector<int> un = T[ba].vars;
+        for (int w : T[bb].vars)
+          if (std::find(un.begin(), un.end(), w) == un.end()) un.push_back(w);
+        for (int w : un) {
+          const int c_in = (int)(std::find(T[ba].vars.begin(), T[ba].vars.end(), w) != T[ba].vars.end()) +
+                           (int)(std::find(T[bb].vars.begin(), T[bb].vars.end(), w) != T[bb].vars.end());
+          (c_in == count[w] ? p_sum : p_out).push_back(w);
+        }
+        std::sort(p_out.begin(), p_out.end(), [&](int x, int y) { return pos[x] < pos[y]; });
+        std::sort(p_sum.begin(), p_sum.end(), [&](int x, int y) { return pos[x] < pos[y]; });
+        const bool pc = T[ba].is_const && T[bb].is_const && T[ba].leaf < 0 && T[bb].leaf < 0;
+        const int c = emit(ST_ELIM, {ba, bb}, p_out, p_sum, pc, -1, 0, 0);
+        for (int i : {ba, bb}) {
+          for (int w : T[i].vars) count[w]--;
+          T[i].alive = 0;
+        }
+        for (int w : p_out) count[w]++;
+        for (int w : p_sum) done[w] = 1;
+        std::vector<int> tv2{c};
+        for (int i : tv)
+          if (i != ba && i != bb) tv2.push_back(i);
+        tv.swap(tv2);
+        split_vars();
       }
     }
     emit(ST_ELIM, tv, out, S, all_const, -1, 0, 0);
