@@ -61,8 +61,12 @@ WORKLOADS = {
 PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # Planner objective per workload (qgm_plan_slices_ex flags): 4096 items are
 # too few to fill the GPU, so the 5x5x20 batch is planned for the latency of
-# one item on four wavefronts; the others keep the sum of 2^deg(v).
-PLAN_FLAGS = {"5x5x20": 4}
+# one item on four wavefronts; the wide-engine workloads search several plans
+# (seeds, with and without re-ordering) scored by their compiled wide program
+# (QGM_PLAN_SEARCH | QGM_PLAN_WIDE_TIME); 6x6x25 keeps the sum of 2^deg(v).
+PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24}
+# planner time budget per workload (seconds; the search flag plans up to 8 times)
+PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 60.0, "8x8x40-full": 60.0}
 
 
 def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
@@ -140,7 +144,11 @@ def main():
     bits = random_bitstrings(n * n, n_bs, seed + 1000)
     circ = q.Circuit(text)
     plan_flags = PLAN_FLAGS.get(args.workload, 0) if args.plan_flags < 0 else args.plan_flags
-    sliced, order = circ.plan_slices(k_req=k, time_budget_s=5.0 if n >= 7 else 1.0, seed=seed, flags=plan_flags)
+    budget = PLAN_BUDGET.get(args.workload, 1.0)
+    t_plan = time.perf_counter()
+    sliced, order = circ.plan_slices(k_req=k, time_budget_s=budget, seed=seed, flags=plan_flags)
+    t_plan = time.perf_counter() - t_plan
+    print(f"[bench] {args.workload}: planned in {t_plan:.1f} s (k={len(sliced)})", file=sys.stderr, flush=True)
     n_s = (1 << k) if n_run is None else n_run
     n_items = n_bs * n_s
     d_bits = torch.from_numpy(bits).cuda()
@@ -165,6 +173,7 @@ def main():
         r["plan"] = plan
         r["waves"] = waves
         results[name] = r
+        print(f"[bench] {args.workload} {name}: {r['gpu_ms_step']:.4f} ms per step", file=sys.stderr, flush=True)
 
     import oracle
     check = list(range(0, n_bs, max(1, n_bs // 16)))
@@ -215,7 +224,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} grid depth {depth} Rules 1-3 circuit seed {seed}, {n_bs} random "
                                f"bitstrings, k={k} planner-sliced variables: {n_items} slice contractions per step",
-                   "sliced_vars": sliced, "plan_flags": plan_flags, "max_rank": st["max_rank"],
+                   "sliced_vars": sliced, "plan_flags": plan_flags, "plan_s": round(t_plan, 1),
+                   "compile_s": round(st["compile_s"], 1), "max_rank": st["max_rank"],
                    "item_elems": st["item_elems"],
                    "flops_per_slice": st["flops_item"], "parallelism": "single GPU"},
         "roofline": roofline,

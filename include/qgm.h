@@ -152,8 +152,19 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *     fused eliminations as compiled) instead of the sum of 2^deg(v);
  *   QGM_PLAN_LATENCY: choose it by the time of one item on four wavefronts,
  *     max(4 x critical path, total) in flops of the compiled steps, for
- *     batches too small to fill the GPU (takes precedence over BYTES). */
-enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2, QGM_PLAN_LATENCY = 4 };
+ *     batches too small to fill the GPU (takes precedence over BYTES);
+ *   QGM_PLAN_SEARCH: plan up to 8 times (seeds seed, seed', ...; each seed
+ *     once keeping the first ordering and once re-ordering after every
+ *     removal) while the time budget lasts, each with budget / 8, and keep
+ *     the plan whose final ordering scores best (sum of 2^deg(v), or the
+ *     BYTES / LATENCY objective).  Attempts that cannot start within the
+ *     budget are skipped, so a short budget on a slow host can give a
+ *     different plan;
+ *   QGM_PLAN_WIDE_TIME: with SEARCH, score each plan by its program as the
+ *     WIDE engine compiles it (constant factors combined, small eliminations
+ *     absorbed, operand pairs pre-contracted): flops / 40 TFLOP/s + bytes /
+ *     4 TB/s per slice, the rates its kernels reach on MI355X. */
+enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2, QGM_PLAN_LATENCY = 4, QGM_PLAN_SEARCH = 8, QGM_PLAN_WIDE_TIME = 16 };
 qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                               uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                               int32_t* n_order_out);

@@ -62,6 +62,8 @@ def qgm_circuit_free(c) -> None:
 QGM_PLAN_REORDER = 1
 QGM_PLAN_BYTES = 2
 QGM_PLAN_LATENCY = 4
+QGM_PLAN_SEARCH = 8
+QGM_PLAN_WIDE_TIME = 16
 
 
 def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0,

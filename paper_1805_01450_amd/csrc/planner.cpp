@@ -328,8 +328,8 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
 // gives the lowest cost under the fixed ordering `order0` (ties: lower width,
 // then lower vertex id).  Candidates are the `n_cand` highest-degree
 // vertices of the graph with the previous picks removed.
-bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
-                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags) {
+static bool plan_once(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                      std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* score) {
   const bool reorder_each = (flags & 1) != 0;
   std::vector<int> vov;
   Graph g = model_graph(net, vov);
@@ -386,6 +386,48 @@ bool plan_slices(const Network& net, int k_req, int target_rank, double time_bud
   for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
   order_vars.clear();
   for (int v : order1) order_vars.push_back(net.free_vars[v]);
+  if (score) {
+    if (flags & 16) {
+      // the compiled program of the wide engine (with its regroupings):
+      // estimated seconds per slice at the rates those kernels reach
+      Program prog;
+      std::string err;
+      int code = 0;
+      if (!compile_program(net, sliced_vars, order_vars, prog, err, code, false, true)) return false;
+      *score = prog.flops_item / 40e12 + prog.bytes_item / 4e12;
+    } else if (objective == OBJ_COST) {
+      *score = order_cost(g, order1, removed).cost;
+    } else {
+      const SimCost sc = simulate(net, vov, g.n, removed, order1);
+      *score = objective == OBJ_BYTES ? sc.bytes : std::max(4.0 * sc.cp, sc.flops);
+    }
+  }
+  return true;
+}
+
+// QGM_PLAN_SEARCH: whole plans from different seeds, alternately keeping the
+// first ordering and re-ordering after each removal, while the time budget
+// lasts (at most kAttempts); the plan with the best final score is kept.
+bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags) {
+  if (!(flags & 8)) return plan_once(net, k_req, target_rank, time_budget_s, seed, sliced_vars, order_vars, flags,
+                                     nullptr);
+  constexpr int kAttempts = 8;
+  const auto t0 = std::chrono::steady_clock::now();
+  const double per = time_budget_s / kAttempts;
+  double best = 0;
+  for (int a = 0; a < kAttempts; ++a) {
+    if (a > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >= time_budget_s) break;
+    const int f = (flags & ~1) | (((flags & 1) ^ (a & 1)) ? 1 : 0);
+    std::vector<int> sv, ov;
+    double score = 0;
+    if (!plan_once(net, k_req, target_rank, per, seed + 0x51ed27ull * (a / 2), sv, ov, f, &score)) continue;
+    if (a == 0 || score < best) {
+      best = score;
+      sliced_vars = sv;
+      order_vars = ov;
+    }
+  }
   return true;
 }
 
