@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published vector FP32 peak
+PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X published dense FP32 matrix-core peak
 
 
 
@@ -66,7 +67,20 @@ PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # (QGM_PLAN_SEARCH | QGM_PLAN_WIDE_TIME); 6x6x25 keeps the sum of 2^deg(v).
 PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24}
 # planner time budget per workload (seconds; the search flag plans up to 8 times)
-PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 60.0, "8x8x40-full": 60.0}
+PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 150.0, "8x8x40-full": 150.0}
+
+
+def stored_plan(name, n, depth, seed, k):
+    """A plan precomputed by paper_1805_01450_amd/plans/make_plans.py for this
+    circuit, or None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1805_01450_amd", "plans", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec["circuit"] != {"n": n, "depth": depth, "seed": seed} or rec["k"] != k:
+        return None
+    return rec["sliced"], rec["order"], f"stored plan {name}.json (search budget {rec['budget_s']} s)"
 
 
 def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
@@ -109,6 +123,8 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "interpreter", "generated"])
     ap.add_argument("--plan-flags", type=int, default=-1,
                     help="planner flags (QGM_PLAN_*); default: per workload")
+    ap.add_argument("--vector-only", action="store_true",
+                    help="wide engine: keep every step on the vector ALUs (no matrix cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the c128 and interpreter comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -146,9 +162,14 @@ def main():
     plan_flags = PLAN_FLAGS.get(args.workload, 0) if args.plan_flags < 0 else args.plan_flags
     budget = PLAN_BUDGET.get(args.workload, 1.0)
     t_plan = time.perf_counter()
-    sliced, order = circ.plan_slices(k_req=k, time_budget_s=budget, seed=seed, flags=plan_flags)
+    stored = stored_plan(args.workload.split("-")[0], n, depth, seed, k) if args.plan_flags < 0 else None
+    if stored is not None:
+        sliced, order, plan_source = stored
+    else:
+        sliced, order = circ.plan_slices(k_req=k, time_budget_s=budget, seed=seed, flags=plan_flags)
+        plan_source = f"planned here (flags {plan_flags}, budget {budget} s)"
     t_plan = time.perf_counter() - t_plan
-    print(f"[bench] {args.workload}: planned in {t_plan:.1f} s (k={len(sliced)})", file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: {plan_source}, {t_plan:.1f} s (k={len(sliced)})", file=sys.stderr, flush=True)
     n_s = (1 << k) if n_run is None else n_run
     n_items = n_bs * n_s
     d_bits = torch.from_numpy(bits).cuda()
@@ -163,7 +184,7 @@ def main():
     results = {}
     for name, prec, engine in runs:
         try:
-            plan = q.Plan(circ, sliced, order, prec=prec, profile=True, engine=engine)
+            plan = q.Plan(circ, sliced, order, prec=prec, profile=True, engine=engine, vector_only=args.vector_only)
         except q.QgmError:
             if name == "c64":
                 raise
@@ -224,7 +245,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} grid depth {depth} Rules 1-3 circuit seed {seed}, {n_bs} random "
                                f"bitstrings, k={k} planner-sliced variables: {n_items} slice contractions per step",
-                   "sliced_vars": sliced, "plan_flags": plan_flags, "plan_s": round(t_plan, 1),
+                   "sliced_vars": sliced, "plan": plan_source, "plan_s": round(t_plan, 1),
                    "compile_s": round(st["compile_s"], 1), "max_rank": st["max_rank"],
                    "item_elems": st["item_elems"],
                    "flops_per_slice": st["flops_item"], "parallelism": "single GPU"},
@@ -235,7 +256,11 @@ def main():
                   "kernel_ms = HIP events around each kernel over the warm-up runs",
         "gpu_ms_per_step": r["gpu_ms_step"],
         "amplitude_error_c64": nerr(r["amps"]),
-        "mfma_frac": 0.0,
+        # share of the slice flops on the matrix cores, and those flops per
+        # second of the whole chain against the FP32 matrix peak
+        "mfma_flops_share": st["flops_mfma"] / st["flops_item"],
+        "mfma_steps": st["mfma_steps"],
+        "mfma_util_fp32": st["flops_mfma"] * n_items / (r["ms_chain"] * 1e-3) / 1e12 / PEAK_FP32_MATRIX_TFLOPS,
         "kernel_ms": {"prologue": r["ms_pro"], "chain": r["ms_chain"], "reduce": r["ms_red"]},
     }
     if n_run is not None:
@@ -246,7 +271,6 @@ def main():
     if "bf16x3" in results:
         line["bf16x3_value"] = n_items / (results["bf16x3"]["wall"] / args.steps)
         line["amplitude_error_bf16x3"] = nerr(results["bf16x3"]["amps"])
-        line["bf16x3_mfma_frac"] = 0.0
     a0 = complex(r["amps"][0])
     line["amplitude_first_bitstring"] = [a0.real, a0.imag]
     if "c128" in results:

@@ -74,7 +74,10 @@ typedef struct {
   int32_t waves;         /* GENERATED: wavefronts per block to cut the item tree across
                             (1, 2, 4 or 8; fewer when the exchange does not fit in LDS or
                             the program is not a tree); 0 = chosen by the cost model */
-  int32_t reserved[5];
+  int32_t vector_only;   /* WIDE: 1 = run every step on the vector ALUs; 0 = two-operand
+                            complex64 contractions with >= 5 row and >= 5 column bits run
+                            on the matrix cores */
+  int32_t reserved[4];
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
@@ -109,6 +112,9 @@ typedef struct {
   int32_t launches;       /* kernel launches of the item steps per pass: WIDE with
                              generated kernels, one per level of mutually independent
                              steps; otherwise the item steps' kernel count */
+  int32_t mfma_steps;     /* WIDE, complex64: item steps that run on the matrix cores
+                             (two-operand contractions with >= 5 row and >= 5 column bits) */
+  double flops_mfma;      /* the part of flops_item those steps perform */
 } qgm_stats;
 
 /* Circuit text v1, one gate per line, '#' starts a comment:
@@ -153,13 +159,13 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *   QGM_PLAN_LATENCY: choose it by the time of one item on four wavefronts,
  *     max(4 x critical path, total) in flops of the compiled steps, for
  *     batches too small to fill the GPU (takes precedence over BYTES);
- *   QGM_PLAN_SEARCH: plan up to 8 times (seeds seed, seed', ...; each seed
+ *   QGM_PLAN_SEARCH: plan repeatedly (seeds seed, seed', ...; each seed
  *     once keeping the first ordering and once re-ordering after every
- *     removal) while the time budget lasts, each with budget / 8, and keep
- *     the plan whose final ordering scores best (sum of 2^deg(v), or the
- *     BYTES / LATENCY objective).  Attempts that cannot start within the
- *     budget are skipped, so a short budget on a slow host can give a
- *     different plan;
+ *     removal; each attempt with budget / 8; at most 64 attempts) while the
+ *     time budget lasts, and keep the plan whose final ordering scores best
+ *     (sum of 2^deg(v), or the BYTES / LATENCY / WIDE_TIME objective).  The
+ *     number of attempts depends on the host's speed, so the same budget can
+ *     give different plans on different hosts;
  *   QGM_PLAN_WIDE_TIME: with SEARCH, score each plan by its program as the
  *     WIDE engine compiles it (constant factors combined, small eliminations
  *     absorbed, operand pairs pre-contracted): flops / 40 TFLOP/s + bytes /

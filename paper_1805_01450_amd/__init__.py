@@ -84,13 +84,15 @@ def qgm_order_cost(c, sliced, order):
 
 
 def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
-                    engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0):
+                    engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
+                    vector_only: bool = False):
     opts = PlanOpts()
     opts.prec = prec
     opts.profile = 1 if profile else 0
     opts.engine = engine
     opts.gradient = 1 if gradient else 0
     opts.waves = waves
+    opts.vector_only = int(vector_only)
     opts.workspace_cap = workspace_cap
     h = C.c_void_p()
     check(lib.qgm_plan_create(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(opts), C.byref(h)))
@@ -256,14 +258,15 @@ class Plan:
     """Owning wrapper of a qgm_plan handle plus a cached device workspace."""
 
     def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
-                 profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0):
+                 profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
+                 vector_only: bool = False):
         self.circuit = circuit
         self.sliced = list(sliced)
         self.order = list(order)
         self.prec = prec
         self.gradient = gradient
         self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine,
-                                 gradient, waves)
+                                 gradient, waves, vector_only)
         self._ws = None
 
     @property

@@ -25,7 +25,7 @@ class VarInfo(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("profile", C.c_int32), ("workspace_cap", C.c_size_t),
                 ("engine", C.c_int32), ("gradient", C.c_int32), ("waves", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("vector_only", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):
@@ -33,7 +33,7 @@ class Stats(C.Structure):
                 ("item_elems", C.c_int32), ("n_leaves", C.c_int32), ("k", C.c_int32),
                 ("flops_item", C.c_double), ("flops_const", C.c_double), ("bytes_item", C.c_double),
                 ("cost", C.c_double), ("engine", C.c_int32), ("waves", C.c_int32), ("compile_s", C.c_double),
-                ("launches", C.c_int32)]
+                ("launches", C.c_int32), ("mfma_steps", C.c_int32), ("flops_mfma", C.c_double)]
 
 
 def _load():

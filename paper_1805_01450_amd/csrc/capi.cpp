@@ -263,6 +263,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   if (o.engine < QGM_ENGINE_AUTO || o.engine > QGM_ENGINE_WIDE) return fail(QGM_E_ARG, "unknown engine");
   if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8)
     return fail(QGM_E_ARG, "waves must be 0, 1, 2, 4 or 8");
+  if (o.vector_only != 0 && o.vector_only != 1) return fail(QGM_E_ARG, "vector_only must be 0 or 1");
   auto* p = new qgm_plan();
   p->net = c->net;
   p->sliced = sv;
@@ -336,7 +337,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     // per-step generated kernels; the prebuilt step kernel stays the fallback
     if (!std::getenv("QGM_WIDE_PREBUILT")) {
       auto t0 = std::chrono::steady_clock::now();
-      std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels);
+      std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels, !o.vector_only);
       if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
         // debugging aid: keep the generated source
         if (FILE* f = std::fopen((std::string(dir) + "/qgm_wide_" + std::to_string((uintptr_t)p) + ".hip").c_str(), "w")) {
@@ -402,7 +403,11 @@ qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
   s.launches = 1;
   if (p->engine == QGM_ENGINE_WIDE) {
     int lv = 0, item_steps = 0;
-    for (const WideKernel& k : p->wide_kernels) lv += k.kind == 0;
+    for (const WideKernel& k : p->wide_kernels) {
+      lv += k.kind == 0;
+      s.mfma_steps += k.mfma_steps;
+      s.flops_mfma += k.mfma_flops;
+    }
     for (int si = 0; si < p->wide.n_steps; ++si) item_steps += !p->wide.steps[8 * si + 7];
     s.launches = lv > 0 ? lv : item_steps;
   }

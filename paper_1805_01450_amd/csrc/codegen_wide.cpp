@@ -11,6 +11,8 @@
 // an output row are independent and issued together.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <functional>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -29,12 +31,132 @@ std::string lit(double v) {
 
 }  // namespace
 
+// A two-operand contraction step out[b, i, j] = sum_k A[b, i, k] B[b, k, j]
+// (b: output bits both operands carry, i: those only A carries, j: only B,
+// k: summed bits, carried by both) is, for each item, a batch of complex
+// GEMMs.  With at least 5 i bits and 5 j bits it runs on the matrix cores
+// (complex64): v_mfma_f32_32x32x1_2b_f32 computes two independent 32x32
+// rank-1 updates, one per item of a pair, so a wavefront keeps a 32x32 tile
+// of two item pairs (four items) and walks k, loading per k and item one
+// A row element per tile row and one B row element per tile column (lane a
+// of the A operand: item a / 32 of the pair, tile row a % 32; lane b of the
+// B operand likewise with the tile column).  Real parts: Cr += ar br - ai bi,
+// Ci += ar bi + ai br (four MFMAs per k).  Result register r of a lane l
+// holds item r / 16 of the pair, tile row 8 (r % 16 / 4) + 4 (l / 32) +
+// r % 4 and tile column l % 32.  A block of four wavefronts covers 16 items;
+// the grid covers item quarters (fastest), the remaining j bits, the
+// remaining i bits and the b bits.  Returns false when the step does not
+// qualify.
+bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns,
+                    const std::vector<const int32_t*>& rec) {
+  if (kind != ST_ELIM || rec.size() != 2 || rec[0][0] != WOP_ITEM || rec[1][0] != WOP_ITEM) return false;
+  const int32_t* A = rec[0];
+  const int32_t* B = rec[1];
+  std::vector<int> bb, bi, bj, bk;
+  for (int j = 0; j < r; ++j) {
+    const bool a = A[16 + j] != 0, b = B[16 + j] != 0;
+    if (a && b) bb.push_back(j);
+    else if (a) bi.push_back(j);
+    else if (b) bj.push_back(j);
+    else return false;
+  }
+  for (int j = 0; j < ns; ++j) {
+    if (A[48 + j] == 0 || B[48 + j] == 0) return false;
+    bk.push_back(j);
+  }
+  if (bi.size() < 5 || bj.size() < 5 || bk.empty()) return false;
+  // grid: item quarter (2 bits), remaining j bits, remaining i bits, b bits
+  std::vector<int> gj(bj.begin() + 5, bj.end()), gi(bi.begin() + 5, bi.end());
+  const int grid_bits = 2 + (int)gj.size() + (int)gi.size() + (int)bb.size();
+  const unsigned long long nb = 1ull << grid_bits;
+  o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
+    << "  // step " << si << " (matrix cores)\n"
+    << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
+    << "  const int lid = threadIdx.x & 63;\n"
+    << "  const int q0 = (int)(g & 3ull) * 16 + (int)wv * 4;\n";  // first item of the wavefront
+  k.blocks += nb;
+  k.steps.push_back(si);
+  k.mfma_steps += 1;
+  k.mfma_flops += 8.0 * (double)(1ull << (r + ns));
+  // block bases of A, B and the output from the grid bits
+  auto grid_sum = [&](const std::function<long long(int)>& stride_of_out_bit) {
+    std::string e;
+    int pos = 2;
+    for (int j : gj) {
+      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
+                                     std::to_string(stride_of_out_bit(j)) + "ll";
+      ++pos;
+    }
+    for (int j : gi) {
+      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
+                                     std::to_string(stride_of_out_bit(j)) + "ll";
+      ++pos;
+    }
+    for (int j : bb) {
+      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
+                                     std::to_string(stride_of_out_bit(j)) + "ll";
+      ++pos;
+    }
+    return e;
+  };
+  o << "  const long long ba = " << A[1] << "ll" << grid_sum([&](int j) { return (long long)A[16 + j]; }) << ";\n"
+    << "  const long long bbv = " << B[1] << "ll" << grid_sum([&](int j) { return (long long)B[16 + j]; }) << ";\n"
+    << "  const long long bo = " << out << "ll" << grid_sum([&](int j) { return 1ll << j; }) << ";\n";
+  // per-lane tile row of A and tile column of B
+  o << "  const int tr = lid & 31;\n"
+    << "  const long long la = ba";
+  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << A[16 + bi[t]] << "ll";
+  o << ";\n  const long long lb = bbv";
+  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << B[16 + bj[t]] << "ll";
+  o << ";\n  const int hi = lid >> 5;\n"
+    << "  f32x32 cr0 = {}, ci0 = {}, cr1 = {}, ci1 = {};\n"
+    << "  #pragma unroll 2\n"
+    << "  for (int kk = 0; kk < " << (1 << ns) << "; ++kk) {\n"
+    << "    const long long ka = la";
+  for (size_t t = 0; t < bk.size(); ++t) o << " + (long long)((kk >> " << t << ") & 1) * " << A[48 + bk[t]] << "ll";
+  o << ";\n    const long long kb = lb";
+  for (size_t t = 0; t < bk.size(); ++t) o << " + (long long)((kk >> " << t << ") & 1) * " << B[48 + bk[t]] << "ll";
+  o << ";\n"
+    << "    const C2 a0 = gm[ka * 64ll + q0 + hi];\n"
+    << "    const C2 b0 = gm[kb * 64ll + q0 + hi];\n"
+    << "    const C2 a1 = gm[ka * 64ll + q0 + 2 + hi];\n"
+    << "    const C2 b1 = gm[kb * 64ll + q0 + 2 + hi];\n"
+    << "    cr0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.x, b0.x, cr0, 0, 0, 0);\n"
+    << "    ci0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.x, b0.y, ci0, 0, 0, 0);\n"
+    << "    cr1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.x, b1.x, cr1, 0, 0, 0);\n"
+    << "    ci1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.x, b1.y, ci1, 0, 0, 0);\n"
+    << "    cr0 = __builtin_amdgcn_mfma_f32_32x32x1f32(-a0.y, b0.y, cr0, 0, 0, 0);\n"
+    << "    ci0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.y, b0.x, ci0, 0, 0, 0);\n"
+    << "    cr1 = __builtin_amdgcn_mfma_f32_32x32x1f32(-a1.y, b1.y, cr1, 0, 0, 0);\n"
+    << "    ci1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.y, b1.x, ci1, 0, 0, 0);\n"
+    << "  }\n";
+  // results: register r -> item r / 16 of the pair, tile row
+  // 8 (r % 16 / 4) + 4 hi + r % 4, tile column lid % 32
+  o << "  const long long oc = bo";
+  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << (1ll << bj[t]) << "ll";
+  o << ";\n  const long long oh = hi ? " << (1ll << bi[2]) << "ll : 0ll;\n";
+  for (int rr = 0; rr < 32; ++rr) {
+    const int row = 8 * ((rr % 16) / 4) + (rr % 4);  // without the 4 hi term
+    long long off = 0;
+    for (int t = 0; t < 5; ++t)
+      if ((row >> t) & 1) off += 1ll << bi[t];
+    const int item = rr / 16;
+    o << "  gm[(oc + oh + " << off << "ll) * 64ll + q0 + " << item << "] = C2{cr0[" << rr << "], ci0[" << rr
+      << "]};\n"
+      << "  gm[(oc + oh + " << off << "ll) * 64ll + q0 + 2 + " << item << "] = C2{cr1[" << rr << "], ci1[" << rr
+      << "]};\n";
+  }
+  o << "  return;\n  }\n";
+  return true;
+}
+
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
-                                 std::vector<WideKernel>& kernels) {
+                                 std::vector<WideKernel>& kernels, bool mfma) {
   kernels.clear();
   std::ostringstream o;
   o << "typedef " << (prec == 0 ? "double" : "float") << " R;\n"
-    << "struct C2 { R x, y; };\n";
+    << "struct C2 { R x, y; };\n"
+    << "typedef float f32x32 __attribute__((ext_vector_type(32)));\n";
   if (prec == 2)
     o << "static __device__ __forceinline__ float bh(float x) { unsigned u = __float_as_uint(x); "
          "u += 0x7FFFu + ((u >> 16) & 1u); return __uint_as_float(u & 0xFFFF0000u); }\n"
@@ -118,6 +240,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
       std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+      if (prec == 1 && mfma && emit_mfma_step(o, k, si, kind, out, r, ns, rec)) continue;
       // Iteration order of the output bits: those that fewer item operands
       // depend on come first (inside the tile, then across neighbouring
       // wavefronts), so an operand row is reused within a tile or soon after

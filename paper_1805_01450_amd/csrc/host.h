@@ -175,9 +175,11 @@ struct WideKernel {
   std::string name;
   unsigned long long blocks;
   std::vector<int> steps;
+  int mfma_steps = 0;       // steps of this kernel on the matrix cores
+  double mfma_flops = 0.0;  // their flops per item
 };
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
-                                 std::vector<WideKernel>& kernels);
+                                 std::vector<WideKernel>& kernels, bool mfma);
 
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.

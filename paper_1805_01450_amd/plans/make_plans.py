@@ -1,0 +1,45 @@
+"""Precompute the elimination plans (sliced variables and ordering) of the
+large benchmark circuits with a long planner search, so that runs do not
+spend minutes planning.  The planner is the library's own
+(qgm_plan_slices_ex with QGM_PLAN_SEARCH | QGM_PLAN_WIDE_TIME); a stored
+plan is an input like any caller-supplied order, validated by
+qgm_plan_create.
+
+    python -m paper_1805_01450_amd.plans.make_plans [--budget SECONDS] [name ...]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# name: (grid n, depth, circuit seed, sliced variables k)
+CIRCUITS = {"7x7x30": (7, 30, 0, 6), "8x8x40": (8, 40, 0, 13)}
+
+
+def main():
+    sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+    import paper_1805_01450_amd as q
+    from workload import generate_circuit
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--budget", type=float, default=600.0)
+    ap.add_argument("names", nargs="*", default=sorted(CIRCUITS))
+    args = ap.parse_args()
+    flags = q.QGM_PLAN_SEARCH | q.QGM_PLAN_WIDE_TIME
+    for name in args.names:
+        n, d, seed, k = CIRCUITS[name]
+        circ = q.Circuit(generate_circuit(n, d, seed))
+        t0 = time.time()
+        sliced, order = circ.plan_slices(k_req=k, time_budget_s=args.budget, seed=seed, flags=flags)
+        st = q.Plan(circ, sliced, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
+        rec = {"circuit": {"n": n, "depth": d, "seed": seed}, "k": k, "flags": flags, "budget_s": args.budget,
+               "plan_s": round(time.time() - t0, 1), "sliced": sliced, "order": order,
+               "flops_item": st["flops_item"], "bytes_item": st["bytes_item"], "max_rank": st["max_rank"]}
+        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+            json.dump(rec, f)
+        print(name, {x: rec[x] for x in ("plan_s", "flops_item", "bytes_item", "max_rank")}, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -528,3 +528,64 @@ def test_wide_prebuilt_step_kernel_matches_generated(config2):
         del os.environ["QGM_WIDE_PREBUILT"]
     assert nerr(pre, ref, 25).max() <= C128_TOL
     assert nerr(gen, ref, 25).max() <= C128_TOL
+
+
+def _stored(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(q.__file__), "plans", name + ".json")
+    with open(path) as f:
+        rec = json.load(f)
+    cc = rec["circuit"]
+    return generate_circuit(cc["n"], cc["depth"], cc["seed"]), rec["sliced"], rec["order"]
+
+
+def test_matrix_core_steps_7x7x30():
+    """Wide engine, complex64, two-operand contractions on the matrix cores:
+    amplitudes against the complex128 path (pinned to the oracle) and the
+    vector-only complex64 path, and single slices against the oracle."""
+    text, sl, order = _stored("7x7x30")
+    c = q.Circuit(text)
+    pm = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE)
+    pv = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, vector_only=True)
+    pd = q.Plan(c, sl, order, prec=q.QGM_C128, engine=q.QGM_ENGINE_WIDE)
+    sm, sv = pm.stats(), pv.stats()
+    note("7x7x30 stored plan: mfma steps", sm["mfma_steps"], "flops share", sm["flops_mfma"] / sm["flops_item"])
+    assert sm["mfma_steps"] >= 1 and sv["mfma_steps"] == 0 and sv["flops_mfma"] == 0.0
+    bits = random_bitstrings(49, 8, 777)
+    am, av, ad = pm.amplitudes(bits), pv.amplitudes(bits), pd.amplitudes(bits)
+    note("max err mfma", nerr(am, ad, 49).max(), "vector", nerr(av, ad, 49).max())
+    assert nerr(am, ad, 49).max() <= C64_TOL
+    assert nerr(av, ad, 49).max() <= C64_TOL
+    net = oracle.build_network(text)
+    scale = 2.0 ** -24.5 / 2.0 ** 3
+    for s in (0, 45):
+        part = pm.amplitudes_range([bits[0]], None, s, s + 1)[0]
+        got = part[0] + part[2] + 1j * (part[1] + part[3])
+        ref = oracle.ve_slice_values(text, bits[0], sliced=sl, slices=[s], net=net)[0]
+        note("slice", s, "mfma", got, "oracle", ref)
+        assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
+
+
+def test_matrix_core_steps_8x8x40():
+    """8x8x40 with the stored k = 13 plan: most of the work runs on the matrix
+    cores; 64 slices of one bitstring against the complex128 path and the
+    vector-only path, slice by slice for three slices."""
+    text, sl, order = _stored("8x8x40")
+    c = q.Circuit(text)
+    pm = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE)
+    pd = q.Plan(c, sl, order, prec=q.QGM_C128, engine=q.QGM_ENGINE_WIDE)
+    sm = pm.stats()
+    note("8x8x40 stored plan: mfma steps", sm["mfma_steps"], "flops share", sm["flops_mfma"] / sm["flops_item"])
+    assert sm["mfma_steps"] >= 5 and sm["flops_mfma"] >= 0.5 * sm["flops_item"]
+    x = random_bitstrings(64, 1, 1000)[0]
+    scale = 2.0 ** -32 / 2.0 ** 6.5
+
+    def val(p, s0, s1):
+        part = p.amplitudes_range([x], None, s0, s1)[0]
+        return part[0] + part[2] + 1j * (part[1] + part[3])
+
+    for s0, s1 in ((0, 64), (100, 101), (4095, 4096), (8191, 8192)):
+        got, ref = val(pm, s0, s1), val(pd, s0, s1)
+        note("slices", s0, s1, "mfma", got, "c128", ref)
+        assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL

@@ -201,3 +201,23 @@ def test_generated_source_shapes():
     sl2, order2 = c2.plan_slices(k_req=2, time_budget_s=0.2)
     g = q.Plan(c2, sl2, order2, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED, gradient=True).stats()
     assert g["waves"] == 1
+
+
+def test_stored_plans_are_valid(monkeypatch):
+    """Plans precomputed for the large benchmark circuits name distinct free
+    variables and order every remaining one (checked by plan creation)."""
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")  # structure only: no kernel build
+    import json
+    import os
+    import glob
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
+    paths = sorted(glob.glob(os.path.join(here, "*.json")))
+    for path in paths:
+        rec = json.load(open(path))
+        cz = rec["circuit"]
+        c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+        assert len(rec["sliced"]) == rec["k"] == len(set(rec["sliced"]))
+        free = [v for v, _, _, out in c.vars() if not out]
+        assert sorted(rec["order"]) == sorted(set(free) - set(rec["sliced"]))
+        st = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
+        assert st["max_rank"] == rec["max_rank"]
