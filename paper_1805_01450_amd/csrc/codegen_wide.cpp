@@ -33,26 +33,35 @@ std::string lit(double v) {
 
 // A two-operand contraction step out[b, i, j] = sum_k A[b, i, k] B[b, k, j]
 // (b: output bits both operands carry, i: those only A carries, j: only B,
-// k: summed bits, carried by both) is, for each item, a batch of complex
-// GEMMs.  With at least 5 i bits and 5 j bits it runs on the matrix cores
-// (complex64): v_mfma_f32_32x32x1_2b_f32 computes two independent 32x32
-// rank-1 updates, one per item of a pair, so a wavefront keeps a 32x32 tile
-// of two item pairs (four items) and walks k, loading per k and item one
-// A row element per tile row and one B row element per tile column (lane a
-// of the A operand: item a / 32 of the pair, tile row a % 32; lane b of the
-// B operand likewise with the tile column).  Real parts: Cr += ar br - ai bi,
-// Ci += ar bi + ai br (four MFMAs per k).  Result register r of a lane l
-// holds item r / 16 of the pair, tile row 8 (r % 16 / 4) + 4 (l / 32) +
-// r % 4 and tile column l % 32.  A block of four wavefronts covers 16 items;
-// the grid covers item quarters (fastest), the remaining j bits, the
-// remaining i bits and the b bits.  Returns false when the step does not
-// qualify.
-bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns,
-                    const std::vector<const int32_t*>& rec) {
+// k: summed bits, carried by both) is, per item, a batch of complex GEMMs.
+// With at least 4 i bits and 4 j bits it runs on the matrix cores in the
+// 16-block 4x4 forms, whose lanes match the item-major memory rows: lane l
+// of an operand holds item l / 4 and tile row (A) or column (B) l % 4, and
+// result register r of lane l is row r, column l % 4 of item l / 4.
+//   complex64: v_mfma_f32_4x4x1_16b_f32, four real rank-1 updates per k
+//     (Cr += ar br - ai bi, Ci += ar bi + ai br);
+//   BF16x3: v_mfma_f32_4x4x4_16b_bf16 with each real product split into the
+//     three bfloat16 products hi*hi + hi*lo + lo*hi (x = hi + lo, hi and lo
+//     rounded to bfloat16; lo*lo is dropped).  A k step contributes six
+//     terms to Cr and six to Ci; two k steps fill three 4-term MFMAs of each.
+// A wavefront owns a 16 x 16 tile (4 x 4 MFMA blocks) of 16 items; the four
+// wavefronts of a block cover 2 x 2 tiles of the same items when there are
+// at least 5 i and 5 j bits, else more items.  The operand rows a block
+// needs for one k (a "unit": two k for BF16x3) are copied from HBM straight
+// into LDS (16 bytes per lane, no registers) through a ring of P stages, so
+// P - 1 units of loads are in flight behind the matrix-core work; each unit
+// costs one block barrier.  Blocks are numbered so that each XCD (block
+// index mod 8) runs a contiguous range of tiles, j fastest within bands of
+// 4 j blocks, so the operand panels a band shares stay in that XCD's L2.
+// Returns false when the step does not qualify; lds_bytes receives the LDS
+// the step needs.
+bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
+                    const std::vector<const int32_t*>& rec, int& lds_bytes) {
   if (kind != ST_ELIM || rec.size() != 2 || rec[0][0] != WOP_ITEM || rec[1][0] != WOP_ITEM) return false;
+  if (ns < 1 || (prec != 1 && prec != 2)) return false;
   const int32_t* A = rec[0];
   const int32_t* B = rec[1];
-  std::vector<int> bb, bi, bj, bk;
+  std::vector<int> bb, bi, bj;
   for (int j = 0; j < r; ++j) {
     const bool a = A[16 + j] != 0, b = B[16 + j] != 0;
     if (a && b) bb.push_back(j);
@@ -60,92 +69,200 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
     else if (b) bj.push_back(j);
     else return false;
   }
-  for (int j = 0; j < ns; ++j) {
+  for (int j = 0; j < ns; ++j)
     if (A[48 + j] == 0 || B[48 + j] == 0) return false;
-    bk.push_back(j);
-  }
-  if (bi.size() < 5 || bj.size() < 5 || bk.empty()) return false;
-  // grid: item quarter (2 bits), remaining j bits, remaining i bits, b bits
-  std::vector<int> gj(bj.begin() + 5, bj.end()), gi(bi.begin() + 5, bi.end());
-  const int grid_bits = 2 + (int)gj.size() + (int)gi.size() + (int)bb.size();
+  if (bi.size() < 4 || bj.size() < 4) return false;
+  const int WI = bi.size() >= 5 ? 2 : 1, WJ = bj.size() >= 5 ? 2 : 1, WQ = 4 / (WI * WJ);
+  const int li = WI == 2 ? 5 : 4, lj = WJ == 2 ? 5 : 4;  // i / j bits inside a block
+  const int nbi = (int)bi.size() - li, nbj = (int)bj.size() - lj, nbb = (int)bb.size();
+  const int nqg = 4 / WQ;  // item groups of 16 * WQ items
+  const int grid_bits = nbj + nbi + nbb + (nqg == 4 ? 2 : nqg == 2 ? 1 : 0);
   const unsigned long long nb = 1ull << grid_bits;
+  const int nk = 1 << ns;
+  const int per = prec == 1 ? 1 : 2;                 // k steps per unit
+  const int nu = nk / per;                            // units
+  const int a_bytes = 16 * WI * 16 * WQ * 8;          // A rows of one k
+  const int b_bytes = 16 * WJ * 16 * WQ * 8;
+  const int stage = per * (a_bytes + b_bytes);
+  const int P = std::max(2, std::min(8, 65536 / stage));
+  lds_bytes = P * stage;
+  const int nA = a_bytes / 1024, nB = b_bytes / 1024;  // 1 KiB copies per k
+  const int n_ins = per * (nA + nB), per_wave = n_ins / 4;
+  // block ranges start at multiples of 8 so that blk & 7 is the XCD
+  k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
     << "  // step " << si << " (matrix cores)\n"
-    << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
-    << "  const int lid = threadIdx.x & 63;\n"
-    << "  const int q0 = (int)(g & 3ull) * 16 + (int)wv * 4;\n";  // first item of the wavefront
+    << "  const unsigned long long g = blk - " << k.blocks << "ull;\n";
+  if (nb >= 8)
+    o << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
+  else
+    o << "  const unsigned long long tx = g;\n";
   k.blocks += nb;
   k.steps.push_back(si);
   k.mfma_steps += 1;
   k.mfma_flops += 8.0 * (double)(1ull << (r + ns));
-  // block bases of A, B and the output from the grid bits
-  auto grid_sum = [&](const std::function<long long(int)>& stride_of_out_bit) {
+  // tile index bits, fastest first: j blocks inside a band of up to 4, i
+  // blocks, the remaining j bits (bands), b bits, item groups
+  const int jband = std::min(nbj, 2);
+  std::vector<std::pair<int, int>> bits;  // (kind 0 = j, 1 = i, 2 = b; out bit)
+  for (int t = 0; t < jband; ++t) bits.push_back({0, bj[lj + t]});
+  for (int t = 0; t < nbi; ++t) bits.push_back({1, bi[li + t]});
+  for (int t = jband; t < nbj; ++t) bits.push_back({0, bj[lj + t]});
+  for (int t = 0; t < nbb; ++t) bits.push_back({2, bb[t]});
+  auto sum_of = [&](const std::function<long long(int, int)>& stride) {
     std::string e;
-    int pos = 2;
-    for (int j : gj) {
-      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
-                                     std::to_string(stride_of_out_bit(j)) + "ll";
-      ++pos;
-    }
-    for (int j : gi) {
-      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
-                                     std::to_string(stride_of_out_bit(j)) + "ll";
-      ++pos;
-    }
-    for (int j : bb) {
-      if (stride_of_out_bit(j)) e += " + (long long)((g >> " + std::to_string(pos) + ") & 1ull) * " +
-                                     std::to_string(stride_of_out_bit(j)) + "ll";
-      ++pos;
+    for (size_t p = 0; p < bits.size(); ++p) {
+      const long long s = stride(bits[p].first, bits[p].second);
+      if (s) e += " + (long long)((tx >> " + std::to_string(p) + ") & 1ull) * " + std::to_string(s) + "ll";
     }
     return e;
   };
-  o << "  const long long ba = " << A[1] << "ll" << grid_sum([&](int j) { return (long long)A[16 + j]; }) << ";\n"
-    << "  const long long bbv = " << B[1] << "ll" << grid_sum([&](int j) { return (long long)B[16 + j]; }) << ";\n"
-    << "  const long long bo = " << out << "ll" << grid_sum([&](int j) { return 1ll << j; }) << ";\n";
-  // per-lane tile row of A and tile column of B
-  o << "  const int tr = lid & 31;\n"
-    << "  const long long la = ba";
-  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << A[16 + bi[t]] << "ll";
-  o << ";\n  const long long lb = bbv";
-  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << B[16 + bj[t]] << "ll";
-  o << ";\n  const int hi = lid >> 5;\n"
-    << "  f32x32 cr0 = {}, ci0 = {}, cr1 = {}, ci1 = {};\n"
-    << "  #pragma unroll 2\n"
-    << "  for (int kk = 0; kk < " << (1 << ns) << "; ++kk) {\n"
-    << "    const long long ka = la";
-  for (size_t t = 0; t < bk.size(); ++t) o << " + (long long)((kk >> " << t << ") & 1) * " << A[48 + bk[t]] << "ll";
-  o << ";\n    const long long kb = lb";
-  for (size_t t = 0; t < bk.size(); ++t) o << " + (long long)((kk >> " << t << ") & 1) * " << B[48 + bk[t]] << "ll";
-  o << ";\n"
-    << "    const C2 a0 = gm[ka * 64ll + q0 + hi];\n"
-    << "    const C2 b0 = gm[kb * 64ll + q0 + hi];\n"
-    << "    const C2 a1 = gm[ka * 64ll + q0 + 2 + hi];\n"
-    << "    const C2 b1 = gm[kb * 64ll + q0 + 2 + hi];\n"
-    << "    cr0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.x, b0.x, cr0, 0, 0, 0);\n"
-    << "    ci0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.x, b0.y, ci0, 0, 0, 0);\n"
-    << "    cr1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.x, b1.x, cr1, 0, 0, 0);\n"
-    << "    ci1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.x, b1.y, ci1, 0, 0, 0);\n"
-    << "    cr0 = __builtin_amdgcn_mfma_f32_32x32x1f32(-a0.y, b0.y, cr0, 0, 0, 0);\n"
-    << "    ci0 = __builtin_amdgcn_mfma_f32_32x32x1f32(a0.y, b0.x, ci0, 0, 0, 0);\n"
-    << "    cr1 = __builtin_amdgcn_mfma_f32_32x32x1f32(-a1.y, b1.y, cr1, 0, 0, 0);\n"
-    << "    ci1 = __builtin_amdgcn_mfma_f32_32x32x1f32(a1.y, b1.x, ci1, 0, 0, 0);\n"
-    << "  }\n";
-  // results: register r -> item r / 16 of the pair, tile row
-  // 8 (r % 16 / 4) + 4 hi + r % 4, tile column lid % 32
-  o << "  const long long oc = bo";
-  for (int t = 0; t < 5; ++t) o << " + (long long)((tr >> " << t << ") & 1) * " << (1ll << bj[t]) << "ll";
-  o << ";\n  const long long oh = hi ? " << (1ll << bi[2]) << "ll : 0ll;\n";
-  for (int rr = 0; rr < 32; ++rr) {
-    const int row = 8 * ((rr % 16) / 4) + (rr % 4);  // without the 4 hi term
-    long long off = 0;
-    for (int t = 0; t < 5; ++t)
-      if ((row >> t) & 1) off += 1ll << bi[t];
-    const int item = rr / 16;
-    o << "  gm[(oc + oh + " << off << "ll) * 64ll + q0 + " << item << "] = C2{cr0[" << rr << "], ci0[" << rr
-      << "]};\n"
-      << "  gm[(oc + oh + " << off << "ll) * 64ll + q0 + 2 + " << item << "] = C2{cr1[" << rr << "], ci1[" << rr
-      << "]};\n";
+  const size_t qpos = bits.size();
+  // row (A) / column (B) offset of block-local index x over the operand's
+  // bits v[0..]
+  auto idx_off = [&](const int32_t* X, const std::vector<int>& v, const std::string& x, int nbits) {
+    std::string e;
+    for (int t = 0; t < nbits; ++t)
+      e += " + (long long)(((" + x + ") >> " + std::to_string(t) + ") & 1) * " + std::to_string(X[16 + v[t]]) + "ll";
+    return e;
+  };
+  auto koff = [&](const int32_t* X, const std::string& kv) {
+    std::string e;
+    for (int t = 0; t < ns; ++t)
+      e += " + (long long)(((" + kv + ") >> " + std::to_string(t) + ") & 1) * " + std::to_string(X[48 + t]) + "ll";
+    return e;
+  };
+  o << "  const int lid = threadIdx.x & 63, sub = lid & 3, w4 = (int)wv;\n"
+    << "  const int wi = " << (WI == 2 ? "w4 & 1" : "0") << ", wj = "
+    << (WJ == 2 ? (WI == 2 ? "(w4 >> 1) & 1" : "w4 & 1") : "0")
+    << ", wq = " << (WQ == 1 ? "0" : WI * WJ == 2 ? "w4 >> 1" : "w4") << ";\n"
+    << "  const long long itb = (long long)(" << (nqg > 1 ? "(tx >> " + std::to_string(qpos) + ")" : "0ull")
+    << " * " << 16 * WQ << "ull);\n"
+    << "  const long long ba = " << A[1] << "ll" << sum_of([&](int kd, int b) { return kd == 0 ? 0ll : (long long)A[16 + b]; })
+    << ";\n"
+    << "  const long long bbk = " << B[1] << "ll" << sum_of([&](int kd, int b) { return kd == 1 ? 0ll : (long long)B[16 + b]; })
+    << ";\n"
+    << "  const long long lo = " << out << "ll" << sum_of([&](int, int b) { return 1ll << b; })
+    << (WI == 2 ? " + (long long)wi * " + std::to_string(1ll << bi[4]) + "ll" : "")
+    << (WJ == 2 ? " + (long long)wj * " + std::to_string(1ll << bj[4]) + "ll" : "")
+    << " + (long long)(sub & 1) * " << (1ll << bj[0]) << "ll + (long long)(sub >> 1) * " << (1ll << bj[1]) << "ll;\n"
+    << "  const int it = (int)itb + wq * 16 + (lid >> 2);\n";
+  // Copies: instruction j = 4 q + wave of a unit; j < per nA: A rows, else
+  // B rows.  A copy moves 1 KiB = 1024 / (128 WQ) rows of 16 WQ items: lane
+  // l takes row l / (8 WQ) of it and 16-byte chunk l % (8 WQ) (items 2c,
+  // 2c + 1).  Per copy: the lane's element offset without the k part, and
+  // the LDS byte offset inside a stage.
+  const int rows_per = 8 / WQ;
+  o << "  const int lrow = lid / " << 8 * WQ << ", lch = lid % " << 8 * WQ << ";\n";
+  for (int q = 0; q < per_wave; ++q) {
+    o << "  const int j" << q << " = " << 4 * q << " + w4;\n";
+    // which operand and which k of the unit: the A copies come first
+    o << "  const bool isa" << q << " = j" << q << " < " << per * nA << ";\n"
+      << "  const int jr" << q << " = isa" << q << " ? j" << q << " : j" << q << " - " << per * nA << ";\n"
+      << "  const int h" << q << " = isa" << q << " ? jr" << q << " / " << nA << " : jr" << q << " / " << nB << ";\n"
+      << "  const int c" << q << " = isa" << q << " ? jr" << q << " % " << nA << " : jr" << q << " % " << nB << ";\n"
+      << "  const int rw" << q << " = c" << q << " * " << rows_per << " + lrow;\n"
+      << "  const long long eo" << q << " = isa" << q << " ? ba" << idx_off(A, bi, "rw" + std::to_string(q), li)
+      << " : bbk" << idx_off(B, bj, "rw" + std::to_string(q), lj) << ";\n"
+      << "  const unsigned lds" << q << " = (unsigned)(h" << q << " * " << (a_bytes + b_bytes) << " + (isa" << q
+      << " ? 0 : " << a_bytes << ") + c" << q << " * 1024);\n";
   }
+  auto issue = [&](const std::string& unit, const std::string& stg) {
+    for (int q = 0; q < per_wave; ++q) {
+      const std::string Q = std::to_string(q);
+      const std::string kv = per == 1 ? "(" + unit + ")" : "(2 * (" + unit + ") + h" + Q + ")";
+      o << "    {\n"
+        << "    const long long e = eo" << Q << " + (isa" << Q << " ? 0ll" << koff(A, kv) << " : 0ll" << koff(B, kv)
+        << ");\n"
+        << "    __builtin_amdgcn_global_load_lds((const void*)(gm + e * 64ll + itb + 2 * lch), "
+        << "(__attribute__((address_space(3))) void*)(lds + (" << stg << ") * " << stage << " + lds" << Q
+        << "), 16, 0, 0);\n"
+        << "    }\n";
+    }
+  };
+  for (int g = 0; g < 4; ++g)
+    o << "  f32x4 cr" << g << "_0 = {}, cr" << g << "_1 = {}, cr" << g << "_2 = {}, cr" << g << "_3 = {};\n"
+      << "  f32x4 ci" << g << "_0 = {}, ci" << g << "_1 = {}, ci" << g << "_2 = {}, ci" << g << "_3 = {};\n";
+  // prologue: units 0 .. P - 2 (clamped to the last unit)
+  for (int s = 0; s < P - 1; ++s) issue(std::to_string(std::min(s, nu - 1)), std::to_string(s));
+  // vmcnt(N) and lgkmcnt(0): this wave's copies of unit u have landed and
+  // its LDS reads of unit u - 1 have completed (a read still in flight at
+  // the barrier could see the copy another wave issues right after it into
+  // that stage)
+  const int N = (P - 2) * per_wave;
+  const int wait_imm = (N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14);
+  o << "  for (int u = 0; u < " << nu << "; ++u) {\n"
+    << "    __builtin_amdgcn_s_waitcnt(" << wait_imm << ");\n"
+    << "    __builtin_amdgcn_s_barrier();  // every wave's copies of unit u are in LDS\n"
+    << "    {\n"
+    << "    const int un = u + " << P - 1 << " < " << nu << " ? u + " << P - 1 << " : " << nu - 1 << ";\n";
+  issue("un", "(u + " + std::to_string(P - 1) + ") % " + std::to_string(P));
+  o << "    }\n"
+    << "    const char* sb = lds + (u % " << P << ") * " << stage << ";\n";
+  // operand reads: A row 16 wi + 4 rg + sub, B column 16 wj + 4 cg + sub,
+  // item 16 wq + lid / 4
+  for (int h = 0; h < per; ++h) {
+    for (int g = 0; g < 4; ++g)
+      o << "    const C2 a" << h << "_" << g << " = *(const C2*)(sb + " << h * (a_bytes + b_bytes) << " + ((16 * wi + "
+        << 4 * g << " + sub) * " << 16 * WQ << " + 16 * wq + (lid >> 2)) * 8);\n";
+    for (int g = 0; g < 4; ++g)
+      o << "    const C2 b" << h << "_" << g << " = *(const C2*)(sb + " << h * (a_bytes + b_bytes) + a_bytes
+        << " + ((16 * wj + " << 4 * g << " + sub) * " << 16 * WQ << " + 16 * wq + (lid >> 2)) * 8);\n";
+  }
+  if (prec == 1) {
+    for (int g = 0; g < 4; ++g) o << "    const float na" << g << " = -a0_" << g << ".y;\n";
+    for (int rg = 0; rg < 4; ++rg)
+      for (int cg = 0; cg < 4; ++cg) {
+        const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
+        const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
+        const std::string a = "a0_" + std::to_string(rg), b = "b0_" + std::to_string(cg);
+        o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".x, " << cr << ", 0, 0, 0);\n"
+          << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".y, " << ci << ", 0, 0, 0);\n"
+          << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(na" << rg << ", " << b << ".y, " << cr << ", 0, 0, 0);\n"
+          << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".y, " << b << ".x, " << ci << ", 0, 0, 0);\n";
+      }
+  } else {
+    // two k steps per unit: 12 terms for Cr and 12 for Ci in three 4-slot
+    // bfloat16 operands each; the A slots are shared by Cr and Ci.
+    //   A: (rh rh rl ih | ih il) per k;  B for Cr: (rh rl rh -ih | -il -ih);
+    //   B for Ci: (ih il ih rh | rl rh)   (r = real, i = imaginary part)
+    for (int g = 0; g < 4; ++g) {
+      const std::string G = std::to_string(g);
+      o << "    s16x4 A" << G << "_0, A" << G << "_1, A" << G << "_2;\n"
+        << "    bsplit(a0_" << G << ", a1_" << G << ", A" << G << "_0, A" << G << "_1, A" << G << "_2);\n"
+        << "    s16x4 R" << G << "_0, R" << G << "_1, R" << G << "_2, I" << G << "_0, I" << G << "_1, I" << G << "_2;\n"
+        << "    bsplitb(b0_" << G << ", b1_" << G << ", R" << G << "_0, R" << G << "_1, R" << G << "_2, I" << G << "_0, I"
+        << G << "_1, I" << G << "_2);\n";
+    }
+    for (int rg = 0; rg < 4; ++rg)
+      for (int cg = 0; cg < 4; ++cg) {
+        const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
+        const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
+        for (int t = 0; t < 3; ++t) {
+          const std::string a = "A" + std::to_string(rg) + "_" + std::to_string(t);
+          const std::string rr = "R" + std::to_string(cg) + "_" + std::to_string(t);
+          const std::string ii = "I" + std::to_string(cg) + "_" + std::to_string(t);
+          o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << rr << ", " << cr << ", 0, 0, 0);\n"
+            << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << ii << ", " << ci << ", 0, 0, 0);\n";
+        }
+      }
+  }
+  o << "  }\n"
+    << "  __builtin_amdgcn_s_waitcnt(" << ((7 << 4) | (15 << 8)) << ");  // no copy left in flight\n";
+  // results: register e of block (rg, cg) -> row bits (e, rg) on i bits
+  // 0..3, column bits (sub, cg) on j bits 0..3, item it
+  for (int rg = 0; rg < 4; ++rg)
+    for (int cg = 0; cg < 4; ++cg)
+      for (int e = 0; e < 4; ++e) {
+        const int row = e + 4 * rg;
+        long long off = 0;
+        for (int t = 0; t < 4; ++t)
+          if ((row >> t) & 1) off += 1ll << bi[t];
+        if (cg & 1) off += 1ll << bj[2];
+        if (cg & 2) off += 1ll << bj[3];
+        o << "  gm[(lo + " << off << "ll) * 64ll + it] = C2{cr" << rg << "_" << cg << "[" << e << "], ci" << rg << "_" << cg << "[" << e
+          << "]};\n";
+      }
   o << "  return;\n  }\n";
   return true;
 }
@@ -156,14 +273,33 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
   std::ostringstream o;
   o << "typedef " << (prec == 0 ? "double" : "float") << " R;\n"
     << "struct C2 { R x, y; };\n"
-    << "typedef float f32x32 __attribute__((ext_vector_type(32)));\n";
+    << "typedef float f32x4 __attribute__((ext_vector_type(4)));\n"
+    << "typedef short s16x4 __attribute__((ext_vector_type(4)));\n";
   if (prec == 2)
     o << "static __device__ __forceinline__ float bh(float x) { unsigned u = __float_as_uint(x); "
          "u += 0x7FFFu + ((u >> 16) & 1u); return __uint_as_float(u & 0xFFFF0000u); }\n"
          "static __device__ __forceinline__ float m3(float a, float b) { const float ah = bh(a), al = bh(a - ah), "
          "bh_ = bh(b), bl = bh(b - bh_); return ah * bh_ + (ah * bl + al * bh_); }\n"
          "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = m3(a.x, b.x) - m3(a.y, b.y); "
-         "c.y = m3(a.x, b.y) + m3(a.y, b.x); return c; }\n";
+         "c.y = m3(a.x, b.y) + m3(a.y, b.x); return c; }\n"
+         // bfloat16 halves for the matrix-core form: x = hi + lo, each
+         // rounded to nearest even; bit patterns as shorts
+         "static __device__ __forceinline__ short bhi(float x, float& rest) { unsigned u = __float_as_uint(x); "
+         "u += 0x7FFFu + ((u >> 16) & 1u); u &= 0xFFFF0000u; rest = x - __uint_as_float(u); return (short)(u >> 16); }\n"
+         "static __device__ __forceinline__ short blo(float x) { unsigned u = __float_as_uint(x); "
+         "u += 0x7FFFu + ((u >> 16) & 1u); return (short)(u >> 16); }\n"
+         "static __device__ __forceinline__ short bneg(short x) { return (short)(x ^ (short)0x8000); }\n"
+         "static __device__ __forceinline__ void bsplit(C2 p, C2 q, s16x4& A0, s16x4& A1, s16x4& A2) { float t; "
+         "const short prh = bhi(p.x, t), prl = blo(t); const short pih = bhi(p.y, t), pil = blo(t); "
+         "const short qrh = bhi(q.x, t), qrl = blo(t); const short qih = bhi(q.y, t), qil = blo(t); "
+         "A0 = s16x4{prh, prh, prl, pih}; A1 = s16x4{pih, pil, qrh, qrh}; A2 = s16x4{qrl, qih, qih, qil}; }\n"
+         "static __device__ __forceinline__ void bsplitb(C2 p, C2 q, s16x4& R0, s16x4& R1, s16x4& R2, s16x4& I0, "
+         "s16x4& I1, s16x4& I2) { float t; "
+         "const short prh = bhi(p.x, t), prl = blo(t); const short pih = bhi(p.y, t), pil = blo(t); "
+         "const short qrh = bhi(q.x, t), qrl = blo(t); const short qih = bhi(q.y, t), qil = blo(t); "
+         "R0 = s16x4{prh, prl, prh, bneg(pih)}; R1 = s16x4{bneg(pil), bneg(pih), qrh, qrl}; "
+         "R2 = s16x4{qrh, bneg(qih), bneg(qil), bneg(qih)}; "
+         "I0 = s16x4{pih, pil, pih, prh}; I1 = s16x4{prl, prh, qih, qil}; I2 = s16x4{qih, qrh, qrl, qrh}; }\n";
   else
     o << "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = a.x * b.x - a.y * b.y; "
          "c.y = a.x * b.y + a.y * b.x; return c; }\n";
@@ -205,16 +341,23 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
     n_levels = std::max(n_levels, lev + 1);
   }
   // one kernel per level; a block runs 4 wavefront tiles of one of its steps
+  std::vector<int> level_lds(n_levels, 0);  // LDS of the level's matrix-core steps
   for (int lev = 0; lev < n_levels; ++lev) {
     WideKernel k;
     k.kind = 0;
     k.name = "wl" + std::to_string(lev);
     k.blocks = 0;
-    o << "extern \"C\" __global__ void __launch_bounds__(256) " << k.name
+    // Two wavefronts per SIMD: caps a wavefront at 256 registers, which
+    // also makes the compiler keep matrix-core accumulators in ordinary
+    // VGPRs (with 512 it places them in AGPRs and copies them between
+    // register sets inside the K loops).
+    o << "extern \"C\" __global__ void __launch_bounds__(256) "
+      << (mfma && prec != 0 ? "__attribute__((amdgpu_waves_per_eu(2))) " : "") << k.name
       << "(C2* __restrict__ mem, const C2* __restrict__ cst, const unsigned long long* __restrict__ packed, "
          "unsigned long long group_elems, unsigned long long s_begin, unsigned long long n_s, int group0, "
          "int ns_log2, unsigned long long n_items, unsigned long long n_bs, C2* __restrict__ res, "
          "C2* __restrict__ gres) {\n"
+      << "/*LDS" << lev << "*/\n"
       << "  const int lane = threadIdx.x & 63;\n"
       << "  const unsigned long long wv = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
       << "  unsigned long long item = (unsigned long long)(group0 + blockIdx.y) * 64ull + lane;\n"
@@ -240,7 +383,11 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
       std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
-      if (prec == 1 && mfma && emit_mfma_step(o, k, si, kind, out, r, ns, rec)) continue;
+      int lds_bytes = 0;
+      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes)) {
+        level_lds[lev] = std::max(level_lds[lev], lds_bytes);
+        continue;
+      }
       // Iteration order of the output bits: those that fewer item operands
       // depend on come first (inside the tile, then across neighbouring
       // wavefronts), so an operand row is reused within a tile or soon after
@@ -431,7 +578,17 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
   flush_run();
   (void)lit;
   (void)prog;
-  return o.str();
+  // the LDS ring of each level kernel with matrix-core steps
+  std::string src = o.str();
+  for (int lev = 0; lev < n_levels; ++lev) {
+    const std::string mark = "/*LDS" + std::to_string(lev) + "*/";
+    const size_t at = src.find(mark);
+    if (at == std::string::npos) continue;
+    src.replace(at, mark.size(),
+                level_lds[lev] ? "  __shared__ __attribute__((aligned(16))) char lds[" + std::to_string(level_lds[lev]) + "];"
+                               : std::string());
+  }
+  return src;
 }
 
 }  // namespace qgm

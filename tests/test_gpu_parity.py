@@ -541,7 +541,7 @@ def _stored(name):
 
 
 def test_matrix_core_steps_7x7x30():
-    """Wide engine, complex64, two-operand contractions on the matrix cores:
+    """Wide engine, complex64 and BF16x3, two-operand contractions on the matrix cores:
     amplitudes against the complex128 path (pinned to the oracle) and the
     vector-only complex64 path, and single slices against the oracle."""
     text, sl, order = _stored("7x7x30")
@@ -557,6 +557,13 @@ def test_matrix_core_steps_7x7x30():
     note("max err mfma", nerr(am, ad, 49).max(), "vector", nerr(av, ad, 49).max())
     assert nerr(am, ad, 49).max() <= C64_TOL
     assert nerr(av, ad, 49).max() <= C64_TOL
+    pb = q.Plan(c, sl, order, prec=q.QGM_BF16X3, engine=q.QGM_ENGINE_WIDE)
+    pbv = q.Plan(c, sl, order, prec=q.QGM_BF16X3, engine=q.QGM_ENGINE_WIDE, vector_only=True)
+    assert pb.stats()["mfma_steps"] == sm["mfma_steps"] and pbv.stats()["mfma_steps"] == 0
+    ab, abv = pb.amplitudes(bits), pbv.amplitudes(bits)
+    note("max err bf16x3 mfma", nerr(ab, ad, 49).max(), "vector", nerr(abv, ad, 49).max())
+    assert nerr(ab, ad, 49).max() <= BF16X3_TOL
+    assert nerr(abv, ad, 49).max() <= BF16X3_TOL
     net = oracle.build_network(text)
     scale = 2.0 ** -24.5 / 2.0 ** 3
     for s in (0, 45):
@@ -585,7 +592,10 @@ def test_matrix_core_steps_8x8x40():
         part = p.amplitudes_range([x], None, s0, s1)[0]
         return part[0] + part[2] + 1j * (part[1] + part[3])
 
+    pb = q.Plan(c, sl, order, prec=q.QGM_BF16X3, engine=q.QGM_ENGINE_WIDE)
+    assert pb.stats()["mfma_steps"] == sm["mfma_steps"]
     for s0, s1 in ((0, 64), (100, 101), (4095, 4096), (8191, 8192)):
-        got, ref = val(pm, s0, s1), val(pd, s0, s1)
-        note("slices", s0, s1, "mfma", got, "c128", ref)
+        got, ref, gb = val(pm, s0, s1), val(pd, s0, s1), val(pb, s0, s1)
+        note("slices", s0, s1, "mfma", got, "bf16x3", gb, "c128", ref)
         assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
+        assert abs(gb - ref) / max(abs(ref), scale) <= BF16X3_TOL
