@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published vector FP32 peak
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X published dense FP32 matrix-core peak
+PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X published dense BF16 matrix-core peak
 
 
 
@@ -93,6 +94,9 @@ def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
     for _ in range(warmup):
         q.qgm_amplitudes_device(plan.h, d_bits, None, 0, n_s, ws, d_part, stream)
     torch.cuda.synchronize()
+    levels = None
+    if plan.stats()["engine"] == q.QGM_ENGINE_WIDE:
+        levels = q.qgm_plan_level_timing(plan.h, reset=False)  # per level kernel: ms, flops/slice, mfma steps
     (ms_pro, ms_chain, ms_red), n_runs = q.qgm_plan_timing(plan.h, reset=True)
     g = q.qgm_graph_create(plan.h, d_bits, None, 0, n_s, ws, d_part, repeat=steps)
     q.qgm_graph_launch(g, stream)  # first replay outside the timed region
@@ -111,7 +115,7 @@ def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
     part = d_part.cpu().numpy()
     amps = part[:, 0] + part[:, 2] + 1j * (part[:, 1] + part[:, 3])
     return dict(wall=wall, gpu_ms_step=gpu_ms / steps, ms_chain=ms_chain, ms_pro=ms_pro, ms_red=ms_red, amps=amps,
-                n_runs=n_runs)
+                n_runs=n_runs, levels=levels)
 
 
 def main():
@@ -212,24 +216,36 @@ def main():
     achieved = flops_launch / (r["ms_chain"] * 1e-3) / 1e12
     bytes_launch = st["bytes_item"] * n_items
     wide = st["engine"] == 3
-    # The wide engine is priced against whichever of its two ceilings it is
-    # closer to: HBM bytes (every intermediate written and read once) or
-    # vector FP32 flops; the others are ALU/latency bound.
+    # Roofline of the dominant kernel.  Wide engine: the level kernel (one
+    # launch of independent steps) with the longest HIP-event duration; with
+    # matrix-core steps it is priced against the FP32 matrix peak (complex64
+    # runs as FP32 MFMA), else against vector FP32.  The generated and
+    # interpreter engines run one kernel per call (the item chain).
     gbs = bytes_launch / (r["ms_chain"] * 1e-3) / 1e9
-    if not wide or achieved / PEAK_FP32_VECTOR_TFLOPS >= gbs / PEAK_HBM_GBS:
+    if wide and r["levels"] and r["levels"][0]:
+        ms_l, fl_l, mf_l, _ = r["levels"]
+        i = max(range(len(ms_l)), key=lambda j: ms_l[j])
+        k_flops = fl_l[i] * n_items
+        k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
+        peak = PEAK_FP32_MATRIX_TFLOPS if mf_l[i] else PEAK_FP32_VECTOR_TFLOPS
+        roofline = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
+                    "frac": k_tf / peak, "traffic": None, "kernel": f"wl{i} (generated level kernel)",
+                    "kernel_ms": ms_l[i], "flops_per_launch": k_flops, "matrix_core_steps": mf_l[i],
+                    "chain_ms": r["ms_chain"], "chain_tflops": achieved, "chain_hbm_gbs": gbs,
+                    "chain_bytes_per_launch": bytes_launch,
+                    "chain_hbm_frac": gbs / PEAK_HBM_GBS}
+        # the kernels on the matrix cores together
+        mk = [j for j in range(len(ms_l)) if mf_l[j]]
+        if mk:
+            roofline["matrix_core_kernels_ms"] = sum(ms_l[j] for j in mk)
+            roofline["matrix_core_kernels_tflops"] = (sum(fl_l[j] for j in mk) * n_items
+                                                       / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12)
+    else:
         roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
                     "kernel": {1: "chain_kernel<float>", 2: "qgm_chain (generated)",
                                3: "generated wide step kernels (all levels of a run)"}[st["engine"]],
                     "kernel_ms": r["ms_chain"], "flops_per_launch": flops_launch}
-    else:
-        roofline = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "traffic": None, "kernel": "generated wide step kernels (all levels of a run)",
-                    "kernel_ms": r["ms_chain"], "flops_per_launch": flops_launch}
-    if wide:
-        roofline["bytes_per_launch"] = bytes_launch
-        roofline["hbm_gbs"] = gbs
-        roofline["tflops"] = achieved
     line = {
         "metric": "slice contractions/sec",
         "value": value,
@@ -256,11 +272,9 @@ def main():
                   "kernel_ms = HIP events around each kernel over the warm-up runs",
         "gpu_ms_per_step": r["gpu_ms_step"],
         "amplitude_error_c64": nerr(r["amps"]),
-        # share of the slice flops on the matrix cores, and those flops per
-        # second of the whole chain against the FP32 matrix peak
+        # share of the slice flops on the matrix cores
         "mfma_flops_share": st["flops_mfma"] / st["flops_item"],
         "mfma_steps": st["mfma_steps"],
-        "mfma_util_fp32": st["flops_mfma"] * n_items / (r["ms_chain"] * 1e-3) / 1e12 / PEAK_FP32_MATRIX_TFLOPS,
         "kernel_ms": {"prologue": r["ms_pro"], "chain": r["ms_chain"], "reduce": r["ms_red"]},
     }
     if n_run is not None:
@@ -269,8 +283,20 @@ def main():
         line["slices_timed"] = n_items
         line["projected_full_sum_s"] = per_slice_ms * 1e-3 * (1 << k) * n_bs
     if "bf16x3" in results:
-        line["bf16x3_value"] = n_items / (results["bf16x3"]["wall"] / args.steps)
-        line["amplitude_error_bf16x3"] = nerr(results["bf16x3"]["amps"])
+        rb = results["bf16x3"]
+        line["bf16x3_value"] = n_items / (rb["wall"] / args.steps)
+        line["amplitude_error_bf16x3"] = nerr(rb["amps"])
+        if rb["levels"] and rb["levels"][0]:
+            # BF16x3 performs three bfloat16 products per real product: its
+            # matrix-core kernels execute 3x the useful flops in bf16
+            ms_l, fl_l, mf_l, _ = rb["levels"]
+            mk = [j for j in range(len(ms_l)) if mf_l[j]]
+            if mk:
+                tf = sum(fl_l[j] for j in mk) * n_items / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12
+                line["bf16x3_matrix_core_kernels_tflops"] = tf
+                line["bf16x3_mfma_frac_bf16_peak"] = 3 * tf / PEAK_BF16_MATRIX_TFLOPS
+    if "matrix_core_kernels_tflops" in roofline:
+        line["c64_mfma_frac_fp32_peak"] = roofline["matrix_core_kernels_tflops"] / PEAK_FP32_MATRIX_TFLOPS
     a0 = complex(r["amps"][0])
     line["amplitude_first_bitstring"] = [a0.real, a0.imag]
     if "c128" in results:

@@ -201,6 +201,19 @@ def qgm_plan_timing(p, reset: bool = True):
     return (ms[0], ms[1], ms[2]), n.value
 
 
+def qgm_plan_level_timing(p, reset: bool = True):
+    """Per level kernel of a WIDE plan: (ms, flops_item, mfma_steps) lists and
+    the number of runs averaged."""
+    nl, nr = C.c_int32(), C.c_int32()
+    check(lib.qgm_plan_level_timing(p, 0, None, None, None, 0, C.byref(nl), C.byref(nr)))
+    n = nl.value
+    ms = (C.c_double * max(1, n))()
+    fl = (C.c_double * max(1, n))()
+    mf = (C.c_int32 * max(1, n))()
+    check(lib.qgm_plan_level_timing(p, 1 if reset else 0, ms, fl, mf, n, C.byref(nl), C.byref(nr)))
+    return list(ms[:n]), list(fl[:n]), list(mf[:n]), nr.value
+
+
 def qgm_plan_autotune(p, n_bs: int, n_slices: int, workspace, stream=None) -> int:
     """Time the generated kernel's wavefront cuts on the device; keeps the fastest. Returns the wave count."""
     w = C.c_int32()

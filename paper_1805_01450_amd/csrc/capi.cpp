@@ -44,8 +44,11 @@ struct qgm_plan {
   double cost = 0;
   std::mutex mu;
   std::vector<std::array<hipEvent_t, 4>> runs;  // profiling events, one set per run
+  std::vector<std::vector<hipEvent_t>> level_runs;  // WIDE profiling: events around each level launch
   ~qgm_plan() {
     for (auto& r : runs)
+      for (hipEvent_t e : r) (void)hipEventDestroy(e);
+    for (auto& r : level_runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
   }
 };
@@ -459,9 +462,17 @@ qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const d
       if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
     p->runs.push_back(r);
     for (int i = 0; i < 4; ++i) ev[i] = r[i];
+    if (p->engine == QGM_ENGINE_WIDE && !p->dev.wide.levels.empty()) {
+      std::vector<hipEvent_t> le(p->dev.wide.levels.size() + 1);
+      for (auto& e : le)
+        if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
+      p->level_runs.push_back(le);
+      p->dev.wide.level_events = (void* const*)p->level_runs.back().data();
+    }
   }
   int rc = dev_run(p->prog, p->dev, cfg, ws, d_bits, d_params, d_ws, stream, d_partial, d_grad_partial,
                    profile ? ev : nullptr, err);
+  p->dev.wide.level_events = nullptr;
   if (rc) return fail((qgm_status)rc, err);
   return QGM_OK;
 }
@@ -614,6 +625,43 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
     for (auto& r : p->runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->runs.clear();
+    for (auto& r : p->level_runs)
+      for (hipEvent_t e : r) (void)hipEventDestroy(e);
+    p->level_runs.clear();
+  }
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, int32_t* mfma_steps,
+                                 int32_t cap, int32_t* n_levels, int32_t* n_runs) {
+  GUARD_BEGIN
+  if (!p || !n_levels || !n_runs || cap < 0 || (cap > 0 && (!ms || !flops_item || !mfma_steps)))
+    return fail(QGM_E_ARG, "bad argument");
+  if (!p->opts.profile) return fail(QGM_E_ARG, "plan was not created with opts.profile = 1");
+  std::lock_guard<std::mutex> lk(p->mu);
+  std::vector<const WideKernel*> lv;
+  for (const WideKernel& k : p->wide_kernels)
+    if (k.kind == 0) lv.push_back(&k);
+  *n_levels = (int32_t)lv.size();
+  *n_runs = (int32_t)p->level_runs.size();
+  for (int i = 0; i < std::min<int>(cap, (int)lv.size()); ++i) {
+    double acc = 0;
+    for (auto& r : p->level_runs) {
+      if (r.size() != lv.size() + 1) return fail(QGM_E_HIP, "level event count mismatch");
+      if (hipEventSynchronize(r.back()) != hipSuccess) return fail(QGM_E_HIP, "hipEventSynchronize failed");
+      float t = 0;
+      if (hipEventElapsedTime(&t, r[i], r[i + 1]) != hipSuccess) return fail(QGM_E_HIP, "hipEventElapsedTime failed");
+      acc += t;
+    }
+    ms[i] = p->level_runs.empty() ? 0.0 : acc / p->level_runs.size();
+    flops_item[i] = lv[i]->flops;
+    mfma_steps[i] = lv[i]->mfma_steps;
+  }
+  if (reset) {
+    for (auto& r : p->level_runs)
+      for (hipEvent_t e : r) (void)hipEventDestroy(e);
+    p->level_runs.clear();
   }
   return QGM_OK;
   GUARD_END

@@ -79,12 +79,12 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   const int grid_bits = nbj + nbi + nbb + (nqg == 4 ? 2 : nqg == 2 ? 1 : 0);
   const unsigned long long nb = 1ull << grid_bits;
   const int nk = 1 << ns;
-  const int per = prec == 1 ? 1 : 2;                 // k steps per unit
+  const int per = 2;                                  // k steps per unit (one barrier each)
   const int nu = nk / per;                            // units
   const int a_bytes = 16 * WI * 16 * WQ * 8;          // A rows of one k
   const int b_bytes = 16 * WJ * 16 * WQ * 8;
   const int stage = per * (a_bytes + b_bytes);
-  const int P = std::max(2, std::min(8, 65536 / stage));
+  const int P = std::max(2, std::min(8, 53248 / stage));  // three blocks per CU
   lds_bytes = P * stage;
   const int nA = a_bytes / 1024, nB = b_bytes / 1024;  // 1 KiB copies per k
   const int n_ins = per * (nA + nB), per_wave = n_ins / 4;
@@ -210,17 +210,21 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
         << " + ((16 * wj + " << 4 * g << " + sub) * " << 16 * WQ << " + 16 * wq + (lid >> 2)) * 8);\n";
   }
   if (prec == 1) {
-    for (int g = 0; g < 4; ++g) o << "    const float na" << g << " = -a0_" << g << ".y;\n";
-    for (int rg = 0; rg < 4; ++rg)
-      for (int cg = 0; cg < 4; ++cg) {
-        const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
-        const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
-        const std::string a = "a0_" + std::to_string(rg), b = "b0_" + std::to_string(cg);
-        o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".x, " << cr << ", 0, 0, 0);\n"
-          << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".y, " << ci << ", 0, 0, 0);\n"
-          << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(na" << rg << ", " << b << ".y, " << cr << ", 0, 0, 0);\n"
-          << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".y, " << b << ".x, " << ci << ", 0, 0, 0);\n";
-      }
+    for (int h = 0; h < per; ++h) {
+      const std::string H = std::to_string(h);
+      for (int g = 0; g < 4; ++g) o << "    const float na" << H << g << " = -a" << H << "_" << g << ".y;\n";
+      for (int rg = 0; rg < 4; ++rg)
+        for (int cg = 0; cg < 4; ++cg) {
+          const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
+          const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
+          const std::string a = "a" + H + "_" + std::to_string(rg), b = "b" + H + "_" + std::to_string(cg);
+          o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".x, " << cr << ", 0, 0, 0);\n"
+            << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".x, " << b << ".y, " << ci << ", 0, 0, 0);\n"
+            << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x1f32(na" << H << rg << ", " << b << ".y, " << cr
+            << ", 0, 0, 0);\n"
+            << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x1f32(" << a << ".y, " << b << ".x, " << ci << ", 0, 0, 0);\n";
+        }
+    }
   } else {
     // two k steps per unit: 12 terms for Cr and 12 for Ci in three 4-slot
     // bfloat16 operands each; the A slots are shared by Cr and Ci.
@@ -383,6 +387,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
       std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+      if (kind == ST_ELIM || kind == ST_FINAL) k.flops += (double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0);
       int lds_bytes = 0;
       if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes)) {
         level_lds[lev] = std::max(level_lds[lev], lds_bytes);

@@ -23,6 +23,9 @@ struct WideDev {
     unsigned long long blocks;  // 256-thread blocks per 64-item group
   };
   std::vector<Level> levels;
+  // profiling: when set, levels.size() + 1 events recorded on the launch
+  // stream around the level launches of the first pass of a run
+  mutable void* const* level_events = nullptr;
   // constant steps: runs of small steps in one single-block launch (indices
   // in const_list[first, first + count)), large steps alone (first = step)
   struct ConstLaunch {

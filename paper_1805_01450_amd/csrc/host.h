@@ -177,6 +177,7 @@ struct WideKernel {
   std::vector<int> steps;
   int mfma_steps = 0;       // steps of this kernel on the matrix cores
   double mfma_flops = 0.0;  // their flops per item
+  double flops = 0.0;       // flops per item of all its steps
 };
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
                                  std::vector<WideKernel>& kernels, bool mfma);

@@ -222,10 +222,15 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
     void* a_res = res;
     void* a_gres = gres;
     void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
-    for (const WideDev::Level& lv : wd.levels)
+    void* const* ev = first_group == 0 ? wd.level_events : nullptr;
+    for (size_t li = 0; li < wd.levels.size(); ++li) {
+      const WideDev::Level& lv = wd.levels[li];
+      if (ev && hipEventRecord((hipEvent_t)ev[li], stream) != hipSuccess) return -6;
       if (hipModuleLaunchKernel((hipFunction_t)lv.fn, (unsigned)lv.blocks, (unsigned)n_groups, 1, 256, 1, 1, 0, stream,
                                 args, nullptr) != hipSuccess)
         return -6;
+    }
+    if (ev && hipEventRecord((hipEvent_t)ev[wd.levels.size()], stream) != hipSuccess) return -6;
     return hipGetLastError() == hipSuccess ? 0 : -6;
   }
   for (int si = 0; si < wd.n_steps; ++si) {
