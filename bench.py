@@ -223,9 +223,9 @@ def main():
     # interpreter engines run one kernel per call (the item chain).
     gbs = bytes_launch / (r["ms_chain"] * 1e-3) / 1e9
     if wide and r["levels"] and r["levels"][0]:
-        ms_l, fl_l, mf_l, _ = r["levels"]
+        ms_l, fl_l, mf_l, _, items_l = r["levels"]  # the first pass of items is timed
         i = max(range(len(ms_l)), key=lambda j: ms_l[j])
-        k_flops = fl_l[i] * n_items
+        k_flops = fl_l[i] * items_l
         k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
         peak = PEAK_FP32_MATRIX_TFLOPS if mf_l[i] else PEAK_FP32_VECTOR_TFLOPS
         roofline = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
@@ -238,7 +238,7 @@ def main():
         mk = [j for j in range(len(ms_l)) if mf_l[j]]
         if mk:
             roofline["matrix_core_kernels_ms"] = sum(ms_l[j] for j in mk)
-            roofline["matrix_core_kernels_tflops"] = (sum(fl_l[j] for j in mk) * n_items
+            roofline["matrix_core_kernels_tflops"] = (sum(fl_l[j] for j in mk) * items_l
                                                        / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12)
     else:
         roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -289,10 +289,10 @@ def main():
         if rb["levels"] and rb["levels"][0]:
             # BF16x3 performs three bfloat16 products per real product: its
             # matrix-core kernels execute 3x the useful flops in bf16
-            ms_l, fl_l, mf_l, _ = rb["levels"]
+            ms_l, fl_l, mf_l, _, items_l = rb["levels"]
             mk = [j for j in range(len(ms_l)) if mf_l[j]]
             if mk:
-                tf = sum(fl_l[j] for j in mk) * n_items / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12
+                tf = sum(fl_l[j] for j in mk) * items_l / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12
                 line["bf16x3_matrix_core_kernels_tflops"] = tf
                 line["bf16x3_mfma_frac_bf16_peak"] = 3 * tf / PEAK_BF16_MATRIX_TFLOPS
     if "matrix_core_kernels_tflops" in roofline:

@@ -45,6 +45,7 @@ struct qgm_plan {
   std::mutex mu;
   std::vector<std::array<hipEvent_t, 4>> runs;  // profiling events, one set per run
   std::vector<std::vector<hipEvent_t>> level_runs;  // WIDE profiling: events around each level launch
+  std::vector<uint64_t> level_items;                 // items of the pass those events cover
   ~qgm_plan() {
     for (auto& r : runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
@@ -467,6 +468,7 @@ qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const d
       for (auto& e : le)
         if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
       p->level_runs.push_back(le);
+      p->level_items.push_back(std::min<uint64_t>((uint64_t)n_bs * (s_end - s_begin), (uint64_t)ws.wide_groups * 64));
       p->dev.wide.level_events = (void* const*)p->level_runs.back().data();
     }
   }
@@ -628,15 +630,16 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
     for (auto& r : p->level_runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->level_runs.clear();
+    p->level_items.clear();
   }
   return QGM_OK;
   GUARD_END
 }
 
 qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, int32_t* mfma_steps,
-                                 int32_t cap, int32_t* n_levels, int32_t* n_runs) {
+                                 int32_t cap, int32_t* n_levels, int32_t* n_runs, uint64_t* items) {
   GUARD_BEGIN
-  if (!p || !n_levels || !n_runs || cap < 0 || (cap > 0 && (!ms || !flops_item || !mfma_steps)))
+  if (!p || !n_levels || !n_runs || !items || cap < 0 || (cap > 0 && (!ms || !flops_item || !mfma_steps)))
     return fail(QGM_E_ARG, "bad argument");
   if (!p->opts.profile) return fail(QGM_E_ARG, "plan was not created with opts.profile = 1");
   std::lock_guard<std::mutex> lk(p->mu);
@@ -645,6 +648,7 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
     if (k.kind == 0) lv.push_back(&k);
   *n_levels = (int32_t)lv.size();
   *n_runs = (int32_t)p->level_runs.size();
+  *items = p->level_items.empty() ? 0 : p->level_items.back();
   for (int i = 0; i < std::min<int>(cap, (int)lv.size()); ++i) {
     double acc = 0;
     for (auto& r : p->level_runs) {
@@ -662,6 +666,7 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
     for (auto& r : p->level_runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->level_runs.clear();
+    p->level_items.clear();
   }
   return QGM_OK;
   GUARD_END
