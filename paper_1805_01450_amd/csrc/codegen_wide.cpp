@@ -286,24 +286,30 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
          "bh_ = bh(b), bl = bh(b - bh_); return ah * bh_ + (ah * bl + al * bh_); }\n"
          "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = m3(a.x, b.x) - m3(a.y, b.y); "
          "c.y = m3(a.x, b.y) + m3(a.y, b.x); return c; }\n"
-         // bfloat16 halves for the matrix-core form: x = hi + lo, each
-         // rounded to nearest even; bit patterns as shorts
-         "static __device__ __forceinline__ short bhi(float x, float& rest) { unsigned u = __float_as_uint(x); "
-         "u += 0x7FFFu + ((u >> 16) & 1u); u &= 0xFFFF0000u; rest = x - __uint_as_float(u); return (short)(u >> 16); }\n"
-         "static __device__ __forceinline__ short blo(float x) { unsigned u = __float_as_uint(x); "
-         "u += 0x7FFFu + ((u >> 16) & 1u); return (short)(u >> 16); }\n"
-         "static __device__ __forceinline__ short bneg(short x) { return (short)(x ^ (short)0x8000); }\n"
-         "static __device__ __forceinline__ void bsplit(C2 p, C2 q, s16x4& A0, s16x4& A1, s16x4& A2) { float t; "
-         "const short prh = bhi(p.x, t), prl = blo(t); const short pih = bhi(p.y, t), pil = blo(t); "
-         "const short qrh = bhi(q.x, t), qrl = blo(t); const short qih = bhi(q.y, t), qil = blo(t); "
-         "A0 = s16x4{prh, prh, prl, pih}; A1 = s16x4{pih, pil, qrh, qrh}; A2 = s16x4{qrl, qih, qih, qil}; }\n"
+         // bfloat16 halves for the matrix-core form: x = hi + lo, hi and lo
+         // rounded to nearest even (the hardware pack-convert, two at a
+         // time); operands as packed 4 x bfloat16
+         "typedef float f32x2 __attribute__((ext_vector_type(2)));\n"
+         "typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));\n"
+         "static __device__ __forceinline__ unsigned pk(float a, float b) { "
+         "return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2)); }\n"
+         "static __device__ __forceinline__ float lowf(unsigned p) { return __uint_as_float(p << 16); }\n"
+         "static __device__ __forceinline__ s16x4 v4(unsigned lo, unsigned hi) { "
+         "return __builtin_bit_cast(s16x4, (unsigned long long)lo | ((unsigned long long)hi << 32)); }\n"
+         // A slots (rh rh rl ih | ih il) per k, k = p then q
+         "static __device__ __forceinline__ void bsplit(C2 p, C2 q, s16x4& A0, s16x4& A1, s16x4& A2) { "
+         "const unsigned prr = pk(p.x, p.x), pii = pk(p.y, p.y), qrr = pk(q.x, q.x), qii = pk(q.y, q.y); "
+         "const float prl = p.x - lowf(prr), pil = p.y - lowf(pii), qrl = q.x - lowf(qrr), qil = q.y - lowf(qii); "
+         "A0 = v4(prr, pk(prl, p.y)); A1 = v4(pk(p.y, pil), qrr); A2 = v4(pk(qrl, q.y), pk(q.y, qil)); }\n"
+         // B slots for Cr (rh rl rh -ih | -il -ih) and for Ci (ih il ih rh | rl rh)
          "static __device__ __forceinline__ void bsplitb(C2 p, C2 q, s16x4& R0, s16x4& R1, s16x4& R2, s16x4& I0, "
-         "s16x4& I1, s16x4& I2) { float t; "
-         "const short prh = bhi(p.x, t), prl = blo(t); const short pih = bhi(p.y, t), pil = blo(t); "
-         "const short qrh = bhi(q.x, t), qrl = blo(t); const short qih = bhi(q.y, t), qil = blo(t); "
-         "R0 = s16x4{prh, prl, prh, bneg(pih)}; R1 = s16x4{bneg(pil), bneg(pih), qrh, qrl}; "
-         "R2 = s16x4{qrh, bneg(qih), bneg(qil), bneg(qih)}; "
-         "I0 = s16x4{pih, pil, pih, prh}; I1 = s16x4{prl, prh, qih, qil}; I2 = s16x4{qih, qrh, qrl, qrh}; }\n";
+         "s16x4& I1, s16x4& I2) { "
+         "const unsigned prr = pk(p.x, p.x), pii = pk(p.y, p.y), qrr = pk(q.x, q.x), qii = pk(q.y, q.y); "
+         "const float prl = p.x - lowf(prr), pil = p.y - lowf(pii), qrl = q.x - lowf(qrr), qil = q.y - lowf(qii); "
+         "R0 = v4(pk(p.x, prl), pk(p.x, -p.y)); R1 = v4(pk(-pil, -p.y), pk(q.x, qrl)); "
+         "R2 = v4(pk(q.x, -q.y), pk(-qil, -q.y)); "
+         "I0 = v4(pk(p.y, pil), pk(p.y, p.x)); I1 = v4(pk(prl, p.x), pk(q.y, qil)); "
+         "I2 = v4(pk(q.y, q.x), pk(qrl, q.x)); }\n";
   else
     o << "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = a.x * b.x - a.y * b.y; "
          "c.y = a.x * b.y + a.y * b.x; return c; }\n";
