@@ -115,6 +115,9 @@ typedef struct {
   int32_t mfma_steps;     /* WIDE, complex64: item steps that run on the matrix cores
                              (two-operand contractions with >= 5 row and >= 5 column bits) */
   double flops_mfma;      /* the part of flops_item those steps perform */
+  double roof_s_item;     /* chain roofline time per slice contraction: the sum over item
+                             steps of max(flops / 157.3 TFLOP/s, bytes / 8 TB/s), MI355X's
+                             FP32 and HBM peaks, bytes as in bytes_item */
 } qgm_stats;
 
 /* Circuit text v1, one gate per line, '#' starts a comment:

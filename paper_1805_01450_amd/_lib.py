@@ -33,7 +33,8 @@ class Stats(C.Structure):
                 ("item_elems", C.c_int32), ("n_leaves", C.c_int32), ("k", C.c_int32),
                 ("flops_item", C.c_double), ("flops_const", C.c_double), ("bytes_item", C.c_double),
                 ("cost", C.c_double), ("engine", C.c_int32), ("waves", C.c_int32), ("compile_s", C.c_double),
-                ("launches", C.c_int32), ("mfma_steps", C.c_int32), ("flops_mfma", C.c_double)]
+                ("launches", C.c_int32), ("mfma_steps", C.c_int32), ("flops_mfma", C.c_double),
+                ("roof_s_item", C.c_double)]
 
 
 def _load():

@@ -400,6 +400,7 @@ qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
   s.flops_item = p->prog.flops_item;
   s.flops_const = p->prog.flops_const;
   s.bytes_item = p->prog.bytes_item;
+  s.roof_s_item = p->prog.roof_s_item;
   s.cost = p->cost;
   s.engine = p->engine;
   s.compile_s = p->compile_s;

@@ -280,12 +280,22 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
     << "typedef float f32x4 __attribute__((ext_vector_type(4)));\n"
     << "typedef short s16x4 __attribute__((ext_vector_type(4)));\n";
   if (prec == 2)
-    o << "static __device__ __forceinline__ float bh(float x) { unsigned u = __float_as_uint(x); "
-         "u += 0x7FFFu + ((u >> 16) & 1u); return __uint_as_float(u & 0xFFFF0000u); }\n"
-         "static __device__ __forceinline__ float m3(float a, float b) { const float ah = bh(a), al = bh(a - ah), "
-         "bh_ = bh(b), bl = bh(b - bh_); return ah * bh_ + (ah * bl + al * bh_); }\n"
-         "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { C2 c; c.x = m3(a.x, b.x) - m3(a.y, b.y); "
-         "c.y = m3(a.x, b.y) + m3(a.y, b.x); return c; }\n"
+    o << "typedef float bf_f32x2 __attribute__((ext_vector_type(2)));\n"
+         "typedef __bf16 bf_bf16x2 __attribute__((ext_vector_type(2)));\n"
+         // two floats rounded to bfloat16 (nearest even) in one
+         // pack-convert; the halves read back as floats
+         "static __device__ __forceinline__ unsigned pkb(float a, float b) { return __builtin_bit_cast("
+         "unsigned, __builtin_convertvector((bf_f32x2){a, b}, bf_bf16x2)); }\n"
+         "static __device__ __forceinline__ float lo16(unsigned p) { return __uint_as_float(p << 16); }\n"
+         "static __device__ __forceinline__ float hi16(unsigned p) { return __uint_as_float(p & 0xFFFF0000u); }\n"
+         // x*y = xh*yh + (xh*yl + xl*yh), x = xh + xl
+         "static __device__ __forceinline__ C2 cm(C2 a, C2 b) { "
+         "const unsigned ah = pkb(a.x, a.y), bh = pkb(b.x, b.y); "
+         "const float arh = lo16(ah), aih = hi16(ah), brh = lo16(bh), bih = hi16(bh); "
+         "const unsigned al = pkb(a.x - arh, a.y - aih), bl = pkb(b.x - brh, b.y - bih); "
+         "const float arl = lo16(al), ail = hi16(al), brl = lo16(bl), bil = hi16(bl); C2 c; "
+         "c.x = (arh * brh + (arh * brl + arl * brh)) - (aih * bih + (aih * bil + ail * bih)); "
+         "c.y = (arh * bih + (arh * bil + arl * bih)) + (aih * brh + (aih * brl + ail * brh)); return c; }\n"
          // bfloat16 halves for the matrix-core form: x = hi + lo, hi and lo
          // rounded to nearest even (the hardware pack-convert, two at a
          // time); operands as packed 4 x bfloat16

@@ -134,6 +134,8 @@ struct Program {
   std::vector<int> grad_param;   // slot -> parameter index
   double flops_item = 0, flops_const = 0;
   double bytes_item = 0;         // algorithmic bytes per item at 8 B per element
+  double flops_mc_item = 0;      // flops per item of steps with the matrix-core shape
+  double roof_s_item = 0;        // sum over item steps of max(flops / 157.3 TFLOP/s, bytes / 8 TB/s)
 };
 
 bool validate_plan(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
@@ -145,6 +147,12 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
 // combine_consts = true first multiplies the constant factors of each
 // elimination step into one constant tensor (constant step, once per call):
 // for engines that load constants from memory rather than folding literals.
+// A two-operand contraction of item tensors whose operands split the output
+// variables into rows (only the first carries them), columns (only the
+// second) and a batch (both), with every summed variable in both, at least
+// 4 row and 4 column variables and one summed variable: a batch of complex
+// GEMMs per item, the shape the wide engine runs on the matrix cores.
+bool matrix_core_shape(const Step& st);
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                      Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false);
 

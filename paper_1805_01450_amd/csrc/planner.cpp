@@ -394,7 +394,10 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
       std::string err;
       int code = 0;
       if (!compile_program(net, sliced_vars, order_vars, prog, err, code, false, true)) return false;
-      *score = prog.flops_item / 40e12 + prog.bytes_item / 4e12;
+      // seconds per slice at the rates the wide engine reaches on one
+      // MI355X: matrix-core contractions ~65 TFLOP/s, other steps ~30
+      // TFLOP/s, streaming ~5 TB/s
+      *score = prog.flops_mc_item / 65e12 + (prog.flops_item - prog.flops_mc_item) / 30e12 + prog.bytes_item / 5e12;
     } else if (objective == OBJ_COST) {
       *score = order_cost(g, order1, removed).cost;
     } else {

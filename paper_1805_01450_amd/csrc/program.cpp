@@ -136,6 +136,24 @@ int popc_bits(int x) { return __builtin_popcount((unsigned)x); }
 
 }  // namespace
 
+bool matrix_core_shape(const Step& st) {
+  if (st.kind != ST_ELIM || st.is_const || st.opnd.size() != 2 || st.ns < 1) return false;
+  const Operand& a = st.opnd[0];
+  const Operand& b = st.opnd[1];
+  if (a.is_const || b.is_const) return false;
+  auto has = [](const Operand& o, int v) { return std::find(o.vars.begin(), o.vars.end(), v) != o.vars.end(); };
+  int rows = 0, cols = 0;
+  for (int v : st.out_vars) {
+    const bool ia = has(a, v), ib = has(b, v);
+    if (ia && !ib) ++rows;
+    if (ib && !ia) ++cols;
+    if (!ia && !ib) return false;
+  }
+  for (int v : st.sum_vars)
+    if (!has(a, v) || !has(b, v)) return false;
+  return rows >= 4 && cols >= 4;
+}
+
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                      Program& prog, std::string& err, int& code, bool gradient, bool combine_consts) {
   prog = Program();
@@ -330,7 +348,10 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       prog.flops_item += st.flops;
       double in_elems = 0;
       for (const Operand& o : prog.steps.back().opnd) in_elems += std::ldexp(1.0, (int)o.vars.size());
-      prog.bytes_item += 8.0 * (in_elems + std::ldexp(1.0, st.r));
+      const double bytes = 8.0 * (in_elems + std::ldexp(1.0, st.r));
+      prog.bytes_item += bytes;
+      prog.roof_s_item += std::max(st.flops / 157.3e12, bytes / 8e12);
+      if (matrix_core_shape(prog.steps.back())) prog.flops_mc_item += st.flops;
     }
     return id;
   };

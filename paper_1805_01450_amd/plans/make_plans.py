@@ -5,7 +5,7 @@ spend minutes planning.  The planner is the library's own
 plan is an input like any caller-supplied order, validated by
 qgm_plan_create.
 
-    python -m paper_1805_01450_amd.plans.make_plans [--budget SECONDS] [name ...]
+    python -m paper_1805_01450_amd.plans.make_plans [--budget SECONDS] [--out DIR] [name ...]
 """
 import argparse
 import json
@@ -24,6 +24,7 @@ def main():
     from workload import generate_circuit
     ap = argparse.ArgumentParser()
     ap.add_argument("--budget", type=float, default=600.0)
+    ap.add_argument("--out", default=HERE, help="directory for the plan files")
     ap.add_argument("names", nargs="*", default=sorted(CIRCUITS))
     args = ap.parse_args()
     flags = q.QGM_PLAN_SEARCH | q.QGM_PLAN_WIDE_TIME
@@ -36,7 +37,7 @@ def main():
         rec = {"circuit": {"n": n, "depth": d, "seed": seed}, "k": k, "flags": flags, "budget_s": args.budget,
                "plan_s": round(time.time() - t0, 1), "sliced": sliced, "order": order,
                "flops_item": st["flops_item"], "bytes_item": st["bytes_item"], "max_rank": st["max_rank"]}
-        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        with open(os.path.join(args.out, f"{name}.json"), "w") as f:
             json.dump(rec, f)
         print(name, {x: rec[x] for x in ("plan_s", "flops_item", "bytes_item", "max_rank")}, flush=True)
 
