@@ -148,12 +148,17 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
     << " + (long long)(sub & 1) * " << (1ll << bj[0]) << "ll + (long long)(sub >> 1) * " << (1ll << bj[1]) << "ll;\n"
     << "  const int it = (int)itb + wq * 16 + (lid >> 2);\n";
   // Copies: instruction j = 4 q + wave of a unit; j < per nA: A rows, else
-  // B rows.  A copy moves 1 KiB = 1024 / (128 WQ) rows of 16 WQ items: lane
-  // l takes row l / (8 WQ) of it and 16-byte chunk l % (8 WQ) (items 2c,
-  // 2c + 1).  Per copy: the lane's element offset without the k part, and
-  // the LDS byte offset inside a stage.
+  // B rows.  A copy moves 1 KiB = 1024 / (128 WQ) rows of 16 WQ items into
+  // LDS slots of 16 bytes (two items of one row), 8 WQ slots per row: lane
+  // l fills slot l % (8 WQ) of row l / (8 WQ) of the copy.  Slot t of row r
+  // holds the item pair t ^ 2 (r % 4): the operand reads of 16 lanes (4
+  // rows x 4 items) then fall on 16 different 8-byte bank pairs (without
+  // the swizzle the 4 rows, 8 WQ slots apart, share banks).  Per copy: the
+  // lane's element offset without the k part, its item pair and the LDS
+  // byte offset inside a stage.
   const int rows_per = 8 / WQ;
-  o << "  const int lrow = lid / " << 8 * WQ << ", lch = lid % " << 8 * WQ << ";\n";
+  o << "  const int lrow = lid / " << 8 * WQ << ", lch = lid % " << 8 * WQ << ";\n"
+    << "  const int xo = ((((16 * wq + (lid >> 2)) >> 1) ^ (2 * sub)) * 16) + ((lid >> 2) & 1) * 8;\n";
   for (int q = 0; q < per_wave; ++q) {
     o << "  const int j" << q << " = " << 4 * q << " + w4;\n";
     // which operand and which k of the unit: the A copies come first
@@ -162,6 +167,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
       << "  const int h" << q << " = isa" << q << " ? jr" << q << " / " << nA << " : jr" << q << " / " << nB << ";\n"
       << "  const int c" << q << " = isa" << q << " ? jr" << q << " % " << nA << " : jr" << q << " % " << nB << ";\n"
       << "  const int rw" << q << " = c" << q << " * " << rows_per << " + lrow;\n"
+      << "  const int pq" << q << " = lch ^ (2 * (rw" << q << " & 3));\n"
       << "  const long long eo" << q << " = isa" << q << " ? ba" << idx_off(A, bi, "rw" + std::to_string(q), li)
       << " : bbk" << idx_off(B, bj, "rw" + std::to_string(q), lj) << ";\n"
       << "  const unsigned lds" << q << " = (unsigned)(h" << q << " * " << (a_bytes + b_bytes) << " + (isa" << q
@@ -174,7 +180,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
       o << "    {\n"
         << "    const long long e = eo" << Q << " + (isa" << Q << " ? 0ll" << koff(A, kv) << " : 0ll" << koff(B, kv)
         << ");\n"
-        << "    __builtin_amdgcn_global_load_lds((const void*)(gm + e * 64ll + itb + 2 * lch), "
+        << "    __builtin_amdgcn_global_load_lds((const void*)(gm + e * 64ll + itb + 2 * pq" << Q << "), "
         << "(__attribute__((address_space(3))) void*)(lds + (" << stg << ") * " << stage << " + lds" << Q
         << "), 16, 0, 0);\n"
         << "    }\n";
@@ -200,14 +206,14 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   o << "    }\n"
     << "    const char* sb = lds + (u % " << P << ") * " << stage << ";\n";
   // operand reads: A row 16 wi + 4 rg + sub, B column 16 wj + 4 cg + sub,
-  // item 16 wq + lid / 4
+  // item 16 wq + lid / 4, in slot (item / 2) ^ 2 sub of its row
   for (int h = 0; h < per; ++h) {
     for (int g = 0; g < 4; ++g)
-      o << "    const C2 a" << h << "_" << g << " = *(const C2*)(sb + " << h * (a_bytes + b_bytes) << " + ((16 * wi + "
-        << 4 * g << " + sub) * " << 16 * WQ << " + 16 * wq + (lid >> 2)) * 8);\n";
+      o << "    const C2 a" << h << "_" << g << " = *(const C2*)(sb + " << h * (a_bytes + b_bytes) << " + (16 * wi + "
+        << 4 * g << " + sub) * " << 128 * WQ << " + xo);\n";
     for (int g = 0; g < 4; ++g)
       o << "    const C2 b" << h << "_" << g << " = *(const C2*)(sb + " << h * (a_bytes + b_bytes) + a_bytes
-        << " + ((16 * wj + " << 4 * g << " + sub) * " << 16 * WQ << " + 16 * wq + (lid >> 2)) * 8);\n";
+        << " + (16 * wj + " << 4 * g << " + sub) * " << 128 * WQ << " + xo);\n";
   }
   if (prec == 1) {
     for (int h = 0; h < per; ++h) {
