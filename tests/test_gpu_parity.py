@@ -599,3 +599,29 @@ def test_matrix_core_steps_8x8x40():
         note("slices", s0, s1, "mfma", got, "bf16x3", gb, "c128", ref)
         assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
         assert abs(gb - ref) / max(abs(ref), scale) <= BF16X3_TOL
+
+
+def test_level_timing_entry_point(cuda):
+    """qgm_plan_level_timing on a profiling wide plan: one entry per level
+    launch, positive HIP-event durations that add up to about the chain's,
+    per-level flops summing to the plan's flops per slice, the matrix-core
+    step counts, and the items of the timed pass."""
+    text, sl, order = _stored("7x7x30")
+    c = q.Circuit(text)
+    p = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, profile=True)
+    st = p.stats()
+    bits = random_bitstrings(49, 2, 55)
+    for _ in range(3):
+        p.amplitudes(bits)
+    cuda.cuda.synchronize()
+    ms, fl, mf, runs, items = q.qgm_plan_level_timing(p.h, reset=False)
+    (ms_pro, ms_chain, ms_red), n = q.qgm_plan_timing(p.h, reset=True)
+    note("levels", len(ms), "runs", runs, "items", items, "sum ms", sum(ms), "chain ms", ms_chain)
+    assert len(ms) == st["launches"] and runs == 3 and items == 2 * 64
+    assert all(t > 0 for t in ms)
+    assert abs(sum(fl) - st["flops_item"]) <= 1e-9 * st["flops_item"]
+    assert sum(mf) == st["mfma_steps"]
+    assert 0.5 * ms_chain <= sum(ms) <= 1.05 * ms_chain
+    # reset forgot the runs
+    ms2, _, _, runs2, _ = q.qgm_plan_level_timing(p.h, reset=True)
+    assert runs2 == 0 and all(t == 0 for t in ms2)

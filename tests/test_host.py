@@ -221,3 +221,34 @@ def test_stored_plans_are_valid(monkeypatch):
         assert sorted(rec["order"]) == sorted(set(free) - set(rec["sliced"]))
         st = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
         assert st["max_rank"] == rec["max_rank"]
+
+
+def test_matrix_core_step_selection():
+    """The wide engine puts the two-operand contractions of a 7x7x30 plan on
+    the matrix cores for complex64 and BF16x3 (the same steps), never for
+    complex128 or with vector_only; vector_only takes 0 or 1."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans",
+                        "7x7x30.json")
+    rec = json.load(open(path))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    sl, order = rec["sliced"], rec["order"]
+    s64 = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
+    sbf = q.Plan(c, sl, order, prec=q.QGM_BF16X3, engine=q.QGM_ENGINE_WIDE).stats()
+    svo = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, vector_only=True).stats()
+    s128 = q.Plan(c, sl, order, prec=q.QGM_C128, engine=q.QGM_ENGINE_WIDE).stats()
+    assert s64["mfma_steps"] >= 1 and 0 < s64["flops_mfma"] < s64["flops_item"]
+    assert sbf["mfma_steps"] == s64["mfma_steps"] and sbf["flops_mfma"] == s64["flops_mfma"]
+    assert svo["mfma_steps"] == 0 and s128["mfma_steps"] == 0
+    # the chain roofline time is at least the flops time and the bytes time
+    assert s64["roof_s_item"] >= max(s64["flops_item"] / 157.3e12, s64["bytes_item"] / 8e12) * (1 - 1e-12)
+    with pytest.raises(q.QgmError):
+        opts = q.PlanOpts()
+        opts.prec = q.QGM_C64
+        opts.engine = q.QGM_ENGINE_WIDE
+        opts.vector_only = 2
+        h = q.C.c_void_p()
+        q.check(q.lib.qgm_plan_create(c.h, q._i32(sl), len(sl), q._i32(order), len(order), q.C.byref(opts),
+                                      q.C.byref(h)))
