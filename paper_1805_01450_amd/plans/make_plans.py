@@ -15,7 +15,8 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # name: (grid n, depth, circuit seed, sliced variables k)
-CIRCUITS = {"7x7x30": (7, 30, 0, 6), "8x8x40": (8, 40, 0, 13)}
+CIRCUITS = {"7x7x30": (7, 30, 0, 6), "8x8x40": (8, 40, 0, 13), "8x8x40-k12": (8, 40, 0, 12),
+            "8x8x40-k14": (8, 40, 0, 14)}
 
 
 def main():
@@ -25,7 +26,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--budget", type=float, default=600.0)
     ap.add_argument("--out", default=HERE, help="directory for the plan files")
-    ap.add_argument("names", nargs="*", default=sorted(CIRCUITS))
+    ap.add_argument("names", nargs="*", default=["7x7x30", "8x8x40"])
     args = ap.parse_args()
     flags = q.QGM_PLAN_SEARCH | q.QGM_PLAN_WIDE_TIME
     for name in args.names:
