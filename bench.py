@@ -59,6 +59,7 @@ WORKLOADS = {
     "7x7x30": (7, 30, 0, 1, 6, None),
     "8x8x40": (8, 40, 0, 1, 13, 64),
     "8x8x40-full": (8, 40, 0, 1, 13, None),  # the whole amplitude: all 2^13 slices per step
+    "8x8x40-k12-full": (8, 40, 0, 1, 12, None),  # the same with a k = 12 plan
 }
 PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # Planner objective per workload (qgm_plan_slices_ex flags): 4096 items are
@@ -66,9 +67,9 @@ PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # one item on four wavefronts; the wide-engine workloads search several plans
 # (seeds, with and without re-ordering) scored by their compiled wide program
 # (QGM_PLAN_SEARCH | QGM_PLAN_WIDE_TIME); 6x6x25 keeps the sum of 2^deg(v).
-PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24}
+PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24, "8x8x40-k12-full": 24}
 # planner time budget per workload (seconds; the search flag plans up to 8 times)
-PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 150.0, "8x8x40-full": 150.0}
+PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 150.0, "8x8x40-full": 150.0, "8x8x40-k12-full": 150.0}
 
 
 def stored_plan(name, n, depth, seed, k):
@@ -169,7 +170,8 @@ def main():
     plan_flags = PLAN_FLAGS.get(args.workload, 0) if args.plan_flags < 0 else args.plan_flags
     budget = PLAN_BUDGET.get(args.workload, 1.0)
     t_plan = time.perf_counter()
-    stored = stored_plan(args.workload.split("-")[0], n, depth, seed, k) if args.plan_flags < 0 else None
+    plan_name = args.workload[:-len("-full")] if args.workload.endswith("-full") else args.workload
+    stored = stored_plan(plan_name, n, depth, seed, k) if args.plan_flags < 0 else None
     if stored is not None:
         sliced, order, plan_source = stored
     else:
