@@ -625,3 +625,28 @@ def test_level_timing_entry_point(cuda):
     # reset forgot the runs
     ms2, _, _, runs2, _ = q.qgm_plan_level_timing(p.h, reset=True)
     assert runs2 == 0 and all(t == 0 for t in ms2)
+
+
+def test_matrix_core_steps_8x8x40_k10():
+    """8x8x40 with the stored k = 10 plan (rank-24 intermediates, several
+    64-item groups per pass): single slices and a range of complex64 on the
+    matrix cores against the complex128 path."""
+    text, sl, order = _stored("8x8x40-k10")
+    c = q.Circuit(text)
+    pm = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE)
+    pd = q.Plan(c, sl, order, prec=q.QGM_C128, engine=q.QGM_ENGINE_WIDE)
+    sm = pm.stats()
+    note("8x8x40 k=10 plan: max rank", sm["max_rank"], "mfma steps", sm["mfma_steps"],
+         "flops share", sm["flops_mfma"] / sm["flops_item"])
+    assert sm["k"] == 10 and sm["mfma_steps"] >= 1
+    x = random_bitstrings(64, 1, 1000)[0]
+    scale = 2.0 ** -32 / 2.0 ** 5
+
+    def val(p, s0, s1):
+        part = p.amplitudes_range([x], None, s0, s1)[0]
+        return part[0] + part[2] + 1j * (part[1] + part[3])
+
+    for s0, s1 in ((0, 1), (777, 778), (0, 200)):
+        got, ref = val(pm, s0, s1), val(pd, s0, s1)
+        note("slices", s0, s1, "c64", got, "c128", ref)
+        assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
