@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # name: (grid n, depth, circuit seed, sliced variables k)
 CIRCUITS = {"7x7x30": (7, 30, 0, 6), "8x8x40": (8, 40, 0, 13), "8x8x40-k12": (8, 40, 0, 12),
             "8x8x40-k14": (8, 40, 0, 14), "8x8x40-k11": (8, 40, 0, 11), "8x8x40-k10": (8, 40, 0, 10),
-            "8x8x40-k9": (8, 40, 0, 9)}
+            "8x8x40-k9": (8, 40, 0, 9), "8x8x40-k8": (8, 40, 0, 8)}
 
 
 def main():
