@@ -47,10 +47,12 @@ std::string lit(double v) {
 // A wavefront owns a 16 x 16 tile (4 x 4 MFMA blocks) of 16 items; the four
 // wavefronts of a block cover 2 x 2 tiles of the same items when there are
 // at least 5 i and 5 j bits, else more items.  The operand rows a block
-// needs for one k (a "unit": two k for BF16x3) are copied from HBM straight
-// into LDS (16 bytes per lane, no registers) through a ring of P stages, so
-// P - 1 units of loads are in flight behind the matrix-core work; each unit
-// costs one block barrier.  Blocks are numbered so that each XCD (block
+// needs for two k (a "unit") are copied from HBM straight into LDS (16
+// bytes per lane, no registers) through a ring of P stages (at most 52 KiB,
+// so three blocks share a CU); P - 1 units of loads are in flight behind the
+// matrix-core work, and each unit costs one block barrier.  Operand slots
+// are swizzled so the LDS reads are free of bank conflicts (see the copy
+// mapping below).  Blocks are numbered so that each XCD (block
 // index mod 8) runs a contiguous range of tiles, j fastest within bands of
 // 4 j blocks, so the operand panels a band shares stay in that XCD's L2.
 // Returns false when the step does not qualify; lds_bytes receives the LDS
