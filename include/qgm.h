@@ -171,9 +171,25 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *     give different plans on different hosts;
  *   QGM_PLAN_WIDE_TIME: with SEARCH, score each plan by its program as the
  *     WIDE engine compiles it (constant factors combined, small eliminations
- *     absorbed, operand pairs pre-contracted): flops / 40 TFLOP/s + bytes /
- *     4 TB/s per slice, the rates its kernels reach on MI355X. */
-enum { QGM_PLAN_REORDER = 1, QGM_PLAN_BYTES = 2, QGM_PLAN_LATENCY = 4, QGM_PLAN_SEARCH = 8, QGM_PLAN_WIDE_TIME = 16 };
+ *     absorbed, operand pairs pre-contracted): seconds per slice with the
+ *     flops of matrix-core-shaped contractions at 65 TFLOP/s, the other
+ *     flops at 30 TFLOP/s and the bytes at 5 TB/s, the rates its kernels
+ *     reach on MI355X;
+ *   QGM_PLAN_CHOOSE_K: with SEARCH | WIDE_TIME and k_req >= 0, k_req is the
+ *     largest k tried: each k from k_req down to k_req - 6 gets an equal
+ *     share of the budget, and the plan with the least predicted time for
+ *     the whole amplitude (2^k x the per-slice score) wins among those
+ *     whose peak item memory fits a 64-item group in 96 GiB (complex128).
+ *     *k_out gives the chosen k.  Fails with QGM_E_WORKSPACE when no k
+ *     fits. */
+enum {
+  QGM_PLAN_REORDER = 1,
+  QGM_PLAN_BYTES = 2,
+  QGM_PLAN_LATENCY = 4,
+  QGM_PLAN_SEARCH = 8,
+  QGM_PLAN_WIDE_TIME = 16,
+  QGM_PLAN_CHOOSE_K = 32
+};
 qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                               uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                               int32_t* n_order_out);

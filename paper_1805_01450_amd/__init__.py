@@ -64,6 +64,7 @@ QGM_PLAN_BYTES = 2
 QGM_PLAN_LATENCY = 4
 QGM_PLAN_SEARCH = 8
 QGM_PLAN_WIDE_TIME = 16
+QGM_PLAN_CHOOSE_K = 32
 
 
 def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0,

@@ -219,7 +219,9 @@ qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t targe
   if (k_req > 40) return fail(QGM_E_ARG, "k_req > 40");
   if (!(time_budget_s >= 0)) return fail(QGM_E_ARG, "negative time budget");
   std::vector<int> sl, ord;
-  plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord, flags);
+  if (!plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord, flags))
+    return fail((flags & QGM_PLAN_CHOOSE_K) ? QGM_E_WORKSPACE : QGM_E_SLICE,
+                "no plan found (QGM_PLAN_CHOOSE_K: no k fits a 64-item group in 96 GiB)");
   for (size_t i = 0; i < sl.size(); ++i) sliced_out[i] = sl[i];
   *k_out = (int32_t)sl.size();
   for (size_t i = 0; i < ord.size(); ++i) order_out[i] = ord[i];

@@ -329,7 +329,8 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
 // then lower vertex id).  Candidates are the `n_cand` highest-degree
 // vertices of the graph with the previous picks removed.
 static bool plan_once(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
-                      std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* score) {
+                      std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* score,
+                      double* item_elems = nullptr) {
   const bool reorder_each = (flags & 1) != 0;
   std::vector<int> vov;
   Graph g = model_graph(net, vov);
@@ -398,6 +399,7 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
       // MI355X: matrix-core contractions ~65 TFLOP/s, other steps ~30
       // TFLOP/s, streaming ~5 TB/s
       *score = prog.flops_mc_item / 65e12 + (prog.flops_item - prog.flops_mc_item) / 30e12 + prog.bytes_item / 5e12;
+      if (item_elems) *item_elems = prog.item_elems;
     } else if (objective == OBJ_COST) {
       *score = order_cost(g, order1, removed).cost;
     } else {
@@ -414,27 +416,63 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
 // with the best final score is kept.  Seeds vary widely in quality (the
 // estimated time per slice of 8x8x40 plans spans 10x), so more attempts
 // pay on large circuits.
-bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
-                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags) {
-  if (!(flags & 8)) return plan_once(net, k_req, target_rank, time_budget_s, seed, sliced_vars, order_vars, flags,
-                                     nullptr);
+// The SEARCH loop for one k: the best-scoring plan of the attempts that fit
+// in the budget, its score and (WIDE_TIME) its item memory.
+static bool search(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                   std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* best_score,
+                   double* best_elems) {
   constexpr int kAttempts = 64;
   const auto t0 = std::chrono::steady_clock::now();
   const double per = time_budget_s / 8;
+  bool found = false;
   double best = 0;
   for (int a = 0; a < kAttempts; ++a) {
     if (a > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >= time_budget_s) break;
     const int f = (flags & ~1) | (((flags & 1) ^ (a & 1)) ? 1 : 0);
     std::vector<int> sv, ov;
-    double score = 0;
-    if (!plan_once(net, k_req, target_rank, per, seed + 0x51ed27ull * (a / 2), sv, ov, f, &score)) continue;
-    if (a == 0 || score < best) {
+    double score = 0, elems = 0;
+    if (!plan_once(net, k_req, target_rank, per, seed + 0x51ed27ull * (a / 2), sv, ov, f, &score, &elems)) continue;
+    if (!found || score < best) {
+      found = true;
       best = score;
+      sliced_vars = sv;
+      order_vars = ov;
+      if (best_elems) *best_elems = elems;
+    }
+  }
+  if (best_score) *best_score = best;
+  return found;
+}
+
+bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
+                 std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags) {
+  if (!(flags & 8)) return plan_once(net, k_req, target_rank, time_budget_s, seed, sliced_vars, order_vars, flags,
+                                     nullptr);
+  if (!(flags & 32) || !(flags & 16) || k_req < 0)
+    return search(net, k_req, target_rank, time_budget_s, seed, sliced_vars, order_vars, flags, nullptr, nullptr);
+  // QGM_PLAN_CHOOSE_K: k_req is the largest k tried.  Each k from k_req down
+  // to k_req - 6 gets an equal share of the budget; the plan with the least
+  // predicted time for the whole amplitude, 2^k times the per-slice score,
+  // wins among those whose item memory fits one 64-item group in 96 GiB.
+  constexpr double kMaxGroupBytes = 96.0 * (1ull << 30);
+  const int k_lo = std::max(0, k_req - 6);
+  const double per_k = time_budget_s / (k_req - k_lo + 1);
+  bool found = false;
+  double best = 0;
+  for (int k = k_req; k >= k_lo; --k) {
+    std::vector<int> sv, ov;
+    double score = 0, elems = 0;
+    if (!search(net, k, 0, per_k, seed, sv, ov, flags & ~32, &score, &elems)) continue;
+    if (elems * 64.0 * 16.0 > kMaxGroupBytes) continue;  // complex128 bytes of one group
+    const double total = std::ldexp(score, k);
+    if (!found || total < best) {
+      found = true;
+      best = total;
       sliced_vars = sv;
       order_vars = ov;
     }
   }
-  return true;
+  return found;
 }
 
 }  // namespace qgm

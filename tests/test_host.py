@@ -252,3 +252,15 @@ def test_matrix_core_step_selection():
         h = q.C.c_void_p()
         q.check(q.lib.qgm_plan_create(c.h, q._i32(sl), len(sl), q._i32(order), len(order), q.C.byref(opts),
                                       q.C.byref(h)))
+
+
+def test_planner_choose_k():
+    """QGM_PLAN_CHOOSE_K tries k_req down to k_req - 6 and returns a valid
+    plan for one of them (the least predicted whole-amplitude time)."""
+    c = q.Circuit(generate_circuit(6, 25, 0))
+    free = [v for v, _, _, out in c.vars() if not out]
+    flags = q.QGM_PLAN_SEARCH | q.QGM_PLAN_WIDE_TIME | q.QGM_PLAN_CHOOSE_K
+    sl, order = c.plan_slices(k_req=8, time_budget_s=3.5, seed=0, flags=flags)
+    assert 2 <= len(sl) <= 8 and len(set(sl)) == len(sl)
+    assert sorted(order) == sorted(set(free) - set(sl))
+    q.qgm_order_cost(c.h, sl, order)  # validated by the library
