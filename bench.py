@@ -63,6 +63,7 @@ WORKLOADS = {
     "8x8x40-k11-full": (8, 40, 0, 1, 11, None),
     "8x8x40-k10-full": (8, 40, 0, 1, 10, None),
     "8x8x40-k9-full": (8, 40, 0, 1, 9, None),
+    "8x8x40-k8-full": (8, 40, 0, 1, 8, None),
 }
 PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # Planner objective per workload (qgm_plan_slices_ex flags): 4096 items are
@@ -70,10 +71,10 @@ PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 # one item on four wavefronts; the wide-engine workloads search several plans
 # (seeds, with and without re-ordering) scored by their compiled wide program
 # (QGM_PLAN_SEARCH | QGM_PLAN_WIDE_TIME); 6x6x25 keeps the sum of 2^deg(v).
-PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24, "8x8x40-k12-full": 24, "8x8x40-k11-full": 24, "8x8x40-k10-full": 24, "8x8x40-k9-full": 24}
+PLAN_FLAGS = {"5x5x20": 4, "7x7x30": 24, "8x8x40": 24, "8x8x40-full": 24, "8x8x40-k12-full": 24, "8x8x40-k11-full": 24, "8x8x40-k10-full": 24, "8x8x40-k9-full": 24, "8x8x40-k8-full": 24}
 # planner time budget per workload (seconds; the search flag plans up to 8 times)
 PLAN_BUDGET = {"7x7x30": 30.0, "8x8x40": 150.0, "8x8x40-full": 150.0, "8x8x40-k12-full": 150.0, "8x8x40-k11-full": 150.0,
-               "8x8x40-k10-full": 150.0, "8x8x40-k9-full": 150.0}
+               "8x8x40-k10-full": 150.0, "8x8x40-k9-full": 150.0, "8x8x40-k8-full": 150.0}
 
 
 def stored_plan(name, n, depth, seed, k):
