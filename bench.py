@@ -233,7 +233,7 @@ def main():
     # interpreter engines run one kernel per call (the item chain).
     gbs = bytes_launch / (r["ms_chain"] * 1e-3) / 1e9
     if wide and r["levels"] and r["levels"][0]:
-        ms_l, fl_l, mf_l, _, items_l = r["levels"]  # the first pass of items is timed
+        ms_l, fl_l, mf_l, _, items_l, by_l = r["levels"]  # the first pass of items is timed
         i = max(range(len(ms_l)), key=lambda j: ms_l[j])
         k_flops = fl_l[i] * items_l
         k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
@@ -244,6 +244,19 @@ def main():
                     "chain_ms": r["ms_chain"], "chain_tflops": achieved, "chain_hbm_gbs": gbs,
                     "chain_bytes_per_launch": bytes_launch,
                     "chain_hbm_frac": gbs / PEAK_HBM_GBS}
+        # per level kernel (the eight longest): which ceiling it is closest
+        # to, matrix-core / vector FP32 flops or HBM bytes (algorithmic: each
+        # step's operands and output once)
+        per_level = []
+        for j in sorted(range(len(ms_l)), key=lambda x: -ms_l[x])[:8]:
+            tf = fl_l[j] * items_l / (ms_l[j] * 1e-3) / 1e12
+            gb = by_l[j] * items_l / (ms_l[j] * 1e-3) / 1e9
+            pk = PEAK_FP32_MATRIX_TFLOPS if mf_l[j] else PEAK_FP32_VECTOR_TFLOPS
+            fr_f, fr_b = tf / pk, gb / PEAK_HBM_GBS
+            per_level.append({"kernel": f"wl{j}", "ms": ms_l[j], "tflops": tf, "hbm_gbs": gb,
+                              "bound": ("mfma" if mf_l[j] else "alu") if fr_f >= fr_b else "hbm",
+                              "frac": max(fr_f, fr_b)})
+        roofline["levels"] = per_level
         # the kernels on the matrix cores together
         mk = [j for j in range(len(ms_l)) if mf_l[j]]
         if mk:
@@ -303,7 +316,7 @@ def main():
         if rb["levels"] and rb["levels"][0]:
             # BF16x3 performs three bfloat16 products per real product: its
             # matrix-core kernels execute 3x the useful flops in bf16
-            ms_l, fl_l, mf_l, _, items_l = rb["levels"]
+            ms_l, fl_l, mf_l, _, items_l, _ = rb["levels"]
             mk = [j for j in range(len(ms_l)) if mf_l[j]]
             if mk:
                 tf = sum(fl_l[j] for j in mk) * items_l / (sum(ms_l[j] for j in mk) * 1e-3) / 1e12

@@ -274,16 +274,18 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
  * launch of mutually independent elimination steps, in launch order) the
  * duration averaged over the runs since the last reset, measured with HIP
  * events recorded on the run's stream around each launch of the first pass
- * of items, plus the kernel's useful flops per slice contraction (the
- * flops_item convention of qgm_stats) and its number of matrix-core steps.
+ * of items, plus the kernel's useful flops and algorithmic bytes per slice
+ * contraction (the flops_item / bytes_item conventions of qgm_stats) and its
+ * number of matrix-core steps.
  * Fills min(cap, *n_levels) entries of the caller's arrays; *n_levels gets
  * the level count, *n_runs the runs averaged, *items the slice contractions
  * that first pass held (the last run's; a run larger than the workspace
  * takes several passes).  Waits for the last recorded run.  reset = 1
  * forgets the runs afterwards.  Other engines: *n_levels = 0.  Errors:
  * QGM_E_ARG (null or negative arguments, plan not profiling), QGM_E_HIP. */
-qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, int32_t* mfma_steps,
-                                 int32_t cap, int32_t* n_levels, int32_t* n_runs, uint64_t* items);
+qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, double* bytes_item,
+                                 int32_t* mfma_steps, int32_t cap, int32_t* n_levels, int32_t* n_runs,
+                                 uint64_t* items);
 /* Amplitudes and their derivatives with respect to every RZ angle, for a
  * plan created with opts.gradient = 1.  Reverse mode over the elimination
  * steps: the adjoint of alpha_{x,s} is 1; a step out = sum_S prod_i op_i

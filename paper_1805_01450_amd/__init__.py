@@ -204,15 +204,18 @@ def qgm_plan_timing(p, reset: bool = True):
 
 def qgm_plan_level_timing(p, reset: bool = True):
     """Per level kernel of a WIDE plan: (ms, flops_item, mfma_steps) lists, the
-    number of runs averaged and the items of the timed (first) pass."""
+    number of runs averaged, the items of the timed (first) pass, and the
+    bytes_item list."""
     nl, nr, it = C.c_int32(), C.c_int32(), C.c_uint64()
-    check(lib.qgm_plan_level_timing(p, 0, None, None, None, 0, C.byref(nl), C.byref(nr), C.byref(it)))
+    check(lib.qgm_plan_level_timing(p, 0, None, None, None, None, 0, C.byref(nl), C.byref(nr), C.byref(it)))
     n = nl.value
     ms = (C.c_double * max(1, n))()
     fl = (C.c_double * max(1, n))()
+    by = (C.c_double * max(1, n))()
     mf = (C.c_int32 * max(1, n))()
-    check(lib.qgm_plan_level_timing(p, 1 if reset else 0, ms, fl, mf, n, C.byref(nl), C.byref(nr), C.byref(it)))
-    return list(ms[:n]), list(fl[:n]), list(mf[:n]), nr.value, it.value
+    check(lib.qgm_plan_level_timing(p, 1 if reset else 0, ms, fl, by, mf, n, C.byref(nl), C.byref(nr),
+                                    C.byref(it)))
+    return list(ms[:n]), list(fl[:n]), list(mf[:n]), nr.value, it.value, list(by[:n])
 
 
 def qgm_plan_autotune(p, n_bs: int, n_slices: int, workspace, stream=None) -> int:

@@ -67,7 +67,7 @@ def _load():
         "qgm_amplitudes_range": (i32, [P, pu8, i32, pd, u64, u64, P, sz, P, pd]),
         "qgm_amplitudes_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P]),
         "qgm_plan_timing": (i32, [P, i32, pd, pi32]),
-        "qgm_plan_level_timing": (i32, [P, i32, pd, pd, pi32, i32, pi32, pi32, C.POINTER(u64)]),
+        "qgm_plan_level_timing": (i32, [P, i32, pd, pd, pd, pi32, i32, pi32, pi32, C.POINTER(u64)]),
         "qgm_plan_autotune": (i32, [P, i32, u64, P, sz, P, pi32]),
         "qgm_gradients_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P, P]),
         "qgm_amplitude_grad": (i32, [P, pu8, pd, P, sz, P, pd, pd]),

@@ -639,10 +639,12 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
   GUARD_END
 }
 
-qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, int32_t* mfma_steps,
-                                 int32_t cap, int32_t* n_levels, int32_t* n_runs, uint64_t* items) {
+qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, double* bytes_item,
+                                 int32_t* mfma_steps, int32_t cap, int32_t* n_levels, int32_t* n_runs,
+                                 uint64_t* items) {
   GUARD_BEGIN
-  if (!p || !n_levels || !n_runs || !items || cap < 0 || (cap > 0 && (!ms || !flops_item || !mfma_steps)))
+  if (!p || !n_levels || !n_runs || !items || cap < 0 ||
+      (cap > 0 && (!ms || !flops_item || !bytes_item || !mfma_steps)))
     return fail(QGM_E_ARG, "bad argument");
   if (!p->opts.profile) return fail(QGM_E_ARG, "plan was not created with opts.profile = 1");
   std::lock_guard<std::mutex> lk(p->mu);
@@ -663,6 +665,7 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
     }
     ms[i] = p->level_runs.empty() ? 0.0 : acc / p->level_runs.size();
     flops_item[i] = lv[i]->flops;
+    bytes_item[i] = lv[i]->bytes;
     mfma_steps[i] = lv[i]->mfma_steps;
   }
   if (reset) {

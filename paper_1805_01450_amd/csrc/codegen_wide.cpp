@@ -411,7 +411,18 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
       std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
-      if (kind == ST_ELIM || kind == ST_FINAL) k.flops += (double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0);
+      if (kind == ST_ELIM || kind == ST_FINAL) {
+        k.flops += (double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0);
+        // every operand and the output once, 8 B per element
+        double elems = (double)(1ull << r);
+        for (int i = 0; i < m; ++i) {
+          int nv = 0;
+          for (int j = 0; j < r; ++j) nv += rec[i][16 + j] != 0;
+          for (int j = 0; j < ns; ++j) nv += rec[i][48 + j] != 0;
+          elems += (double)(1ull << nv);
+        }
+        k.bytes += 8.0 * elems;
+      }
       int lds_bytes = 0;
       if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes)) {
         level_lds[lev] = std::max(level_lds[lev], lds_bytes);

@@ -186,6 +186,7 @@ struct WideKernel {
   int mfma_steps = 0;       // steps of this kernel on the matrix cores
   double mfma_flops = 0.0;  // their flops per item
   double flops = 0.0;       // flops per item of all its steps
+  double bytes = 0.0;       // algorithmic bytes per item of all its steps (8 B per element)
 };
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
                                  std::vector<WideKernel>& kernels, bool mfma);

@@ -614,16 +614,17 @@ def test_level_timing_entry_point(cuda):
     for _ in range(3):
         p.amplitudes(bits)
     cuda.cuda.synchronize()
-    ms, fl, mf, runs, items = q.qgm_plan_level_timing(p.h, reset=False)
+    ms, fl, mf, runs, items, by = q.qgm_plan_level_timing(p.h, reset=False)
     (ms_pro, ms_chain, ms_red), n = q.qgm_plan_timing(p.h, reset=True)
     note("levels", len(ms), "runs", runs, "items", items, "sum ms", sum(ms), "chain ms", ms_chain)
     assert len(ms) == st["launches"] and runs == 3 and items == 2 * 64
     assert all(t > 0 for t in ms)
     assert abs(sum(fl) - st["flops_item"]) <= 1e-9 * st["flops_item"]
+    assert abs(sum(by) - st["bytes_item"]) <= 1e-9 * st["bytes_item"]
     assert sum(mf) == st["mfma_steps"]
     assert 0.5 * ms_chain <= sum(ms) <= 1.05 * ms_chain
     # reset forgot the runs
-    ms2, _, _, runs2, _ = q.qgm_plan_level_timing(p.h, reset=True)
+    ms2, _, _, runs2, _, _ = q.qgm_plan_level_timing(p.h, reset=True)
     assert runs2 == 0 and all(t == 0 for t in ms2)
 
 
