@@ -178,7 +178,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   auto issue = [&](const std::string& unit, const std::string& stg) {
     for (int q = 0; q < per_wave; ++q) {
       const std::string Q = std::to_string(q);
-      const std::string kv = per == 1 ? "(" + unit + ")" : "(2 * (" + unit + ") + h" + Q + ")";
+      const std::string kv = per == 1 ? "(" + unit + ")" : "(" + std::to_string(per) + " * (" + unit + ") + h" + Q + ")";
       o << "    {\n"
         << "    const long long e = eo" << Q << " + (isa" << Q << " ? 0ll" << koff(A, kv) << " : 0ll" << koff(B, kv)
         << ");\n"
