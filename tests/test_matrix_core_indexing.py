@@ -1,0 +1,155 @@
+"""Host-side model of the generated matrix-core steps (no GPU).
+
+The wide engine emits each matrix-core step as straight-line HIP whose index
+arithmetic is fixed at plan time.  This test evaluates that arithmetic for
+every block and thread of every matrix-core step of a 7x7x30 plan (complex64
+and BF16x3) and replays the LDS ring in program order:
+  - every HBM copy stays inside the group's item memory and every LDS copy
+    target and operand read inside the kernel's LDS array;
+  - every operand read finds a slot written by a copy of the same unit,
+    holding the item the lane owns (lane l: item 16 wq + l / 4);
+  - over the K loop each operand lane reads each summed row exactly once;
+  - the result stores cover distinct elements.
+The barrier protocol itself (which copies a wave may issue after which wait)
+is exercised on the device by the parity tests."""
+import glob
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1805_01450_amd as q
+from workload import generate_circuit
+
+
+def _py_expr(e):
+    """A C integer expression of the generated code as a numpy expression."""
+    for cast in ("(long long)", "(int)", "(unsigned long long)", "(unsigned)"):
+        e = e.replace(cast, "")
+    e = re.sub(r"(\d+)ull", r"\1", e)
+    e = re.sub(r"(\d+)ll", r"\1", e)
+    e = re.sub(r"(\d+)u\b", r"\1", e)
+    e = e.replace("/", "//")
+    while True:  # "(name ? a : b)" with nested parentheses
+        m = re.search(r"\((\w+) \? ", e)
+        if not m:
+            break
+        i, depth, j, colon = m.start(), 0, m.start(), None
+        while True:
+            if e[j] == "(":
+                depth += 1
+            elif e[j] == ")":
+                depth -= 1
+                if depth == 0:
+                    break
+            elif e.startswith(" : ", j) and depth == 1 and colon is None:
+                colon = j
+            j += 1
+        e = e[:i] + f"np.where({m.group(1)}, {e[m.end():colon]}, {e[colon + 3:j]})" + e[j + 1:]
+    if " ? " in e:
+        c, rest = e.split(" ? ", 1)
+        a, b = rest.rsplit(" : ", 1)
+        e = f"np.where({c}, {a}, {b})"
+    return e.replace("threadIdx.x", "threadIdx_x")
+
+
+COPY = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(gm \+ e \* 64ll \+ itb \+ 2 \* pq(\d+)\), "
+                  r"\(__attribute__\(\(address_space\(3\)\)\) void\*\)\(lds \+ \((.*?)\) \* (\d+) \+ lds(\d+)\), 16, 0, 0\);")
+E_LINE = re.compile(r"const (?:long long|unsigned) e = (.*);$")
+
+
+def check_step(body, S, E, lds_size, group_c2):
+    lines = [l.strip() for l in body.split("\n")]
+    blk = np.repeat(np.arange(S, E, dtype=np.int64), 256)
+    th = np.tile(np.arange(256, dtype=np.int64), E - S)
+    env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
+
+    def ev(e):
+        return np.asarray(eval(_py_expr(e), env))
+
+    i_loop = next(i for i, l in enumerate(lines) if l.startswith("for (int u = 0;"))
+    for l in lines[:i_loop]:  # per-thread set-up values
+        m = re.match(r"const (?:unsigned long long|long long|unsigned|int|bool) (.*);$", l)
+        if m and not E_LINE.match(l):
+            for part in re.split(r", (?=[a-z]\w* = )", m.group(1)):
+                name, e = part.split(" = ", 1)
+                env[name.strip()] = ev(e)
+    nu = int(re.search(r"for \(int u = 0; u < (\d+); \+\+u\)", body).group(1))
+    m = re.search(r"const char\* sb = lds \+ \(u % (\d+)\) \* (\d+);", body)
+    P, stage = int(m.group(1)), int(m.group(2))
+    ring = {}
+
+    def copy(line, e_expr, st, unit):
+        m = COPY.match(line)
+        g = ev(e_expr) * 64 + env["itb"] + 2 * env["pq" + m.group(1)]
+        lo = st * int(m.group(3)) + env["lds" + m.group(4)] + 16 * env["lid"]
+        assert lo.min() >= 0 and lo.max() + 16 <= lds_size
+        assert g.min() >= 0 and g.max() + 1 < group_c2
+        ring.setdefault(st, []).append((unit, g, lo))
+
+    e_expr = None
+    for l in lines[:i_loop]:  # prologue copies: literal unit and stage
+        if E_LINE.match(l):
+            e_expr = E_LINE.match(l).group(1)
+        m = COPY.match(l)
+        if m:
+            mu = re.search(r"\(\(\((\d+)\)\) >> 0\)|\(\(\(\d \* \((\d+)\) \+ h\d+\)\) >> 0\)", e_expr)
+            env["u"] = 0
+            copy(l, e_expr, int(m.group(2)), int(mu.group(1) or mu.group(2)))
+    loop = lines[i_loop:]
+    copies = [l for l in loop if E_LINE.match(l) or l.startswith("__builtin_amdgcn_global_load_lds")]
+    reads = [l for l in loop if re.match(r"const C2 [ab]\d_\d = ", l)]
+    rows = {}
+    for u in range(nu):
+        env["u"] = u
+        env["un"] = min(u + P - 1, nu - 1)
+        st = u % P
+        slot = {}
+        for (un, g, lo) in ring.get(st, []):
+            if un == u:
+                for c in range(2):
+                    slot.update(zip(zip(blk.tolist(), (lo + 8 * c).tolist()), (g + c).tolist()))
+        want_item = env["itb"] + 16 * env["wq"] + (env["lid"] >> 2)
+        for l in reads:
+            m = re.match(r"const C2 ([ab])\d_(\d) = \*\(const C2\*\)\(sb \+ (.*)\);$", l)
+            off = ev(m.group(3)) + st * stage
+            assert off.min() >= 0 and off.max() + 8 <= lds_size
+            got = np.array([slot.get(k, -1) for k in zip(blk.tolist(), off.tolist())])
+            assert (got >= 0).all(), "operand read of a slot this unit did not fill"
+            assert ((got % 64) == want_item).all(), "operand read of another item"
+            rows.setdefault((m.group(1), m.group(2)), []).append(got // 64)
+        st2 = (u + P - 1) % P
+        ring[st2] = []
+        for l in copies:
+            if E_LINE.match(l):
+                e_expr = E_LINE.match(l).group(1)
+            else:
+                copy(l, e_expr, st2, env["un"])
+    for r in rows.values():
+        r = np.stack(r, 0)
+        assert all(len(np.unique(r[:, c])) == r.shape[0] for c in range(0, r.shape[1], 61)), \
+            "a summed row read twice or not at all"
+    stores = np.concatenate([ev(re.match(r"gm\[\((lo \+ \d+ll)\) \* 64ll \+ it\]", l).group(1)) * 64 + env["it"]
+                             for l in lines if l.startswith("gm[(lo + ")])
+    assert len(np.unique(stores)) == len(stores) and stores.min() >= 0 and stores.max() < group_c2
+    return nu
+
+
+@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
+def test_matrix_core_step_indexing_7x7x30(prec, tmp_path, monkeypatch):
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
+    rec = json.load(open(os.path.join(here, "7x7x30.json")))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    st = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE).stats()
+    src = open(glob.glob(str(tmp_path / "qgm_wide_*.hip"))[0]).read()
+    steps = list(re.finditer(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores\)\n"
+                             r"(.*?)\n  return;\n  \}", src, re.S))
+    assert len(steps) == st["mfma_steps"] >= 1
+    for m in steps:
+        lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
+        nu = check_step(m.group(4), int(m.group(1)), int(m.group(2)), lds_size, st["item_elems"] * 64)
+        assert nu >= 1
