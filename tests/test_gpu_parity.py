@@ -651,3 +651,20 @@ def test_matrix_core_steps_8x8x40_k10():
         got, ref = val(pm, s0, s1), val(pd, s0, s1)
         note("slices", s0, s1, "c64", got, "c128", ref)
         assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
+
+
+def test_gradient_c64_with_matrix_core_steps(config4):
+    """Reverse-mode plans run their large two-operand steps on the matrix
+    cores too: complex64 amplitude and d alpha / d theta for every angle of
+    the 7x7x30 RZ circuit against the complex128 plan (pinned above)."""
+    text, th, x, c, sl, order = config4
+    g64 = q.Plan(c, sl, order, prec=q.QGM_C64, gradient=True)
+    st = g64.stats()
+    note("7x7x30 c64 gradient plan: engine", st["engine"], "mfma steps", st["mfma_steps"])
+    assert st["engine"] == q.QGM_ENGINE_WIDE and st["mfma_steps"] >= 1
+    a64, d64 = g64.amplitude_grad(x, th)
+    a128, d128 = q.Plan(c, sl, order, gradient=True).amplitude_grad(x, th)
+    scale = max(abs(a128), 2.0 ** -24.5)
+    note("amp err", abs(a64 - a128) / scale, "max grad err", np.max(np.abs(d64 - d128)) / scale)
+    assert abs(a64 - a128) / scale <= C64_TOL
+    assert np.max(np.abs(d64 - d128)) / scale <= C64_TOL
