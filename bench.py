@@ -135,6 +135,8 @@ def main():
                     help="planner flags (QGM_PLAN_*); default: per workload")
     ap.add_argument("--vector-only", action="store_true",
                     help="wide engine: keep every step on the vector ALUs (no matrix cores)")
+    ap.add_argument("--workspace-gib", type=float, default=0.0,
+                    help="wide engine: item memory per pass in GiB (0 = the library default, 96 GiB)")
     ap.add_argument("--seeds", default=None,
                     help="comma-separated extra circuit seeds timed beside seed 0 (c64 only); default 1-4 for "
                          "5x5x20 and 6x6x25, none for the larger workloads")
@@ -198,7 +200,8 @@ def main():
     results = {}
     for name, prec, engine in runs:
         try:
-            plan = q.Plan(circ, sliced, order, prec=prec, profile=True, engine=engine, vector_only=args.vector_only)
+            plan = q.Plan(circ, sliced, order, prec=prec, profile=True, engine=engine, vector_only=args.vector_only,
+                          workspace_cap=int(args.workspace_gib * (1 << 30)))
         except q.QgmError:
             if name == "c64":
                 raise

@@ -285,14 +285,6 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     delete p;
     return fail(QGM_E_UNSUPPORTED, "plan has a step of rank + summed variables > 16: only the WIDE engine runs it");
   }
-  if (o.workspace_cap) {
-    const size_t el = o.prec == QGM_C128 ? 16 : 8;
-    size_t need = (size_t)p->prog.item_elems * 64 * el + (size_t)p->prog.n_const * el;
-    if (need > o.workspace_cap) {
-      delete p;
-      return fail(QGM_E_WORKSPACE, "plan needs " + std::to_string(need) + " bytes per wavefront, over the cap");
-    }
-  }
   std::vector<int> vov;
   Graph g = model_graph(p->net, vov);
   std::vector<char> removed(g.n, 0);
@@ -313,6 +305,16 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     // combined per step first (a different grouping of the same products)
     Program combined;
     if (compile_program(p->net, sv, ov, combined, err, code, false, true)) p->prog = std::move(combined);
+  }
+  // the cap applies to the program that runs (after the wide engine's
+  // regrouping, which changes its item memory)
+  if (o.workspace_cap) {
+    const size_t el = o.prec == QGM_C128 ? 16 : 8;
+    size_t need = (size_t)p->prog.item_elems * 64 * el + (size_t)p->prog.n_const * el;
+    if (need > o.workspace_cap) {
+      delete p;
+      return fail(QGM_E_WORKSPACE, "plan needs " + std::to_string(need) + " bytes per wavefront, over the cap");
+    }
   }
   if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
     // debugging aid: the compiled step list, one step per line
