@@ -208,6 +208,8 @@ def main():
             continue  # comparison engine cannot run this plan (e.g. interpreter on large ranks)
         waves = plan.autotune(n_bs, n_s) if plan.stats()["engine"] == q.QGM_ENGINE_GENERATED else 1
         r = timed(q, torch, plan, d_bits, d_part, n_s, args.steps, args.warmup, stream)
+        plan.release_workspace()  # the next precision's plan may need the memory
+        torch.cuda.empty_cache()
         r["plan"] = plan
         r["waves"] = waves
         results[name] = r

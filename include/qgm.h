@@ -67,8 +67,10 @@ typedef struct {
 typedef struct {
   int32_t prec;          /* qgm_precision */
   int32_t profile;       /* 1 = record HIP events around each kernel of every run (qgm_plan_timing) */
-  size_t workspace_cap;  /* 0 = no cap (WIDE: 96 GiB of item tensors per pass); else plan_create
-                            fails with QGM_E_WORKSPACE when one work item's memory cannot fit */
+  size_t workspace_cap;  /* bytes; 0 = no cap (WIDE: 96 GiB of item tensors per pass); else the
+                            WIDE engine's item memory per pass, and plan_create fails with
+                            QGM_E_WORKSPACE when the memory of one 64-item group (one
+                            wavefront) of the program that runs cannot fit */
   int32_t engine;        /* QGM_ENGINE_*: how the per-item chain runs on the device */
   int32_t gradient;      /* 1 = also compile the reverse-mode steps for d alpha / d theta */
   int32_t waves;         /* GENERATED: wavefronts per block to cut the item tree across

@@ -301,6 +301,10 @@ class Plan:
             self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
         return self._ws
 
+    def release_workspace(self):
+        """Drop the cached workspace (the next call allocates a new one)."""
+        self._ws = None
+
     def amplitudes(self, bitstrings, params=None, stream=None):
         bs = np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8))
         return qgm_amplitudes(self.h, bs, params, self.workspace(bs.shape[0]), stream)

@@ -266,3 +266,24 @@ def test_planner_choose_k():
     assert 2 <= len(sl) <= 8 and len(set(sl)) == len(sl)
     assert sorted(order) == sorted(set(free) - set(sl))
     q.qgm_order_cost(c.h, sl, order)  # validated by the library
+
+
+def test_workspace_cap_applies_to_the_wide_program(monkeypatch):
+    """The cap is checked against the program the wide engine runs: at
+    8x8x40, k = 8 one 64-slice group needs 33.6 GiB after the constant
+    regrouping (far more before it), so a 40 GiB cap is accepted and a
+    30 GiB cap is refused."""
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")  # structure only: no kernel build
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans",
+                        "8x8x40-k8.json")
+    rec = json.load(open(path))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    st = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE,
+                workspace_cap=40 << 30).stats()
+    assert st["item_elems"] * 64 * 8 < 40 << 30
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, workspace_cap=30 << 30)
+    assert e.value.status == -5
