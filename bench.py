@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published vector FP32 peak
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X published dense FP32 matrix-core peak
 PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X published dense BF16 matrix-core peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")  # rocprofv3 HBM byte counters, summarised
 
 
 
@@ -88,6 +89,40 @@ def stored_plan(name, n, depth, seed, k):
     if rec["circuit"] != {"n": n, "depth": depth, "seed": seed} or rec["k"] != k:
         return None
     return rec["sliced"], rec["order"], f"stored plan {name}.json (search budget {rec['budget_s']} s)"
+
+
+def source_digest() -> str:
+    """sha256 over the library sources that the kernels are built and
+    generated from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1805_01450_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        path = os.path.join(d, name)
+        if os.path.isfile(path):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str, waves: int):
+    """HBM bytes per launch of `kernel`, from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs of this workload, each scaled by what the counter reads
+    for a plain copy of known size.  The counters cannot be read from inside
+    the process, so they are stored with a digest of the sources they were
+    taken on; None once the sources have changed or when no run matches."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    for e in rec["entries"]:
+        if e["workload"] == workload and e["kernel"] == kernel and e["waves"] == waves:
+            return e["bytes_per_launch"]
+    return None
 
 
 def timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream):
@@ -277,7 +312,9 @@ def main():
         k_ms = min(r["ms_chain"], r["gpu_ms_step"])
         k_tf = flops_launch / (k_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": k_tf, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": k_tf / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                    "frac": k_tf / PEAK_FP32_VECTOR_TFLOPS,
+                    "traffic": measured_traffic(args.workload, "qgm_chain", r["waves"])
+                    if st["engine"] == q.QGM_ENGINE_GENERATED else None,
                     "kernel": {1: "chain_kernel<float>", 2: "qgm_chain (generated)",
                                3: "generated wide step kernels (all levels of a run)"}[st["engine"]],
                     "kernel_ms": k_ms, "kernel_ms_events": r["ms_chain"], "ms_per_run_graph": r["gpu_ms_step"],

@@ -287,3 +287,21 @@ def test_workspace_cap_applies_to_the_wide_program(monkeypatch):
     with pytest.raises(q.QgmError) as e:
         q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, workspace_cap=30 << 30)
     assert e.value.status == -5
+
+
+def test_bench_traffic_lookup(monkeypatch):
+    """bench.py reports stored HBM counter bytes only for the sources they
+    were taken on: a changed source digest gives None."""
+    import importlib.util
+    import os
+    import json
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    rec = json.load(open(b.TRAFFIC_FILE))
+    e = rec["entries"][0]
+    monkeypatch.setattr(b, "source_digest", lambda: rec["source_sha256"])
+    assert b.measured_traffic(e["workload"], e["kernel"], e["waves"]) == e["bytes_per_launch"]
+    assert b.measured_traffic(e["workload"], e["kernel"], 3) is None
+    monkeypatch.setattr(b, "source_digest", lambda: "0" * 64)
+    assert b.measured_traffic(e["workload"], e["kernel"], e["waves"]) is None
