@@ -92,15 +92,17 @@ def stored_plan(name, n, depth, seed, k):
 
 
 def source_digest() -> str:
-    """sha256 over the library sources that the kernels are built and
-    generated from."""
+    """sha256 over what the timed kernels are built and generated from: the
+    library sources, the stored plans and the circuit generator."""
     import hashlib
-    d = os.path.join(ROOT, "paper_1805_01450_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_1805_01450_amd")
+    paths = [os.path.join(ROOT, "workload.py")]
+    for d in (os.path.join(pkg, "csrc"), os.path.join(pkg, "plans")):
+        paths += [os.path.join(d, name) for name in sorted(os.listdir(d))]
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        path = os.path.join(d, name)
-        if os.path.isfile(path):
-            h.update(name.encode())
+    for path in paths:
+        if os.path.isfile(path) and not path.endswith(".pyc"):
+            h.update(os.path.relpath(path, ROOT).encode())
             with open(path, "rb") as f:
                 h.update(f.read())
     return h.hexdigest()
@@ -279,7 +281,8 @@ def main():
         k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
         peak = PEAK_FP32_MATRIX_TFLOPS if mf_l[i] else PEAK_FP32_VECTOR_TFLOPS
         roofline = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
-                    "frac": k_tf / peak, "traffic": None, "kernel": f"wl{i} (generated level kernel)",
+                    "frac": k_tf / peak, "traffic": measured_traffic(args.workload, f"wl{i}", 1),
+                    "kernel": f"wl{i} (generated level kernel)",
                     "kernel_ms": ms_l[i], "flops_per_launch": k_flops, "matrix_core_steps": mf_l[i],
                     "chain_ms": r["ms_chain"], "chain_tflops": achieved, "chain_hbm_gbs": gbs,
                     "chain_bytes_per_launch": bytes_launch,
