@@ -96,8 +96,8 @@ def source_digest() -> str:
     library sources, the stored plans and the circuit generator."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_1805_01450_amd")
-    paths = [os.path.join(ROOT, "workload.py")]
-    for d in (os.path.join(pkg, "csrc"), os.path.join(pkg, "plans")):
+    paths = []
+    for d in (os.path.join(pkg, "csrc"), os.path.join(pkg, "plans"), os.path.join(ROOT, "workload")):
         paths += [os.path.join(d, name) for name in sorted(os.listdir(d))]
     h = hashlib.sha256()
     for path in paths:
