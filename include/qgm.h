@@ -77,8 +77,8 @@ typedef struct {
                             (1, 2, 4 or 8; fewer when the exchange does not fit in LDS or
                             the program is not a tree); 0 = chosen by the cost model */
   int32_t vector_only;   /* WIDE: 1 = run every step on the vector ALUs; 0 = two-operand
-                            complex64 contractions with >= 5 row and >= 5 column bits run
-                            on the matrix cores */
+                            complex64 and BF16x3 contractions with >= 4 row bits, >= 4
+                            column bits and >= 1 summed bit run on the matrix cores */
   int32_t reserved[4];
 } qgm_plan_opts;
 
@@ -114,8 +114,9 @@ typedef struct {
   int32_t launches;       /* kernel launches of the item steps per pass: WIDE with
                              generated kernels, one per level of mutually independent
                              steps; otherwise the item steps' kernel count */
-  int32_t mfma_steps;     /* WIDE, complex64: item steps that run on the matrix cores
-                             (two-operand contractions with >= 5 row and >= 5 column bits) */
+  int32_t mfma_steps;     /* WIDE, complex64 and BF16x3: item steps that run on the matrix
+                             cores (two-operand contractions with >= 4 row, >= 4 column and
+                             >= 1 summed bits) */
   double flops_mfma;      /* the part of flops_item those steps perform */
   double roof_s_item;     /* chain roofline time per slice contraction: the sum over item
                              steps of max(flops / 157.3 TFLOP/s, bytes / 8 TB/s), MI355X's
@@ -134,6 +135,8 @@ typedef struct {
  * (Clock cycles C_1..C_d of Eq. (1); gates of Fig. 2 and Rule 3.)
  * Errors: QGM_E_ARG (null), QGM_E_PARSE (message names the line). */
 qgm_status qgm_circuit_parse(const char* text, size_t len, qgm_circuit** out);
+/* Sizes of a parsed circuit: qubits, variables of the graphical model
+ * (Section "Undirected Graphical Model"), RZ parameters.  Errors: QGM_E_ARG. */
 qgm_status qgm_circuit_info(const qgm_circuit* c, int32_t* n_qubits, int32_t* n_vars, int32_t* n_params);
 /* Variable table (Section "Undirected Graphical Model"): writes min(cap, n_vars)
  * entries of buf. */
@@ -142,6 +145,7 @@ qgm_status qgm_circuit_vars(const qgm_circuit* c, qgm_var_info* buf, int32_t cap
  * two variables are adjacent when a gate acts on both (Fig. 3).  Writes up to
  * cap pairs into edges[2*cap]; *n_edges gets the total count. */
 qgm_status qgm_circuit_graph(const qgm_circuit* c, int32_t* edges, int32_t cap, int32_t* n_edges);
+/* Releases a parsed circuit.  NULL is a no-op. */
 void qgm_circuit_free(qgm_circuit* c);
 
 /* Host planner (Section "The variable elimination ordering", Section
@@ -183,14 +187,19 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *     the whole amplitude (2^k x the per-slice score) wins among those
  *     whose peak item memory fits a 64-item group in 96 GiB (complex128).
  *     *k_out gives the chosen k.  Fails with QGM_E_WORKSPACE when no k
- *     fits. */
+ *     fits;
+ *   QGM_PLAN_DETERMINISTIC: the budget counts work instead of wall-clock
+ *     time (320 min-fill restarts per second of budget, at most 128 per ordering; SEARCH makes
+ *     exactly 8 attempts), so every host returns the same plan for the
+ *     same arguments. */
 enum {
   QGM_PLAN_REORDER = 1,
   QGM_PLAN_BYTES = 2,
   QGM_PLAN_LATENCY = 4,
   QGM_PLAN_SEARCH = 8,
   QGM_PLAN_WIDE_TIME = 16,
-  QGM_PLAN_CHOOSE_K = 32
+  QGM_PLAN_CHOOSE_K = 32,
+  QGM_PLAN_DETERMINISTIC = 64
 };
 qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                               uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
@@ -202,19 +211,30 @@ qgm_status qgm_order_cost(const qgm_circuit* c, const int32_t* sliced_vars, int3
                           int32_t n_order, double* cost, int32_t* width);
 
 /* Compile the per-slice contraction program for (circuit, sliced_vars,
- * order).  Host only; device tables are uploaded at the first run on the
+ * order): the variable elimination of Section "Variable elimination"
+ * (steps 1-4: for each variable in the order, multiply the tensors that hold
+ * it and sum it out) on the network with the outputs and the sliced
+ * variables fixed (Section "Parallelization by fixing the values of
+ * variables").  Host only; device tables are uploaded at the first run on the
  * then-current device.  opts may be NULL (complex128, no cap).
  * Errors: QGM_E_SLICE (ids not distinct free variables, or k > 40),
  * QGM_E_ORDER (order not a permutation of the free non-sliced variables),
  * QGM_E_WORKSPACE (over opts->workspace_cap), QGM_E_UNSUPPORTED (precision). */
 qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
                            int32_t n_order, const qgm_plan_opts* opts, qgm_plan** out);
+/* Statistics of a compiled plan (cost: the sum of 2^deg(v) of Section
+ * "Variable elimination"; flops and bytes: the algorithmic work of the
+ * compiled steps).  Errors: QGM_E_ARG (null). */
 qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out);
 /* Device workspace bytes needed by a run over n_bs bitstrings and n_slices
- * slices, including the staging room that the host-pointer entry points use. */
+ * slices, including the staging room that the host-pointer entry points use.
+ * (Workspace sizing is this library's; the paper's subtasks each hold one
+ * slice's tensors.)  Errors: QGM_E_ARG, QGM_E_HIP (first upload). */
 qgm_status qgm_workspace_size(const qgm_plan* p, int32_t n_bs, uint64_t n_slices, size_t* bytes);
 
-/* alpha_x for n_bs bitstrings, summed over all 2^k slices.  Host inputs
+/* alpha_x = <x|C|0...0> (Eq. (1)) for n_bs bitstrings, summed over all 2^k
+ * slices (Section "Parallelization by fixing the values of variables":
+ * the slices are independent and their results are added).  Host inputs
  * (bitstrings n_bs x n_qubits bytes; params n_params doubles, or NULL when
  * the circuit has no RZ), host output out[2*n_bs] = (re, im).  The slice sum
  * is FP64 with Neumaier compensation in ascending s.  Synchronises `stream`
@@ -223,7 +243,9 @@ qgm_status qgm_workspace_size(const qgm_plan* p, int32_t n_bs, uint64_t n_slices
  * QGM_E_WORKSPACE (ws_bytes < qgm_workspace_size), QGM_E_HIP. */
 qgm_status qgm_amplitudes(qgm_plan* p, const uint8_t* bitstrings, int32_t n_bs, const double* params,
                           void* d_workspace, size_t ws_bytes, void* hip_stream, double* out);
-/* Slices [s_begin, s_end) only.  partial[4*n_bs] = (sum re, sum im, comp re,
+/* Slices [s_begin, s_end) only: the paper's subtasks, any contiguous subset
+ * of which can run on its own (Section "Parallelization by fixing the values
+ * of variables").  partial[4*n_bs] = (sum re, sum im, comp re,
  * comp im) per bitstring: the Neumaier sum and its compensation, so ranges run
  * separately (e.g. after a failure) combine to the full result.
  * Errors: as qgm_amplitudes, plus QGM_E_ARG when the range is not inside
@@ -239,7 +261,10 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bitstrings, int32_t 
 qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
                                  uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
                                  void* hip_stream, double* d_partial);
-/* HIP graph of `repeat` back-to-back runs of qgm_amplitudes_device with
+/* Batching (the paper's independent subtasks run together, Section
+ * "Parallelization by fixing the values of variables"; the graph itself is
+ * this library's launch mechanism):
+ * HIP graph of `repeat` back-to-back runs of qgm_amplitudes_device with
  * these arguments (every array a device pointer, read at each replay).  The
  * runs are captured from a private stream; each replay executes them again
  * on the launch stream, so repeated amplitude batches cost one host call.
@@ -253,7 +278,8 @@ qgm_status qgm_graph_create(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_
 qgm_status qgm_graph_launch(qgm_graph* g, void* hip_stream);
 void qgm_graph_free(qgm_graph* g);
 
-/* Autotuner of the GENERATED engine: the item tree of a plan can be cut
+/* Not in the paper (a launch-shape choice of this library).
+ * Autotuner of the GENERATED engine: the item tree of a plan can be cut
  * across 1, 2, 4 or 8 wavefronts of a block (the cut is the launch shape of
  * the generated kernel).  Each feasible variant is generated, compiled,
  * timed on the device for a batch of n_bs bitstrings x n_slices slices (all
@@ -265,14 +291,16 @@ void qgm_graph_free(qgm_graph* g);
 qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void* d_workspace, size_t ws_bytes,
                              void* hip_stream, int32_t* waves_out);
 
-/* Kernel durations of the runs made since the last reset by a plan created
+/* Measurement (not in the paper, which times whole subtasks on CPU nodes).
+ * Kernel durations of the runs made since the last reset by a plan created
  * with opts.profile = 1: ms[0] prologue (tables, constant steps), ms[1]
  * per-item contraction chain, ms[2] slice reduction, each averaged over the
  * runs and measured with HIP events recorded on each run's own stream.
  * Waits for the last recorded run.  reset = 1 forgets the runs afterwards.
  * Errors: QGM_E_ARG (plan not profiling), QGM_E_HIP. */
 qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_runs);
-/* WIDE engine, plan created with opts.profile = 1: per level kernel (one
+/* Measurement (not in the paper).
+ * WIDE engine, plan created with opts.profile = 1: per level kernel (one
  * launch of mutually independent elimination steps, in launch order) the
  * duration averaged over the runs since the last reset, measured with HIP
  * events recorded on the run's stream around each launch of the first pass
@@ -288,7 +316,9 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
 qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, double* bytes_item,
                                  int32_t* mfma_steps, int32_t cap, int32_t* n_levels, int32_t* n_runs,
                                  uint64_t* items);
-/* Amplitudes and their derivatives with respect to every RZ angle, for a
+/* Not in the paper (which evaluates amplitudes only): reverse-mode
+ * differentiation of the elimination of Section "Variable elimination".
+ * Amplitudes and their derivatives with respect to every RZ angle, for a
  * plan created with opts.gradient = 1.  Reverse mode over the elimination
  * steps: the adjoint of alpha_{x,s} is 1; a step out = sum_S prod_i op_i
  * gives each operand the adjoint sum over the variables it lacks of
@@ -304,15 +334,50 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
 qgm_status qgm_gradients_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
                                 uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
                                 void* hip_stream, double* d_partial, double* d_grad_partial);
-/* Host form for one bitstring over all slices: amp_out[2] = alpha,
+/* Host form of qgm_gradients_device (same passages) for one bitstring over
+ * all slices: amp_out[2] = alpha,
  * dalpha_dtheta[2 * n_params] = (re, im) of d alpha / d theta_j.  Synchronises
  * `stream`.  Errors: as qgm_gradients_device, QGM_E_WORKSPACE. */
 qgm_status qgm_amplitude_grad(qgm_plan* p, const uint8_t* bitstring, const double* params, void* d_workspace,
                               size_t ws_bytes, void* hip_stream, double* amp_out, double* dalpha_dtheta);
+/* Releases the plan and its device tables (call with the plan's device
+ * current).  NULL is a no-op. */
 void qgm_plan_free(qgm_plan* p);
+/* Message of the last non-OK status on this thread. */
 const char* qgm_last_error(void);
 
-/* One-shot form plan(circuit, bitstring, sliced_vars, order) -> amplitude:
+/* One step of the elimination on its own: out[b, j, i] = sum_k A[b, k, i] *
+ * B[b, j, k] for every item, the pairwise form of "multiply the tensors that
+ * hold the summed variables, then sum them out" (Section "Variable
+ * elimination", steps 2-3) with ni row, nj column, nb batch and nk summed
+ * binary indices.  The kernel is generated by the same code as the chain's
+ * level kernels: on the matrix cores when the shape qualifies (complex64 or
+ * BF16x3, nk >= 1, ni >= 4, nj >= 4) unless flags bit 0 (vector ALUs only)
+ * is set, else on the vector ALUs.  For tests and tile tuning.
+ * Layout (caller-owned device memory, complex elements of the precision:
+ * 16 B for QGM_C128, 8 B (float re, im) otherwise): group g of 64 items
+ * starts at element g * E * 64 with E = 2^(nb+ni+nk) + 2^(nb+nk+nj) +
+ * 2^(nb+ni+nj); inside a group element e of item l is at e * 64 + l.  A is
+ * elements [0, 2^(nb+ni+nk)) with index i + 2^ni k + 2^(ni+nk) b, B follows
+ * with index k + 2^nk j + 2^(nk+nj) b, then C with index i + 2^ni j +
+ * 2^(ni+nj) b.  qgm_contraction_run queues n_groups groups (at most 65535)
+ * on `stream`, overwriting C only; no synchronisation.
+ * Errors: QGM_E_ARG (counts: nb + ni + nj <= 32, nk <= 16, E < 2^31),
+ * QGM_E_UNSUPPORTED (precision, compile failure), QGM_E_HIP. */
+typedef struct qgm_contraction qgm_contraction;
+qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t nj, int32_t nk, int32_t flags,
+                                  qgm_contraction** out);
+/* *matrix_cores = 1 when the step runs on the matrix cores; *elems_per_item
+ * = E; *flops_per_item = useful real flops per item (8 per complex
+ * multiply-add). */
+qgm_status qgm_contraction_info(const qgm_contraction* c, int32_t* matrix_cores, uint64_t* elems_per_item,
+                                double* flops_per_item);
+qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups, void* hip_stream);
+void qgm_contraction_free(qgm_contraction* c);
+
+/* One-shot form plan(circuit, bitstring, sliced_vars, order) -> amplitude,
+ * the paper's problem statement (compute one amplitude <x|C|0...0> of a
+ * circuit, Section "Our Contributions") with a given slicing and ordering:
  * parse, plan, run one bitstring in complex128 with a library-allocated
  * workspace on the default stream, free.  out[2] = (re, im). */
 qgm_status qgm_amplitude(const char* circuit_text, size_t len, const uint8_t* bitstring,

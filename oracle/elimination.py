@@ -131,3 +131,36 @@ def exact_sum(values) -> complex:
 def ve_amplitude(circuit, x, sliced=(), order=None, params=None, net=None) -> complex:
     """alpha_x = sum over all 2^k slices, combined exactly (fsum)."""
     return exact_sum(ve_slice_values(circuit, x, sliced, order, params, net=net))
+
+
+def greedy_extra_slices(vertices, edges, order, j, n_candidates=40):
+    """Fix j more vertices, one at a time, each the one whose removal gives
+    the least cost sum 2^deg(v) of eliminating the rest of ``order`` (the
+    paper's greedy key-vertex removal under a fixed ordering, Section "The
+    variable elimination ordering").  Candidates at each pick are the
+    ``n_candidates`` vertices of largest degree at their elimination; ties
+    go to the smaller vertex id.  Returns (picked, remaining order, cost,
+    width)."""
+    picked = []
+    rest = [int(v) for v in order]
+    live = set(int(v) for v in vertices)
+    edges = [(int(a), int(b)) for a, b in edges]
+    for _ in range(j):
+        g = Graph(sorted(live), [(a, b) for a, b in edges if a in live and b in live])
+        deg = {}
+        for v in rest:
+            deg[v] = g.eliminate(v)
+        cands = sorted(rest, key=lambda v: (-deg[v], v))[:n_candidates]
+        best = None
+        for c in cands:
+            live_c = live - {c}
+            cost, width = order_cost(sorted(live_c), [(a, b) for a, b in edges if a in live_c and b in live_c],
+                                     [v for v in rest if v != c])
+            if best is None or (cost, width, c) < best:
+                best = (cost, width, c)
+        picked.append(best[2])
+        live.discard(best[2])
+        rest = [v for v in rest if v != best[2]]
+    live_edges = [(a, b) for a, b in edges if a in live and b in live]
+    cost, width = order_cost(sorted(live), live_edges, rest)
+    return picked, rest, cost, width

@@ -45,6 +45,9 @@ class Network:
     factors: list = field(default_factory=list)  # list of (tuple vars, ndarray)
     output_var: list = field(default_factory=list)  # per qubit: var id or INPUT
     n_params: int = 0
+    # per RZ parameter index: the variable its diagonal factor sits on (the
+    # qubit's current variable when the gate acts), or INPUT
+    param_var: dict = field(default_factory=dict)
 
     @property
     def free_vars(self):
@@ -99,6 +102,8 @@ def build_network(circuit, params=None) -> Network:
             theta = None if g.param < 0 else float(params[g.param])
             d = np.diag(gate_matrix(g.name, theta)).copy()
             q = g.qubits[0]
+            if g.param >= 0:
+                net.param_var[g.param] = cur[q]
             vs, t = _restrict((cur[q],), d, fixed_input)
             net.factors.append((vs, t))
         else:  # H, SX, SY: new variable

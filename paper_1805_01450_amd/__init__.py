@@ -65,6 +65,7 @@ QGM_PLAN_LATENCY = 4
 QGM_PLAN_SEARCH = 8
 QGM_PLAN_WIDE_TIME = 16
 QGM_PLAN_CHOOSE_K = 32
+QGM_PLAN_DETERMINISTIC = 64
 
 
 def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: float = 1.0, seed: int = 0,
@@ -244,6 +245,47 @@ def qgm_amplitude(text: str, bitstring, sliced=(), order=None, params=None) -> c
                             _i32(order), len(order),
                             None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)), out))
     return complex(out[0], out[1])
+
+
+def qgm_contraction_create(prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False):
+    h = C.c_void_p()
+    check(lib.qgm_contraction_create(prec, nb, ni, nj, nk, 1 if vector_only else 0, C.byref(h)))
+    return h
+
+
+def qgm_contraction_info(h):
+    """(runs on the matrix cores, elements per item, useful flops per item)."""
+    mc, el, fl = C.c_int32(), C.c_uint64(), C.c_double()
+    check(lib.qgm_contraction_info(h, C.byref(mc), C.byref(el), C.byref(fl)))
+    return bool(mc.value), el.value, fl.value
+
+
+def qgm_contraction_run(h, d_mem, n_groups: int, stream=None) -> None:
+    check(lib.qgm_contraction_run(h, _ptr(d_mem), n_groups, _stream(stream)))
+
+
+def qgm_contraction_free(h) -> None:
+    lib.qgm_contraction_free(h)
+
+
+class Contraction:
+    """Owning wrapper of one two-operand contraction step (qgm_contraction_*)."""
+
+    def __init__(self, prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False):
+        self.prec, self.nb, self.ni, self.nj, self.nk = prec, nb, ni, nj, nk
+        self.h = qgm_contraction_create(prec, nb, ni, nj, nk, vector_only)
+        self.matrix_cores, self.elems, self.flops = qgm_contraction_info(self.h)
+
+    def run(self, d_mem, n_groups: int, stream=None) -> None:
+        qgm_contraction_run(self.h, d_mem, n_groups, stream)
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h and lib is not None:
+            try:
+                lib.qgm_contraction_free(h)
+            except Exception:  # interpreter shutdown
+                pass
 
 
 class Circuit:

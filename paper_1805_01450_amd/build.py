@@ -1,6 +1,6 @@
 """Build libqgm.so (host C++ + gfx950 HIP kernels) in the package directory.
 
-    python -m paper_1805_01450_amd.build        # or: python paper_1805_01450_amd/build.py
+    python paper_1805_01450_amd/build.py   (the package import would load the library being built)
 """
 from __future__ import annotations
 

@@ -862,3 +862,138 @@ qgm_status qgm_amplitude(const char* text, size_t len, const uint8_t* bitstring,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// One two-operand contraction step on caller-laid-out item tensors.
+struct qgm_contraction {
+  int prec = 1, nb = 0, ni = 0, nj = 0, nk = 0;
+  uint64_t ea = 0, eb = 0, ec = 0;  // elements per item of A, B, C
+  WideKernel kern;
+  std::vector<char> code;
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  int device = -1;
+  std::mutex mu;
+  ~qgm_contraction() {
+    if (mod) (void)hipModuleUnload(mod);
+  }
+};
+
+extern "C" {
+
+qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t nj, int32_t nk, int32_t flags,
+                                  qgm_contraction** out) {
+  GUARD_BEGIN
+  if (!out) return fail(QGM_E_ARG, "null argument");
+  *out = nullptr;
+  if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");
+  if (nb < 0 || ni < 0 || nj < 0 || nk < 0 || nb + ni + nj > kWideMaxOut || nk > kWideMaxSum)
+    return fail(QGM_E_ARG, "index counts out of range (b + i + j <= 32, k <= 16)");
+  if (flags & ~1) return fail(QGM_E_ARG, "unknown flags");
+  const uint64_t ea = 1ull << (nb + ni + nk), eb = 1ull << (nb + nk + nj), ec = 1ull << (nb + ni + nj);
+  if (ea + eb + ec >= (1ull << 31)) return fail(QGM_E_ARG, "operands exceed 2^31 elements per item");
+  if (ec >= (1ull << 40)) return fail(QGM_E_ARG, "output too large");
+  auto* c = new qgm_contraction();
+  c->prec = prec;
+  c->nb = nb;
+  c->ni = ni;
+  c->nj = nj;
+  c->nk = nk;
+  c->ea = ea;
+  c->eb = eb;
+  c->ec = ec;
+  // one elimination step: output bits i (0..ni-1), j, b; A = [b][k][i],
+  // B = [b][j][k], C = [b][j][i] (first index slowest), item-major rows
+  WideProgram w;
+  const int r = ni + nj + nb;
+  std::vector<int32_t> A(kWideOpInts, 0), B(kWideOpInts, 0);
+  A[0] = B[0] = WOP_ITEM;
+  A[1] = 0;
+  B[1] = (int32_t)ea;
+  for (int t = 0; t < ni; ++t) A[16 + t] = 1 << t;
+  for (int t = 0; t < nj; ++t) B[16 + ni + t] = 1 << (nk + t);
+  for (int t = 0; t < nb; ++t) {
+    A[16 + ni + nj + t] = 1 << (ni + nk + t);
+    B[16 + ni + nj + t] = 1 << (nk + nj + t);
+  }
+  for (int t = 0; t < nk; ++t) {
+    A[48 + t] = 1 << (ni + t);
+    B[48 + t] = 1 << t;
+  }
+  w.ops.insert(w.ops.end(), A.begin(), A.end());
+  w.ops.insert(w.ops.end(), B.begin(), B.end());
+  const int32_t srec[8] = {ST_ELIM, (int32_t)(ea + eb), r, nk, 2, -1, 0, 0};
+  w.steps.assign(srec, srec + 8);
+  w.n_steps = 1;
+  std::vector<WideKernel> kernels;
+  Program none;
+  const std::string src = generate_wide_source(none, w, prec, kernels, (flags & 1) == 0);
+  if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
+    // debugging aid: keep the generated source
+    if (FILE* f = std::fopen((std::string(dir) + "/qgm_contract_" + std::to_string((uintptr_t)c) + ".hip").c_str(), "w")) {
+      std::fwrite(src.data(), 1, src.size(), f);
+      std::fclose(f);
+    }
+  }
+  std::string jerr;
+  if (kernels.size() != 1 || !jit_compile(src, "qgm_contract.hip", c->code, jerr)) {
+    delete c;
+    return fail(QGM_E_UNSUPPORTED, "contraction kernel did not compile: " + jerr);
+  }
+  c->kern = kernels[0];
+  if (c->kern.blocks == 0 || c->kern.blocks > 0x7fffffffull) {
+    delete c;
+    return fail(QGM_E_ARG, "contraction grid out of range");
+  }
+  *out = c;
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_contraction_info(const qgm_contraction* c, int32_t* matrix_cores, uint64_t* elems_per_item,
+                                double* flops_per_item) {
+  if (!c) return fail(QGM_E_ARG, "null contraction");
+  if (matrix_cores) *matrix_cores = c->kern.mfma_steps;
+  if (elems_per_item) *elems_per_item = c->ea + c->eb + c->ec;
+  if (flops_per_item) *flops_per_item = c->kern.flops;
+  return QGM_OK;
+}
+
+qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups, void* stream) {
+  GUARD_BEGIN
+  if (!c || !d_mem || n_groups < 0) return fail(QGM_E_ARG, "bad argument");
+  if (n_groups > 65535) return fail(QGM_E_ARG, "at most 65535 groups of 64 items per call");
+  if (n_groups == 0) return QGM_OK;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(QGM_E_HIP, "hipGetDevice failed");
+  if (!c->mod) {
+    hipError_t e = hipModuleLoadData(&c->mod, c->code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&c->fn, c->mod, c->kern.name.c_str());
+    if (e != hipSuccess) return fail(QGM_E_HIP, std::string("loading the contraction kernel: ") + hipGetErrorString(e));
+    c->device = dev;
+  } else if (dev != c->device) {
+    return fail(QGM_E_ARG, "contraction was loaded on device " + std::to_string(c->device));
+  }
+  // The level kernel's item bookkeeping: one bitstring (b = item >> 40 = 0)
+  // whose packed bits are read from d_mem[0] and never used (no leaves);
+  // no constants, results or gradient rows are touched by an item step.
+  void* a_mem = d_mem;
+  const void* a_cst = d_mem;
+  const void* a_packed = d_mem;
+  unsigned long long a_ge = c->ea + c->eb + c->ec, a_sb = 0, a_ns = 1ull << 40, a_ni = (unsigned long long)n_groups * 64,
+                     a_nbs = 1;
+  int a_g0 = 0, a_log2 = 40;
+  void* a_res = d_mem;
+  void* a_gres = d_mem;
+  void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
+  hipError_t e = hipModuleLaunchKernel(c->fn, (unsigned)c->kern.blocks, (unsigned)n_groups, 1, 256, 1, 1, 0,
+                                       (hipStream_t)stream, args, nullptr);
+  if (e != hipSuccess) return fail(QGM_E_HIP, std::string("contraction launch: ") + hipGetErrorString(e));
+  return QGM_OK;
+  GUARD_END
+}
+
+void qgm_contraction_free(qgm_contraction* c) { delete c; }
+
+}  // extern "C"

@@ -93,7 +93,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   // block ranges start at multiples of 8 so that blk & 7 is the XCD
   k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
-    << "  // step " << si << " (matrix cores)\n"
+    << "  // step " << si << " (matrix cores) b " << nbb << " i " << bi.size() << " j " << bj.size() << " k " << ns << "\n"
     << "  const unsigned long long g = blk - " << k.blocks << "ull;\n";
   if (nb >= 8)
     o << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
@@ -201,7 +201,9 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   const int wait_imm = (N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14);
   o << "  for (int u = 0; u < " << nu << "; ++u) {\n"
     << "    __builtin_amdgcn_s_waitcnt(" << wait_imm << ");\n"
+    << "    __asm__ volatile(\"\" ::: \"memory\");  // LDS reads of unit u - 1 stay above the barrier\n"
     << "    __builtin_amdgcn_s_barrier();  // every wave's copies of unit u are in LDS\n"
+    << "    __asm__ volatile(\"\" ::: \"memory\");  // and this unit's reads below it\n"
     << "    {\n"
     << "    const int un = u + " << P - 1 << " < " << nu << " ? u + " << P - 1 << " : " << nu - 1 << ";\n";
   issue("un", "(u + " + std::to_string(P - 1) + ") % " + std::to_string(P));

@@ -287,9 +287,13 @@ static SimCost simulate(const Network& net, const std::vector<int>& vov, int n, 
 // flops), the time of one item on four wavefronts (for batches too small to
 // fill the GPU), ties broken by flops.
 enum { OBJ_COST = 0, OBJ_BYTES = 1, OBJ_LATENCY = 2 };
+// With `det` the budget is a work count instead of a deadline:
+// kRestartsPerSecond restarts per second of budget, whatever the host's
+// speed, so every host returns the same ordering.
+constexpr double kRestartsPerSecond = 320.0;
 static std::vector<int> best_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, double budget_s,
                                    OrderCost* out_cost, int objective = OBJ_COST, const Network* net = nullptr,
-                                   const std::vector<int>* vov = nullptr) {
+                                   const std::vector<int>* vov = nullptr, bool det = false) {
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> best = min_fill_order(g, removed, seed, 0);
   OrderCost bc = order_cost(g, best, removed);
@@ -303,9 +307,11 @@ static std::vector<int> best_order(const Graph& g, const std::vector<char>& remo
   // At most kMaxRestarts restarts, so small graphs give the same ordering on
   // every run; large graphs may stop earlier on the time budget.
   const int kMaxRestarts = 128;
-  for (int it = 1; it <= kMaxRestarts; ++it) {
+  const int n_restarts = det ? (int)std::min<double>(kMaxRestarts, std::floor(budget_s * kRestartsPerSecond + 0.5))
+                             : kMaxRestarts;
+  for (int it = 1; it <= n_restarts; ++it) {
     double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (el >= budget_s) break;
+    if (!det && el >= budget_s) break;
     std::vector<int> o = min_fill_order(g, removed, seed + 0x9e3779b97f4a7c15ull * it, 1);
     OrderCost c = order_cost(g, o, removed);
     if (objective != OBJ_COST) {
@@ -332,12 +338,13 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
                       std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* score,
                       double* item_elems = nullptr) {
   const bool reorder_each = (flags & 1) != 0;
+  const bool det = (flags & 64) != 0;
   std::vector<int> vov;
   Graph g = model_graph(net, vov);
   std::vector<char> removed(g.n, 0);
   double b0 = k_req == 0 ? time_budget_s : time_budget_s * 0.4;
   OrderCost c0;
-  std::vector<int> order0 = best_order(g, removed, seed, b0, &c0);
+  std::vector<int> order0 = best_order(g, removed, seed, b0, &c0, OBJ_COST, nullptr, nullptr, det);
   std::vector<int> picks;
   const int n_cand = 64;
   int kmax = k_req >= 0 ? k_req : 40;
@@ -373,7 +380,8 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
       // a fresh ordering of the reduced graph guides the next removal
       const double per_pick = time_budget_s * 0.4 / std::max(1, kmax);
       OrderCost c1;
-      std::vector<int> o1 = best_order(g, removed, seed + 31 * picks.size(), per_pick, &c1);
+      std::vector<int> o1 = best_order(g, removed, seed + 31 * picks.size(), per_pick, &c1, OBJ_COST, nullptr, nullptr,
+                                       det);
       if (c1.cost < cur.cost || (c1.cost == cur.cost && c1.width < cur.width)) {
         order0 = o1;
         cur = c1;
@@ -382,7 +390,7 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
   }
   double b1 = k_req == 0 ? 0.0 : time_budget_s * 0.6;
   const int objective = (flags & 4) ? OBJ_LATENCY : (flags & 2) ? OBJ_BYTES : OBJ_COST;
-  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr, objective, &net, &vov);
+  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr, objective, &net, &vov, det);
   sliced_vars.clear();
   for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
   order_vars.clear();
@@ -422,12 +430,15 @@ static bool search(const Network& net, int k_req, int target_rank, double time_b
                    std::vector<int>& sliced_vars, std::vector<int>& order_vars, int flags, double* best_score,
                    double* best_elems) {
   constexpr int kAttempts = 64;
+  const bool det = (flags & 64) != 0;  // deterministic: exactly 8 attempts of budget / 8 each
   const auto t0 = std::chrono::steady_clock::now();
   const double per = time_budget_s / 8;
   bool found = false;
   double best = 0;
-  for (int a = 0; a < kAttempts; ++a) {
-    if (a > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >= time_budget_s) break;
+  for (int a = 0; a < (det ? 8 : kAttempts); ++a) {
+    if (!det && a > 0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >= time_budget_s)
+      break;
     const int f = (flags & ~1) | (((flags & 1) ^ (a & 1)) ? 1 : 0);
     std::vector<int> sv, ov;
     double score = 0, elems = 0;

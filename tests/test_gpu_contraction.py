@@ -1,0 +1,119 @@
+"""One two-operand contraction step (qgm_contraction_*) against its FP64
+product, element by element, with a rigorous first-order bound for each
+precision.
+
+For an output element c = sum_{k<K} a_k b_k (complex), the computed value
+differs from the exact product of the stored operands by at most
+
+    eps_prec * sum_k |a_k| |b_k|
+
+because each real part sums 2K real products (|ar br| + |ai bi| <= |a||b|):
+* complex128: eps = (2K + 2) 2^-53 (one rounding per multiply-add);
+* complex64: eps = (2K + 2) 2^-24;
+* BF16x3: every real product x y becomes xh yh + xh yl + xl yh with
+  x = xh + xl + dx, xh = bf16(x), xl = bf16(x - xh) (round to nearest even,
+  8 significant bits): |x - xh| <= 2^-8 |x| and |dx| <= 2^-8 |x - xh| <=
+  2^-16 |x|, so the dropped xl yl and the two split residuals cost at most
+  3 * 2^-16 |x y| per product, plus the FP32 accumulation of complex64:
+  eps = 3 * 2^-16 + (2K + 2) 2^-24.
+A plain bfloat16 product (or a lost cross term xh yl) errs by about 2^-8 per
+product, far above the BF16x3 bound for these sizes, so either mistake
+fails here.
+"""
+import numpy as np
+import pytest
+
+import paper_1805_01450_amd as q
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*args):
+    print("[gpu-contract]", *args, flush=True)
+
+
+def _eps(prec, K):
+    if prec == q.QGM_C128:
+        return (2 * K + 2) * 2.0 ** -53
+    if prec == q.QGM_C64:
+        return (2 * K + 2) * 2.0 ** -24
+    return 3 * 2.0 ** -16 + (2 * K + 2) * 2.0 ** -24
+
+
+def _run(prec, nb, ni, nj, nk, n_groups, vector_only, seed):
+    import torch
+    c = q.Contraction(prec, nb, ni, nj, nk, vector_only=vector_only)
+    ea, eb = 1 << (nb + ni + nk), 1 << (nb + nk + nj)
+    ec = 1 << (nb + ni + nj)
+    assert c.elems == ea + eb + ec
+    items = 64 * n_groups
+    rng = np.random.default_rng(seed)
+    cdt = np.complex128 if prec == q.QGM_C128 else np.complex64
+    # A[item, b, k, i], B[item, b, j, k]: the element orders of the layout
+    A = (rng.standard_normal((items, 1 << nb, 1 << nk, 1 << ni))
+         + 1j * rng.standard_normal((items, 1 << nb, 1 << nk, 1 << ni))).astype(cdt)
+    B = (rng.standard_normal((items, 1 << nb, 1 << nj, 1 << nk))
+         + 1j * rng.standard_normal((items, 1 << nb, 1 << nj, 1 << nk))).astype(cdt)
+    mem = np.zeros((n_groups, c.elems, 64), dtype=cdt)
+    mem[:, :ea, :] = A.reshape(n_groups, 64, ea).transpose(0, 2, 1)
+    mem[:, ea:ea + eb, :] = B.reshape(n_groups, 64, eb).transpose(0, 2, 1)
+    tdt = torch.complex128 if prec == q.QGM_C128 else torch.complex64
+    d_mem = torch.from_numpy(mem).to("cuda")
+    assert d_mem.dtype == tdt and d_mem.is_contiguous()
+    note("prec", prec, "nb ni nj nk", (nb, ni, nj, nk), "groups", n_groups, "vector_only", vector_only,
+         "matrix cores", c.matrix_cores)
+    c.run(d_mem, n_groups)
+    torch.cuda.synchronize()
+    got = d_mem.cpu().numpy()[:, ea + eb:, :].transpose(0, 2, 1).reshape(items, 1 << nb, 1 << nj, 1 << ni)
+    # untouched operands
+    assert np.array_equal(d_mem.cpu().numpy()[:, :ea + eb, :], mem[:, :ea + eb, :])
+    A64, B64 = A.astype(np.complex128), B.astype(np.complex128)
+    want = np.matmul(B64, A64)  # [item, b, j, i] = sum_k B[.., j, k] A[.., k, i]
+    mag = np.matmul(np.abs(B64), np.abs(A64))
+    return c, got, want, mag
+
+
+SHAPES = [
+    (2, 5, 5, 3),  # 2 x 2 wavefront tiles of one 16-item group
+    (1, 4, 4, 1),  # 4 i and 4 j bits: four item groups per block
+    (2, 5, 4, 2),  # 5 i bits, 4 j bits: wavefronts split i and items
+    (2, 4, 5, 2),  # 4 i bits, 5 j bits: wavefronts split j and items
+    (1, 6, 7, 8),  # K = 256, several tiles per item
+    (0, 3, 3, 2),  # too narrow for the matrix cores: vector ALUs
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
+@pytest.mark.parametrize("vector_only", [False, True])
+def test_contraction_within_bound(shape, prec, vector_only):
+    nb, ni, nj, nk = shape
+    c, got, want, mag = _run(prec, nb, ni, nj, nk, 2, vector_only, seed=hash(shape) % 1000)
+    on_mc = not vector_only and ni >= 4 and nj >= 4 and nk >= 1
+    assert c.matrix_cores == on_mc
+    K = 1 << nk
+    ratio = np.abs(got - want) / mag
+    note("max |err| / sum|a||b|", ratio.max(), "bound", _eps(prec, K))
+    assert np.all(np.isfinite(got))
+    assert ratio.max() <= _eps(prec, K)
+    if prec == q.QGM_BF16X3:
+        # the split products are coarser than FP32 ones, and far finer than bf16
+        assert ratio.max() > 2.0 ** -24
+        assert ratio.max() < 2.0 ** -12
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 5, 3), (0, 3, 3, 2)])
+def test_contraction_c128(shape):
+    nb, ni, nj, nk = shape
+    c, got, want, mag = _run(q.QGM_C128, nb, ni, nj, nk, 1, False, seed=5)
+    assert not c.matrix_cores
+    assert (np.abs(got - want) / mag).max() <= _eps(q.QGM_C128, 1 << nk)
+
+
+def test_contraction_rejects_bad_shapes():
+    with pytest.raises(q.QgmError) as e:
+        q.Contraction(q.QGM_C64, 20, 10, 10, 1)
+    assert e.value.status == -1
+    with pytest.raises(q.QgmError) as e:
+        q.Contraction(7, 1, 4, 4, 1)
+    assert e.value.status == -7

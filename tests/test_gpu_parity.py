@@ -7,6 +7,7 @@ Tolerances: complex128 1e-12; complex64 (FP32 arithmetic, unit roundoff
 u = 2^-24) C64_TOL, a bound on accumulated rounding over a few hundred
 dependent operations per slice times the slice-sum cancellation factor.
 """
+import math
 import sys
 
 import numpy as np
@@ -21,11 +22,21 @@ pytestmark = pytest.mark.gpu
 
 C128_TOL = 1e-12
 C64_TOL = 2e-4
-# BF16x3: each real product keeps ~16 significant bits (x = xh + xl with the
-# xl*yl term dropped): relative error <= ~3 * 2^-17 per product; over a few
-# hundred dependent operations (worst-case linear growth) and the slice-sum
-# cancellation 2^{k/2} this bounds the normalised amplitude error by ~2e-2.
-BF16X3_TOL = 2e-2
+# Gradients run the reverse steps after the forward ones: twice the chain
+# depth in the linear rounding bound behind C64_TOL.
+C64_GRAD_TOL = 2 * C64_TOL
+DET = q.QGM_PLAN_DETERMINISTIC
+
+
+def bf16x3_tol(n_steps):
+    """BF16x3: every real product x y becomes xh yh + xh yl + xl yh with
+    x = xh + xl + dx (bfloat16 halves, round to nearest even), which errs by
+    at most 3 * 2^-16 |x y| (tests/test_gpu_contraction.py); over the D =
+    n_steps dependent steps of a plan the rounding errors grow like a random
+    walk, so the normalised amplitude error stays below sqrt(D) * 3 * 2^-16.
+    A plain bfloat16 product (2^-8 per product) or a lost cross term gives
+    about 2^8 times that."""
+    return math.sqrt(n_steps) * 3 * 2.0 ** -16
 
 
 def nerr(a, ref, n_qubits):
@@ -51,7 +62,7 @@ ENGINES = [q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED, q.QGM_ENGINE_WIDE]
 
 def run(text, bits, k=0, prec=q.QGM_C128, params=None, seed=0, engine=q.QGM_ENGINE_AUTO):
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=k, time_budget_s=0.5, seed=seed)
+    sl, order = c.plan_slices(k_req=k, time_budget_s=0.5, seed=seed, flags=DET)
     p = q.Plan(c, sl, order, prec=prec, engine=engine)
     if engine != q.QGM_ENGINE_AUTO:
         assert p.stats()["engine"] == engine
@@ -130,11 +141,11 @@ def test_slicing_and_order_invariance_on_device(config2):
     c = q.Circuit(text)
     outs = []
     for k, seed in [(0, 0), (3, 1), (6, 2), (9, 3), (12, 4)]:
-        sl, order = c.plan_slices(k_req=k, time_budget_s=0.2, seed=seed)
+        sl, order = c.plan_slices(k_req=k, time_budget_s=0.2, seed=seed, flags=DET)
         note("invariance k", k)
         outs.append(q.Plan(c, sl, order).amplitudes(bits[:8]))
     # a different (random) elimination order of the same slices
-    sl, order = c.plan_slices(k_req=4, time_budget_s=0.0)
+    sl, order = c.plan_slices(k_req=4, time_budget_s=0.0, flags=DET)
     rng = np.random.default_rng(0)
     outs.append(q.Plan(c, sl, list(rng.permutation(order))).amplitudes(bits[:8]))
     for o in outs:
@@ -144,7 +155,7 @@ def test_slicing_and_order_invariance_on_device(config2):
 def test_range_resume_equals_full(config2):
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=DET)
     p = q.Plan(c, sl, order)
     full = p.amplitudes_range(bits, None, 0, 64)
     a = p.amplitudes_range(bits, None, 0, 23)     # stop after 23 slices
@@ -170,7 +181,7 @@ def test_device_entry_matches_host_entry(config2, cuda):
     torch = cuda
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=DET)
     p = q.Plan(c, sl, order, prec=q.QGM_C64)
     host = p.amplitudes(bits)
     d_bits = torch.from_numpy(bits).cuda()
@@ -215,7 +226,7 @@ def test_errors_on_device(config2, cuda):
     torch = cuda
     text, bits, _ = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=3, time_budget_s=0.1)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.1, flags=DET)
     p = q.Plan(c, sl, order)
     need = q.qgm_workspace_size(p.h, 4, 8)
     small = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
@@ -236,7 +247,7 @@ def test_errors_on_device(config2, cuda):
 def test_one_shot_entry(config2):
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=2, time_budget_s=0.1)
+    sl, order = c.plan_slices(k_req=2, time_budget_s=0.1, flags=DET)
     a = q.qgm_amplitude(text, bits[5], sl, order)
     assert nerr(a, ref[5], 25) <= C128_TOL
 
@@ -245,7 +256,7 @@ def test_config3_6x6x25_one_launch():
     text = generate_circuit(6, 25, 0)
     bits = random_bitstrings(36, 1024, 1000)
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=10, time_budget_s=1.0)
+    sl, order = c.plan_slices(k_req=10, time_budget_s=1.0, flags=DET)
     p = q.Plan(c, sl, order, prec=q.QGM_C64)
     note("6x6x25, 1024 bitstrings x 2^10 slices, c64, stats", p.stats())
     got = p.amplitudes(bits)
@@ -267,7 +278,7 @@ def test_graph_replay_matches_direct_launch(config2, cuda, engine):
     torch = cuda
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=7, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=7, time_budget_s=0.2, flags=DET)
     p = q.Plan(c, sl, order, prec=q.QGM_C64, engine=engine)
     n_s = 1 << 7
     d_bits = torch.from_numpy(bits).cuda()
@@ -305,7 +316,7 @@ def test_gradient_vs_shift_rule_and_fd(engine):
     text, th, bits = _rz_case(4, 10, 3)
     x = bits[0]
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=2, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=2, time_budget_s=0.2, flags=DET)
     p = q.Plan(c, sl, order, engine=engine, gradient=True)
     note("gradient 4x4x10 RZ, params", len(th), "engine", engine, "stats", p.stats()["n_steps"])
     amp, grad = p.amplitude_grad(x, th)
@@ -325,7 +336,7 @@ def test_gradient_summed_over_slices_5x5x20(engine):
     text, th, bits = _rz_case(5, 20, 1)
     x = bits[0]
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.3)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.3, flags=DET)
     p = q.Plan(c, sl, order, engine=engine, gradient=True)
     note("gradient 5x5x20 RZ, k=6, params", len(th), "engine", engine)
     amp, grad = p.amplitude_grad(x, th)
@@ -346,7 +357,7 @@ def test_gradient_c64_and_device_entry(cuda):
     torch = cuda
     text, th, bits = _rz_case(4, 12, 7, n_bs=3)
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2, flags=DET)
     p = q.Plan(c, sl, order, prec=q.QGM_C64, gradient=True)
     npar = len(th)
     d_bits = torch.from_numpy(bits).cuda()
@@ -360,14 +371,14 @@ def test_gradient_c64_and_device_entry(cuda):
         shift = oracle.sv_gradient_shift(text, bits[i], th)
         ref = oracle.sv_amplitudes(text, [bits[i]], th)[0]
         scale = max(abs(ref), 2.0 ** -8)
-        assert np.max(np.abs(grads[i] - shift)) / scale <= 10 * C64_TOL
+        assert np.max(np.abs(grads[i] - shift)) / scale <= C64_GRAD_TOL
 
 
 def test_autograd_function_gradcheck(cuda):
     torch = cuda
     text, th, bits = _rz_case(3, 8, 11)
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=1, time_budget_s=0.1)
+    sl, order = c.plan_slices(k_req=1, time_budget_s=0.1, flags=DET)
     p = q.Plan(c, sl, order, gradient=True)
     Fn = q.AmplitudeFn
     theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
@@ -387,7 +398,7 @@ def config4():
     """7x7x30 with every T replaced by RZ(theta), k = 6 (64 slices = one group)."""
     text, th, bits = _rz_case(7, 30, 0)
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=2.0)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=2.0, flags=DET)
     return text, th, bits[0], c, sl, order
 
 
@@ -436,7 +447,7 @@ def test_wide_engine_multiple_groups_and_passes(config2):
     text, _, _ = config2
     bits = random_bitstrings(25, 640, 4242)
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=3, time_budget_s=0.2, flags=DET)
     gen = q.Plan(c, sl, order, engine=q.QGM_ENGINE_GENERATED).amplitudes(bits)
     st = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE).stats()
     cap = 7 * st["item_elems"] * 64 * 16 + 100000
@@ -446,33 +457,10 @@ def test_wide_engine_multiple_groups_and_passes(config2):
     assert nerr(wide[::80], ref, 25).max() <= C128_TOL
 
 
-@pytest.mark.parametrize("prec,tol", [(q.QGM_C128, C128_TOL), (q.QGM_C64, C64_TOL)])
-def test_config5_8x8x40_slices_vs_oracle(prec, tol):
-    """8x8x40, k = 20 (max rank <= 22): single slices through the wide engine
-    against the oracle's elimination of the same slice.  Slice values are
-    normalised by the typical slice size 2^{-N/2} / 2^{k/2}."""
-    text = generate_circuit(8, 40, 0)
-    x = random_bitstrings(64, 1, 1000)[0]
-    c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=20, time_budget_s=5.0)
-    p = q.Plan(c, sl, order, prec=prec)
-    st = p.stats()
-    note("8x8x40 k=20 prec", prec, {k: st[k] for k in ("engine", "max_rank", "item_elems", "n_steps")})
-    assert st["engine"] == q.QGM_ENGINE_WIDE
-    net = oracle.build_network(text)
-    scale = 2.0 ** -32 / 2.0 ** 10
-    for s in (0, 12345, (1 << 20) - 1):
-        part = p.amplitudes_range([x], None, s, s + 1)[0]
-        got = part[0] + part[2] + 1j * (part[1] + part[3])
-        ref = oracle.ve_slice_values(text, x, sliced=sl, slices=[s], net=net)[0]
-        note("slice", s, "device", got, "oracle", ref)
-        assert abs(got - ref) / max(abs(ref), scale) <= tol
-
-
 def test_autotune_keeps_results(config2):
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=DET)
     for prec, tol in ((q.QGM_C64, C64_TOL), (q.QGM_C128, C128_TOL)):
         p = q.Plan(c, sl, order, prec=prec, engine=q.QGM_ENGINE_GENERATED)
         w = p.autotune(64)
@@ -483,20 +471,21 @@ def test_autotune_keeps_results(config2):
 
 @pytest.mark.parametrize("flags", [0, q.QGM_PLAN_LATENCY])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
-@pytest.mark.parametrize("prec,tol", [(q.QGM_C64, C64_TOL), (q.QGM_C128, C128_TOL), (q.QGM_BF16X3, BF16X3_TOL)])
+@pytest.mark.parametrize("prec,tol", [(q.QGM_C64, C64_TOL), (q.QGM_C128, C128_TOL), (q.QGM_BF16X3, None)])
 def test_multiwave_schedules(config2, waves, prec, tol, flags):
     """The generated kernel with its item tree list-scheduled on 1, 2, 4 or 8
     wavefronts (tensors crossing wavefronts through LDS) against the oracle;
     a schedule whose exchange does not fit in LDS falls back to fewer."""
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.5, flags=flags)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.5, flags=flags | DET)
     p = q.Plan(c, sl, order, prec=prec, engine=q.QGM_ENGINE_GENERATED, waves=waves)
     got_w = p.stats()["waves"]
     note("5x5x20 planner flags", flags, "prec", prec, "waves asked", waves, "got", got_w)
     assert got_w <= waves
     got = p.amplitudes(bits)
     assert np.all(np.isfinite(got))  # a wait that gave up would flag the block with NaN
+    tol = bf16x3_tol(p.stats()["n_steps"]) if tol is None else tol
     assert nerr(got, ref, 25).max() <= tol
 
 
@@ -508,8 +497,9 @@ def test_bf16x3_config2(config2, engine):
     e = nerr(got, ref, 25)
     c64, _ = run(text, bits, k=6, prec=q.QGM_C64, engine=engine)
     e64 = nerr(c64, ref, 25)
-    note("max normalised error bf16x3", e.max(), "c64", e64.max())
-    assert e.max() <= BF16X3_TOL
+    tol = bf16x3_tol(p.stats()["n_steps"])
+    note("max normalised error bf16x3", e.max(), "c64", e64.max(), "tol", tol)
+    assert e.max() <= tol
     assert e.max() > e64.max()  # the split products are coarser than FP32 products
 
 
@@ -519,7 +509,7 @@ def test_wide_prebuilt_step_kernel_matches_generated(config2):
     import os
     text, bits, ref = config2
     c = q.Circuit(text)
-    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=DET)
     gen = q.Plan(c, sl, order, engine=q.QGM_ENGINE_WIDE).amplitudes(bits)
     os.environ["QGM_WIDE_PREBUILT"] = "1"
     try:
@@ -562,8 +552,10 @@ def test_matrix_core_steps_7x7x30():
     assert pb.stats()["mfma_steps"] == sm["mfma_steps"] and pbv.stats()["mfma_steps"] == 0
     ab, abv = pb.amplitudes(bits), pbv.amplitudes(bits)
     note("max err bf16x3 mfma", nerr(ab, ad, 49).max(), "vector", nerr(abv, ad, 49).max())
-    assert nerr(ab, ad, 49).max() <= BF16X3_TOL
-    assert nerr(abv, ad, 49).max() <= BF16X3_TOL
+    tb = bf16x3_tol(pb.stats()["n_steps"])
+    note("bf16x3 tolerance", tb)
+    assert nerr(ab, ad, 49).max() <= tb
+    assert nerr(abv, ad, 49).max() <= tb
     net = oracle.build_network(text)
     scale = 2.0 ** -24.5 / 2.0 ** 3
     for s in (0, 45):
@@ -594,11 +586,12 @@ def test_matrix_core_steps_8x8x40():
 
     pb = q.Plan(c, sl, order, prec=q.QGM_BF16X3, engine=q.QGM_ENGINE_WIDE)
     assert pb.stats()["mfma_steps"] == sm["mfma_steps"]
+    tb = bf16x3_tol(pb.stats()["n_steps"])
     for s0, s1 in ((0, 64), (100, 101), (4095, 4096), (8191, 8192)):
         got, ref, gb = val(pm, s0, s1), val(pd, s0, s1), val(pb, s0, s1)
         note("slices", s0, s1, "mfma", got, "bf16x3", gb, "c128", ref)
         assert abs(got - ref) / max(abs(ref), scale) <= C64_TOL
-        assert abs(gb - ref) / max(abs(ref), scale) <= BF16X3_TOL
+        assert abs(gb - ref) / max(abs(ref), scale) <= tb
 
 
 def test_level_timing_entry_point(cuda):
@@ -667,4 +660,4 @@ def test_gradient_c64_with_matrix_core_steps(config4):
     scale = max(abs(a128), 2.0 ** -24.5)
     note("amp err", abs(a64 - a128) / scale, "max grad err", np.max(np.abs(d64 - d128)) / scale)
     assert abs(a64 - a128) / scale <= C64_TOL
-    assert np.max(np.abs(d64 - d128)) / scale <= C64_TOL
+    assert np.max(np.abs(d64 - d128)) / scale <= C64_GRAD_TOL

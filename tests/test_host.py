@@ -305,3 +305,36 @@ def test_bench_traffic_lookup(monkeypatch):
     assert b.measured_traffic(e["workload"], e["kernel"], 3) is None
     monkeypatch.setattr(b, "source_digest", lambda: "0" * 64)
     assert b.measured_traffic(e["workload"], e["kernel"], e["waves"]) is None
+
+
+@pytest.mark.parametrize("flags", [0, q.QGM_PLAN_LATENCY, q.QGM_PLAN_SEARCH | q.QGM_PLAN_REORDER])
+def test_deterministic_planning_repeats(flags):
+    """QGM_PLAN_DETERMINISTIC counts work instead of time: the same arguments
+    give the same plan, however long each restart takes (a slow host thread
+    is simulated by a concurrent busy loop), and the plan is valid."""
+    import threading
+    text = generate_circuit(5, 20, 3)
+    c = q.Circuit(text)
+    f = flags | q.QGM_PLAN_DETERMINISTIC
+    a = c.plan_slices(k_req=5, time_budget_s=0.4, seed=7, flags=f)
+    stop = []
+
+    def spin():
+        x = 0
+        while not stop:
+            x += 1
+
+    ts = [threading.Thread(target=spin) for _ in range(4)]
+    for t in ts:
+        t.start()
+    try:
+        b = c.plan_slices(k_req=5, time_budget_s=0.4, seed=7, flags=f)
+    finally:
+        stop.append(1)
+        for t in ts:
+            t.join()
+    assert a == b
+    sl, order = a
+    assert len(sl) == 5
+    net = build_network(text)
+    assert sorted(order + sl) == sorted(net.free_vars)

@@ -2,8 +2,10 @@
 
 The wide engine emits each matrix-core step as straight-line HIP whose index
 arithmetic is fixed at plan time.  This test evaluates that arithmetic for
-every block and thread of every matrix-core step of a 7x7x30 plan (complex64
-and BF16x3) and replays the LDS ring in program order:
+every block and thread of every matrix-core step of the stored 7x7x30 plan
+(complex64 and BF16x3), of blocks at both ends of every matrix-core step of
+the benchmark's 8x8x40 plan, and of single contractions that take each of the
+four block shapes, and replays the LDS ring in program order:
   - every HBM copy stays inside the group's item memory and every LDS copy
     target and operand read inside the kernel's LDS array;
   - every operand read finds a slot written by a copy of the same unit,
@@ -60,10 +62,15 @@ COPY = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(gm \+ e 
 E_LINE = re.compile(r"const (?:long long|unsigned) e = (.*);$")
 
 
-def check_step(body, S, E, lds_size, group_c2):
+def check_step(body, S, E, lds_size, group_c2, max_blocks=None):
+    """max_blocks: evaluate only the first and last max_blocks / 2 blocks of
+    the step's range (large steps)."""
     lines = [l.strip() for l in body.split("\n")]
-    blk = np.repeat(np.arange(S, E, dtype=np.int64), 256)
-    th = np.tile(np.arange(256, dtype=np.int64), E - S)
+    blocks = np.arange(S, E, dtype=np.int64)
+    if max_blocks is not None and E - S > max_blocks:
+        blocks = np.concatenate([blocks[:max_blocks // 2], blocks[-(max_blocks // 2):]])
+    blk = np.repeat(blocks, 256)
+    th = np.tile(np.arange(256, dtype=np.int64), len(blocks))
     env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
 
     def ev(e):
@@ -137,19 +144,52 @@ def check_step(body, S, E, lds_size, group_c2):
     return nu
 
 
-@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
-def test_matrix_core_step_indexing_7x7x30(prec, tmp_path, monkeypatch):
+STEP = re.compile(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores\)[^\n]*\n"
+                  r"(.*?)\n  return;\n  \}", re.S)
+
+
+def check_source(src, group_elems, max_blocks=None):
+    steps = list(STEP.finditer(src))
+    shapes = set()
+    for m in steps:
+        lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
+        nu = check_step(m.group(4), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
+        assert nu >= 1
+        shapes.add(re.search(r"const int wi = (.*?), wj = (.*?), wq = (.*?);", m.group(4)).groups())
+    return len(steps), shapes
+
+
+# (wi, wj, wq) of the four block shapes: 2 x 2 tiles, 2 i tiles x 2 item
+# groups, 2 j tiles x 2 item groups, 4 item groups
+SHAPE_212 = ("w4 & 1", "0", "w4 >> 1")
+
+
+@pytest.mark.parametrize("plan,max_blocks,prec", [("7x7x30", None, q.QGM_C64), ("7x7x30", None, q.QGM_BF16X3),
+                                                  ("8x8x40-k8", 8, q.QGM_C64)])
+def test_matrix_core_step_indexing_stored_plans(plan, max_blocks, prec, tmp_path, monkeypatch):
+    """Every matrix-core step of the stored plans (of the benchmark's 8x8x40
+    k = 8 plan: the first and last four blocks of each step)."""
     here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
-    rec = json.load(open(os.path.join(here, "7x7x30.json")))
+    rec = json.load(open(os.path.join(here, plan + ".json")))
     cz = rec["circuit"]
     c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
     monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
     st = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE).stats()
     src = open(glob.glob(str(tmp_path / "qgm_wide_*.hip"))[0]).read()
-    steps = list(re.finditer(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores\)\n"
-                             r"(.*?)\n  return;\n  \}", src, re.S))
-    assert len(steps) == st["mfma_steps"] >= 1
-    for m in steps:
-        lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
-        nu = check_step(m.group(4), int(m.group(1)), int(m.group(2)), lds_size, st["item_elems"] * 64)
-        assert nu >= 1
+    n, _ = check_source(src, st["item_elems"], max_blocks)
+    assert n == st["mfma_steps"] >= 1
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 5, 3), (2, 5, 4, 2), (2, 4, 5, 2), (1, 4, 4, 1), (0, 4, 6, 4)])
+@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
+def test_matrix_core_step_indexing_block_shapes(shape, prec, tmp_path, monkeypatch):
+    """Single contractions (qgm_contraction_create) that take every block
+    shape, among them 5 i bits with 4 j bits, which no stored plan uses."""
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    con = q.Contraction(prec, *shape)
+    assert con.matrix_cores
+    src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+    n, shapes = check_source(src, con.elems)
+    assert n == 1
+    if shape == (2, 5, 4, 2):
+        assert shapes == {SHAPE_212}

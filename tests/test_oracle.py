@@ -298,3 +298,103 @@ def test_min_fill_order_small_width():
     cost, width = oracle.order_cost(net.free_vars, edges, order)
     assert sorted(order) == sorted(net.free_vars)
     assert width <= 12 and cost < 1 << 16
+
+
+# ------------------------------------------------ cost model of an ordering
+def test_order_cost_on_fig3_graph():
+    """Sum of 2^deg(v) on the Fig. 3 graph, worked by hand for the order
+    d, c, h, i, j, a, b, e, f, g: degrees 1, 1, 2, 2, 2, 3, 2, 2, 1, 0 at
+    their eliminations (h adds a-i, i adds a-j, j adds a-g, a adds e-g), so
+    the cost is 2+2+4+4+4+8+4+4+2+1 = 35 and the width 3.  Eliminating e
+    first costs 2^4 (the rank-4 tensor of Fig. 6); c first costs 2^1."""
+    sec = _read_fig3()
+    verts = sorted(sec["graph"][0].split()[1])
+    edges = _edges(sec["graph"][1])
+    assert oracle.order_cost(verts, edges, list("dchijabefg")) == (35, 3)
+    assert oracle.order_cost(verts, edges, ["e"]) == (16, 4)
+    assert oracle.order_cost(verts, edges, ["c", "e"]) == (2 + 8, 3)
+
+
+def test_greedy_extra_slices_keep_the_sum():
+    """Fixing more variables only splits the sum: the extra pieces chosen by
+    the greedy removal add up to the unsliced slice, and the cost per piece
+    does not grow."""
+    from oracle.elimination import _graph_of, greedy_extra_slices
+    text = generate_circuit(4, 12, 1)
+    x = random_bitstrings(16, 1, 1001)[0]
+    net = build_network(text)
+    base, _ = project(net, x)
+    g = _graph_of(base, net.free_vars)
+    verts = sorted(g.vertices)
+    order = min_fill_order(verts, g.edges)
+    cost0, width0 = oracle.order_cost(verts, g.edges, order)
+    extra, rest, cost, width = greedy_extra_slices(verts, g.edges, order, 3)
+    assert len(set(extra)) == 3 and sorted(rest + extra) == sorted(order)
+    assert cost <= cost0 and width <= width0
+    whole = oracle.ve_amplitude(text, x, order=order, net=net)
+    pieces = oracle.ve_slice_values(text, x, sliced=extra, order=rest, net=net)
+    assert len(pieces) == 8
+    assert abs(exact_sum(pieces) - whole) < 1e-15
+    assert abs(whole - oracle.sv_amplitudes(text, [x])[0]) < 1e-14
+
+
+# ------------------------------------------------------- gradient identities
+def _rz_circuit_with_repeats():
+    """H layer, RZ angles on post-H variables, on a variable that is sliced
+    below, twice on one variable (no non-diagonal gate between), and on
+    output variables (after the last SX/SY of their qubit)."""
+    lines = ["qubits 4"] + [f"0 H {q}" for q in range(4)]
+    lines += ["1 RZ 0 0", "1 CZ 1 2", "2 RZ 0 1", "2 SX 1", "3 CZ 0 1", "3 SY 2", "4 RZ 1 2",
+              "4 CZ 2 3", "5 SX 0", "5 RZ 3 3", "6 CZ 0 3", "6 RZ 2 4", "7 SY 3", "7 RZ 0 5", "8 RZ 3 6"]
+    return "\n".join(lines)
+
+
+def test_network_param_var_is_the_qubits_current_variable():
+    text = _rz_circuit_with_repeats()
+    th = random_thetas(7, 7)
+    net = build_network(text, th)
+    # post-H variables are 0..3; SX on 1 at cycle 2 -> 4; SY on 2 at cycle 3 -> 5;
+    # SX on 0 at cycle 5 -> 6; SY on 3 at cycle 7 -> 7
+    assert net.param_var == {0: 0, 1: 0, 2: 4, 3: 3, 4: 5, 5: 6, 6: 7}
+    outs = sorted(v.id for v in net.variables if v.is_output)
+    assert outs == [4, 5, 6, 7]
+
+
+def test_slice_gradients_sum_to_the_shift_rule():
+    """Per-slice derivatives (slice identity) summed over all slices equal the
+    parameter-shift derivative of the state vector; angles on one variable
+    have equal derivatives; an angle on an output variable u = x_q gives
+    (i/2)(2 x_q - 1) alpha."""
+    from oracle.gradient import ve_slice_gradients
+    text = _rz_circuit_with_repeats()
+    th = random_thetas(7, 8)
+    net = build_network(text, th)
+    for x in ([0, 1, 1, 0], [1, 0, 0, 1]):
+        shift = oracle.sv_gradient_shift(text, x, th)
+        alpha = oracle.sv_amplitudes(text, [x], th)[0]
+        # angles 0 and 1 sit on variable 0; 5 and 6 on outputs 6 (qubit 0) and 7 (qubit 3)
+        assert abs(shift[0] - shift[1]) < 1e-15
+        assert abs(shift[5] - 0.5j * (2 * x[0] - 1) * alpha) < 1e-15
+        assert abs(shift[6] - 0.5j * (2 * x[3] - 1) * alpha) < 1e-15
+        free = net.free_vars
+        for sliced in ([], [0], [3, 1], [0, 1, 2, 3]):
+            rest = [v for v in free if v not in sliced]
+            tot = np.zeros(7, complex)
+            per = []
+            for s in range(1 << len(sliced)):
+                per.append(ve_slice_gradients(text, x, th, sliced, rest, s, net=net))
+            per = np.array(per)
+            tot = np.array([exact_sum(per[:, j]) for j in range(7)])
+            assert np.max(np.abs(tot - shift)) < 1e-15
+
+
+def test_porter_thomas_second_moment():
+    """A deep random 4x4 circuit: over all 2^16 outputs, p = 2^N |alpha_x|^2
+    has mean exactly 1 (unitarity) and second moment close to 2, the
+    exponential (Porter-Thomas) value the paper's Rules 1-3 circuits
+    approach (Section "Numerical Results")."""
+    text = generate_circuit(4, 40, 0)
+    psi = oracle.sv_state(text)
+    p = (2.0 ** 16) * np.abs(psi) ** 2
+    assert abs(p.mean() - 1.0) < 1e-12
+    assert abs((p ** 2).mean() - 2.0) < 0.1
