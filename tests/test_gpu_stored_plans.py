@@ -38,6 +38,18 @@ def note(*args):
     print("[gpu-stored]", *args, flush=True)
 
 
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """Plans of these circuits take tens of GiB of workspace: hand the cached
+    blocks back after each test so the next plan's sizes fit."""
+    yield
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
 def bf16x3_tol(n_steps):
     return math.sqrt(n_steps) * 3 * 2.0 ** -16
 
