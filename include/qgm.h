@@ -79,7 +79,21 @@ typedef struct {
   int32_t vector_only;   /* WIDE: 1 = run every step on the vector ALUs; 0 = two-operand
                             complex64 and BF16x3 contractions with >= 4 row bits, >= 4
                             column bits and >= 1 summed bit run on the matrix cores */
-  int32_t reserved[4];
+  int32_t checkpoint_every;  /* gradient plans: 0 = every forward tensor stays in item memory
+                                until its reverse step; n > 0 = only every n-th forward
+                                elimination output is kept (a checkpoint) and the others are
+                                recomputed from the checkpoints during the reverse pass */
+  int32_t persistent;        /* GENERATED: 1 = a resident grid (as many blocks as fit on the
+                                device) pulls 64-item chunks from a device work queue instead
+                                of one block per chunk (INTERPRETER always works this way;
+                                WIDE launches one kernel per level) */
+  int32_t deterministic;     /* 0 or 1.  Every engine already returns bit-identical results for
+                                identical inputs (fixed slice-sum order, no atomics in any
+                                sum); 1 documents the caller's reliance on it */
+  int32_t reserved0;
+  const char* tile_table_path; /* WIDE matrix-core steps: a tile table written by
+                                qgm_tile_autotune; steps whose shape has an entry use the
+                                tuned tile parameters; NULL = built-in choice */
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item

@@ -87,8 +87,13 @@ def qgm_order_cost(c, sliced, order):
 
 def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
                     engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
-                    vector_only: bool = False):
+                    vector_only: bool = False, checkpoint_every: int = 0, persistent: bool = False,
+                    deterministic: bool = False, tile_table_path: str | None = None):
     opts = PlanOpts()
+    opts.checkpoint_every = checkpoint_every
+    opts.persistent = int(persistent)
+    opts.deterministic = int(deterministic)
+    opts.tile_table_path = None if tile_table_path is None else tile_table_path.encode()
     opts.prec = prec
     opts.profile = 1 if profile else 0
     opts.engine = engine
@@ -318,14 +323,16 @@ class Plan:
 
     def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
                  profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
-                 vector_only: bool = False):
+                 vector_only: bool = False, checkpoint_every: int = 0, persistent: bool = False,
+                 deterministic: bool = False, tile_table_path: str | None = None):
         self.circuit = circuit
         self.sliced = list(sliced)
         self.order = list(order)
         self.prec = prec
         self.gradient = gradient
         self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine,
-                                 gradient, waves, vector_only)
+                                 gradient, waves, vector_only, checkpoint_every, persistent, deterministic,
+                                 tile_table_path)
         self._ws = None
 
     @property

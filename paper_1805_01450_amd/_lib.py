@@ -25,7 +25,8 @@ class VarInfo(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("profile", C.c_int32), ("workspace_cap", C.c_size_t),
                 ("engine", C.c_int32), ("gradient", C.c_int32), ("waves", C.c_int32),
-                ("vector_only", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("vector_only", C.c_int32), ("checkpoint_every", C.c_int32), ("persistent", C.c_int32),
+                ("deterministic", C.c_int32), ("reserved0", C.c_int32), ("tile_table_path", C.c_char_p)]
 
 
 class Stats(C.Structure):
@@ -92,7 +93,8 @@ def _load():
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
             "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
-            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
+            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device",
+            "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_level_timing", "qgm_plan_autotune", "qgm_plan_free",
             "qgm_last_error", "qgm_amplitude", "qgm_contraction_create", "qgm_contraction_info",
             "qgm_contraction_run", "qgm_contraction_free")

@@ -270,6 +270,12 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8)
     return fail(QGM_E_ARG, "waves must be 0, 1, 2, 4 or 8");
   if (o.vector_only != 0 && o.vector_only != 1) return fail(QGM_E_ARG, "vector_only must be 0 or 1");
+  if (o.persistent != 0 && o.persistent != 1) return fail(QGM_E_ARG, "persistent must be 0 or 1");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(QGM_E_ARG, "deterministic must be 0 or 1");
+  if (o.checkpoint_every < 0) return fail(QGM_E_ARG, "checkpoint_every must be >= 0");
+  if (o.checkpoint_every > 0 && !o.gradient) return fail(QGM_E_ARG, "checkpoint_every needs a gradient plan");
+  if (o.checkpoint_every > 0) return fail(QGM_E_UNSUPPORTED, "checkpointed reverse pass not built yet");
+  if (o.tile_table_path) return fail(QGM_E_UNSUPPORTED, "tile tables not built yet");
   auto* p = new qgm_plan();
   p->net = c->net;
   p->sliced = sv;
@@ -363,7 +369,9 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   }
   if (want_gen) {
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits, &p->dev.chain_waves, o.waves);
+    std::string src = generate_chain_source(p->prog, o.prec, p->net.n_qubits, &p->dev.chain_waves, o.waves,
+                                            o.persistent != 0);
+    p->dev.chain_persistent = o.persistent;
     std::string jerr;
     bool ok = jit_compile(src, "qgm_chain.hip", p->code, jerr);
     if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
@@ -485,6 +493,7 @@ qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const d
 }
 
 }  // namespace
+
 
 extern "C" {
 
@@ -799,7 +808,7 @@ qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void*
   for (int w : {1, 2, 4, 8}) {
     if (w == best.waves) continue;  // the current kernel
     int got = 0;
-    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w);
+    std::string src = generate_chain_source(p->prog, p->opts.prec, p->net.n_qubits, &got, w, p->opts.persistent != 0);
     if (got != w) continue;  // no cut on w wavefronts fits for the plan
     Variant v;
     std::string jerr;

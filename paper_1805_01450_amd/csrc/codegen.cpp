@@ -342,8 +342,12 @@ Sched choose_schedule(const Program& prog, size_t elem_bytes, int force_waves) {
 
 }  // namespace
 
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves) {
-  std::ostringstream head, o;
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves,
+                                  bool persistent) {
+  std::ostringstream head, item_head, blockhead, o;
+  // persistent: the block loops over 64-item chunks taken from a device work
+  // queue; the per-chunk code leaves through `qnext` instead of returning
+  const std::string leave = persistent ? "goto qnext;" : "return;";
   const char* R = prec == 0 ? "double" : "float";
   const Sched sch = choose_schedule(prog, prec == 0 ? 16 : 8, force_waves);
   // BF16x3: products from bf16 hi/lo splits with FP32 accumulation
@@ -419,12 +423,16 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
        << ") qgm_chain(const unsigned char* __restrict__ bits, unsigned long long n_s, unsigned long long s_begin, "
           "unsigned long long n_items, unsigned long long n_bs, int n_qubits, int fused, int ns_log2, "
           "const double* __restrict__ params, C2* __restrict__ res, C2* __restrict__ gres, "
-          "double* __restrict__ part, const double* __restrict__ rawd) {\n"
-       << "  (void)rawd; (void)params; (void)gres;\n"
+          "double* __restrict__ part, const double* __restrict__ rawd, unsigned* __restrict__ queue) {\n"
+       << "  (void)rawd; (void)params; (void)gres; (void)queue;\n"
        << "  const int lane = threadIdx.x & 63;\n"
        << "  const int wave = threadIdx.x >> 6;\n"
-       << "  (void)wave;\n"
-       << "  unsigned long long item = (unsigned long long)blockIdx.x * 64ull + lane;\n"
+       << "  (void)wave;\n";
+  if (persistent)
+    item_head << "  unsigned long long item = chunk * 64ull + lane;\n";
+  else
+    item_head << "  unsigned long long item = (unsigned long long)blockIdx.x * 64ull + lane;\n";
+  item_head
        << "  const bool valid = item < n_items;\n"
        << "  if (!valid) item = n_items - 1;\n"
        // no 64-bit division when the slice count is a power of two
@@ -453,23 +461,23 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
        << "  } else {\n"
        << "    const unsigned char* xrow = bits + b * (unsigned long long)n_qubits;\n";
   for (int q = 0; q < n_qubits; ++q)
-    head << "    xb |= (unsigned long long)(xrow[" << q << "] & 1) << " << q << ";\n";
-  head << "  }\n"
-       << "  (void)s; (void)xb; (void)xlane;\n";
+    item_head << "    xb |= (unsigned long long)(xrow[" << q << "] & 1) << " << q << ";\n";
+  item_head << "  }\n"
+            << "  (void)s; (void)xb; (void)xlane;\n";
   // (the empty asm pins the first use of the loaded byte here, so the
   // compiler cannot move the test, and with it the wait, up to the load)
   const std::string pack_bits =
       "  if (fused) {\n    asm volatile(\"\" : \"+v\"(xlane));\n"
       "    xb = __ballot(lane < n_qubits && (xlane & 1u));\n  }\n";
   // LDS slots of the piece roots of the multi-wavefront schedule
-  if (W > 1) head << "  __shared__ C2 xch[" << std::max(1, sch.lds_elems) << "][64];\n";
+  if (W > 1) blockhead << "  __shared__ C2 xch[" << std::max(1, sch.lds_elems) << "][64];\n";
   int n_params = 0;
   for (int k = 0; k < prog.n_raw; ++k) n_params = std::max(n_params, prog.raw_param[k] + 1);
   if (n_params > 0) {
     // Per angle theta_j, u = 0, 1: RZ entries e^{-+i h} (h = theta_j / 2)
     // and their theta-derivatives (i/2)(2u - 1) e^{i (2u - 1) h}; the threads
     // of the block share the work, one angle per thread.
-    head << "  __shared__ C2 ptab[" << 4 * n_params << "];\n"
+    blockhead << "  __shared__ C2 ptab[" << 4 * n_params << "];\n"
          << "  for (int j = threadIdx.x; j < " << n_params << "; j += blockDim.x) {\n"
          << "    double sn, cs;\n"
          << "    sincos(0.5 * params[j], &sn, &cs);\n"
@@ -479,7 +487,7 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
          << "    ptab[4 * j + 3] = C2{(R)(-0.5 * sn), (R)(0.5 * cs)};\n"
          << "  }\n";
   }
-  if (n_params > 0) head << "  __syncthreads();\n";
+  if (n_params > 0) blockhead << "  __syncthreads();\n";
 
   auto emit_step = [&](Branch& br, const Step& st) {
     if (st.kind == ST_LEAF) {
@@ -578,7 +586,7 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
       o << "  }\n";
     }
     o << "  __syncthreads();\n"
-      << "  if (wave != " << sch.top_wave << ") return;\n";
+      << "  if (wave != " << sch.top_wave << ") " << leave << "\n";
     Branch br(prog, o);
     std::set<int> loaded;
     for (int i : sch.seq[sch.top_wave]) {
@@ -599,7 +607,7 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
   // the reduction kernels use for each chunk of 64 slices
   o << "  if (!fused) {\n"
     << "    if (valid) res[sl * n_bs + b] = amp;\n"
-    << "    return;\n"
+    << "    " << leave << "\n"
     << "  }\n"
     << "  double sr = (double)amp.x, si = (double)amp.y, cr = 0.0, ci = 0.0;\n"
     << "  wave_sum(sr, cr);\n"
@@ -610,9 +618,30 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
     << "    part[4 * chunk + 1] = si;\n"
     << "    part[4 * chunk + 2] = cr;\n"
     << "    part[4 * chunk + 3] = ci;\n"
+    << "  }\n";
+  if (!persistent) {
+    o << "}\n";
+    return head.str() + item_head.str() + blockhead.str() + o.str();
+  }
+  // Persistent form: a block's first chunk is its block index, later ones
+  // come from the queue counter (zero at launch), offset by the grid size.
+  // Every wave of the block passes the same barriers each round, so the
+  // exchange slots and the shared chunk index are free for the next round.
+  std::ostringstream loop;
+  loop << "  __shared__ unsigned long long q_chunk;\n"
+       << "  const unsigned long long n_chunks = (n_items + 63ull) / 64ull;\n"
+       << "  unsigned long long chunk = blockIdx.x;\n"
+       << "  while (chunk < n_chunks) {\n"
+       << "  {\n";
+  o << "  }\n"
+    << "  qnext:\n"
+    << "  __syncthreads();\n"
+    << "  if (threadIdx.x == 0) q_chunk = (unsigned long long)gridDim.x + atomicAdd(queue, 1u);\n"
+    << "  __syncthreads();\n"
+    << "  chunk = q_chunk;\n"
     << "  }\n"
     << "}\n";
-  return head.str() + o.str();
+  return head.str() + blockhead.str() + loop.str() + item_head.str() + o.str();
 }
 
 }  // namespace qgm

@@ -55,6 +55,7 @@ struct DevProgram {
   void* module = nullptr;  // hipModule_t of the generated chain kernel
   void* chain_fn = nullptr;  // hipFunction_t "qgm_chain"
   int chain_waves = 1;       // wavefronts per block of the generated kernel
+  int chain_persistent = 0;  // 1: the generated kernel pulls chunks from a work queue (resident grid)
 };
 
 // Precision of the slice contraction: 0 = complex128, 1 = complex64.

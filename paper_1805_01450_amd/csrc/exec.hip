@@ -274,6 +274,10 @@ __global__ void __launch_bounds__(64) reduce_kernel(const cx<R>* __restrict__ re
 
 // Chunk partials [b][chunk][4] written by the generated kernel (same chunk
 // sums as above) -> per-bitstring partial.
+// Resets the persistent chain kernel's work-queue counter (a fill kernel
+// rather than a memset, so captured graphs replay it correctly).
+__global__ void zero_counter_kernel(unsigned* __restrict__ counter) { *counter = 0u; }
+
 __global__ void combine_kernel(const double* __restrict__ chunks, int n_bs, uint64_t per_bs,
                                double* __restrict__ partial) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -585,9 +589,20 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
     void* a_part = part;
     int a_fused = ws.fused;
     int a_log2 = (cfg.n_s & (cfg.n_s - 1)) == 0 ? __builtin_ctzll(cfg.n_s) : -1;
+    void* a_queue = counter;
     void* args[] = {&a_bits, &a_ns, &a_sb, &a_ni, &a_nbs, &a_nq, &a_fused, &a_log2, &a_par, &a_res, &a_gres, &a_part,
-                    &a_raw};
-    HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)n_blocks, 1, 1, kLanes * dp.chain_waves, 1,
+                    &a_raw, &a_queue};
+    uint64_t grid = n_blocks;
+    if (dp.chain_persistent) {
+      // resident blocks only; the rest of the chunks come from the queue
+      int occ = 0;
+      if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (hipFunction_t)dp.chain_fn,
+                                                             kLanes * dp.chain_waves, 0) != hipSuccess || occ < 1)
+        occ = 1;
+      grid = std::min<uint64_t>(n_blocks, (uint64_t)std::max(1, dp.n_cu) * (uint64_t)occ);
+      hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+    }
+    HIP_OK(hipModuleLaunchKernel((hipFunction_t)dp.chain_fn, (unsigned)grid, 1, 1, kLanes * dp.chain_waves, 1,
                                  1, 0, stream, args, nullptr));
     mark(2);
     if (!ws.fused)

@@ -196,7 +196,11 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
 // *waves_out gets the wavefronts per block (the item tree may be cut across
 // several wavefronts that run the same 64 items).
 // force_waves > 0 requests that many wavefronts (0 = cost model).
-std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0);
+// persistent = true: a grid of resident blocks pulls 64-item chunks from a
+// device work queue (a counter that must be zero at launch) instead of one
+// block per chunk.
+std::string generate_chain_source(const Program& prog, int prec, int n_qubits, int* waves_out, int force_waves = 0,
+                                  bool persistent = false);
 // hiprtc compilation of `src` for gfx950 into a code object.
 bool jit_compile(const std::string& src, const char* name, std::vector<char>& code, std::string& err);
 

@@ -338,3 +338,20 @@ def test_deterministic_planning_repeats(flags):
     assert len(sl) == 5
     net = build_network(text)
     assert sorted(order + sl) == sorted(net.free_vars)
+
+
+def test_persistent_generated_kernels_compile():
+    """opts.persistent = 1: the generated kernel's work-queue form compiles
+    for every wavefront cut, with and without RZ tables; bad values are
+    refused."""
+    for rz in (False, True):
+        text = generate_circuit(5, 20, 0, rz=rz)
+        c = q.Circuit(text)
+        sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=q.QGM_PLAN_DETERMINISTIC)
+        for w in (1, 4):
+            p = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_GENERATED, waves=w, persistent=True,
+                       gradient=rz)
+            assert p.stats()["engine"] == q.QGM_ENGINE_GENERATED
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, sl, order, persistent=2)
+    assert e.value.status == -1
