@@ -275,6 +275,23 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bitstrings, int32_t 
 qgm_status qgm_amplitudes_device(qgm_plan* p, const uint8_t* d_bitstrings, int32_t n_bs, const double* d_params,
                                  uint64_t s_begin, uint64_t s_end, void* d_workspace, size_t ws_bytes,
                                  void* hip_stream, double* d_partial);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run of
+ * qgm_amplitudes_device with the workspace taken from a fixed array of
+ * QGM_NOALLOC_SCRATCH_BYTES (64 MiB) in the library's device image, one copy
+ * per GPU, held until the process ends.  No device memory is allocated or
+ * freed by the call.  The plan's tables must already be on the current device
+ * (any earlier ordinary call on it, e.g. qgm_workspace_size, uploads them);
+ * profiling events are not recorded.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (on different streams or
+ * threads) race and give wrong results; the run clears what must start at
+ * zero itself.  Arguments and results as qgm_amplitudes_device.
+ * Errors: QGM_E_ARG (as qgm_amplitudes_device; plan not yet on this device),
+ * QGM_E_WORKSPACE (the run needs more than QGM_NOALLOC_SCRATCH_BYTES; the
+ * message gives the size), QGM_E_HIP. */
+#define QGM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+qgm_status qgm_amplitudes_device_noalloc(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                                         uint64_t s_begin, uint64_t s_end, void* hip_stream, double* d_partial);
 /* Batching (the paper's independent subtasks run together, Section
  * "Parallelization by fixing the values of variables"; the graph itself is
  * this library's launch mechanism):

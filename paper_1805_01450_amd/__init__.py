@@ -163,6 +163,15 @@ def qgm_amplitudes_device(p, d_bits, d_params, s_begin: int, s_end: int, workspa
                                     _ptr(workspace), workspace.numel(), _stream(stream), _ptr(d_partial)))
 
 
+QGM_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def qgm_amplitudes_device_noalloc(p, d_bits, d_params, s_begin: int, s_end: int, d_partial, stream=None) -> None:
+    """qgm_amplitudes_device with the library's fixed device workspace (no allocation)."""
+    check(lib.qgm_amplitudes_device_noalloc(p, _ptr(d_bits), d_bits.shape[0], _ptr(d_params), s_begin, s_end,
+                                            _stream(stream), _ptr(d_partial)))
+
+
 def qgm_gradients_device(p, d_bits, d_params, s_begin: int, s_end: int, workspace, d_partial, d_grad_partial,
                          stream=None) -> None:
     """All-device amplitudes and d alpha / d theta: d_grad_partial float64 (n_bs, n_params, 4)."""

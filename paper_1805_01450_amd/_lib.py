@@ -78,6 +78,7 @@ def _load():
         "qgm_plan_free": (None, [P]),
         "qgm_last_error": (C.c_char_p, []),
         "qgm_amplitude": (i32, [C.c_char_p, sz, pu8, pi32, i32, pi32, i32, pd, pd]),
+        "qgm_amplitudes_device_noalloc": (i32, [P, P, i32, P, u64, u64, P, P]),
         "qgm_contraction_create": (i32, [i32, i32, i32, i32, i32, i32, C.POINTER(P)]),
         "qgm_contraction_info": (i32, [P, pi32, C.POINTER(u64), pd]),
         "qgm_contraction_run": (i32, [P, P, C.c_int64, P]),
@@ -93,7 +94,7 @@ def _load():
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
             "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
-            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device",
+            "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_amplitudes_device_noalloc",
             "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_level_timing", "qgm_plan_autotune", "qgm_plan_free",
             "qgm_last_error", "qgm_amplitude", "qgm_contraction_create", "qgm_contraction_info",

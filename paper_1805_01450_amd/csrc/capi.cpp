@@ -452,14 +452,26 @@ qgm_status qgm_workspace_size(const qgm_plan* pc, int32_t n_bs, uint64_t n_slice
 namespace {
 
 // Queue one run on `stream`; the caller holds p->mu.
+// no_alloc: nothing is allocated on the device or registered with the
+// runtime: the plan's tables must already be on the current device (they
+// are uploaded by the first ordinary run or qgm_workspace_size) and no
+// profiling events are recorded.
 qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params, uint64_t s_begin,
                        uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream, double* d_partial,
-                       bool capturing = false, double* d_grad_partial = nullptr) {
+                       bool capturing = false, double* d_grad_partial = nullptr, bool no_alloc = false) {
   if (!p || n_bs < 0 || (n_bs > 0 && (!d_bits || !d_partial)) || !d_ws) return fail(QGM_E_ARG, "bad argument");
   if (p->net.n_params > 0 && !d_params) return fail(QGM_E_ARG, "circuit has RZ gates but params is NULL");
   qgm_status s = check_range(p, s_begin, s_end);
   if (s) return s;
-  if ((s = ensure_device(p))) return s;
+  if (no_alloc) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(QGM_E_HIP, "hipGetDevice failed");
+    if (!p->dev.steps || p->dev.device != dev)
+      return fail(QGM_E_ARG, "plan tables are not on the current device yet (call qgm_workspace_size first)");
+    capturing = true;  // no profiling events
+  } else if ((s = ensure_device(p))) {
+    return s;
+  }
   WsLayout ws;
   LaunchCfg cfg;
   if ((s = layout_for(p, n_bs, s_end - s_begin, ws, cfg))) return s;
@@ -494,6 +506,21 @@ qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const d
 
 }  // namespace
 
+namespace qgm {
+// The run of qgm_amplitudes_device on a workspace the allocation-free entry
+// point supplies (its fixed device array); see enqueue_run's no_alloc.
+qgm_status run_on_fixed_workspace(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const double* d_params,
+                                  uint64_t s_begin, uint64_t s_end, void* d_ws, size_t ws_bytes, void* stream,
+                                  double* d_partial) {
+  GUARD_BEGIN
+  if (!p) return fail(QGM_E_ARG, "null plan");
+  std::lock_guard<std::mutex> lk(p->mu);
+  return enqueue_run(p, d_bits, n_bs, d_params, s_begin, s_end, d_ws, ws_bytes, stream, d_partial, false, nullptr,
+                     true);
+  GUARD_END
+}
+qgm_status fail_status(qgm_status s, const char* msg) { return fail(s, msg); }
+}  // namespace qgm
 
 extern "C" {
 
