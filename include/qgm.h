@@ -92,8 +92,10 @@ typedef struct {
                                 sum); 1 documents the caller's reliance on it */
   int32_t reserved0;
   const char* tile_table_path; /* WIDE matrix-core steps: a tile table written by
-                                qgm_tile_autotune; steps whose shape has an entry use the
-                                tuned tile parameters; NULL = built-in choice */
+                                qgm_plan_tune_tiles (read at plan creation; the string is
+                                not kept); steps whose shape has an entry use the tuned
+                                tile parameters; NULL = built-in choice.  An unreadable or
+                                malformed table is QGM_E_ARG */
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
@@ -396,8 +398,20 @@ const char* qgm_last_error(void);
  * Errors: QGM_E_ARG (counts: nb + ni + nj <= 32, nk <= 16, E < 2^31),
  * QGM_E_UNSUPPORTED (precision, compile failure), QGM_E_HIP. */
 typedef struct qgm_contraction qgm_contraction;
+/* Tile parameters of a matrix-core step (see qgm_plan_tune_tiles):
+ *   per: k steps per LDS stage, one block barrier each (power of two; BF16x3
+ *     uses pairs, so at least 2);
+ *   lds_budget: bytes of LDS the operand ring may use (2..8 stages);
+ *   jband: log2 of the j blocks that run next to each other on one XCD;
+ *   layout: 0 = built-in (2 x 2 wavefront tiles when both sides have 5 or
+ *     more bits), 1 = four 16-item groups per block, 2 = two i tiles x two
+ *     item groups, 3 = two j tiles x two item groups. */
+typedef struct {
+  int32_t per, lds_budget, jband, layout;
+} qgm_tile;
+/* tile: NULL = built-in choice.  Errors also: QGM_E_ARG (tile out of range). */
 qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t nj, int32_t nk, int32_t flags,
-                                  qgm_contraction** out);
+                                  const qgm_tile* tile, qgm_contraction** out);
 /* *matrix_cores = 1 when the step runs on the matrix cores; *elems_per_item
  * = E; *flops_per_item = useful real flops per item (8 per complex
  * multiply-add). */
@@ -405,6 +419,21 @@ qgm_status qgm_contraction_info(const qgm_contraction* c, int32_t* matrix_cores,
                                 double* flops_per_item);
 qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups, void* hip_stream);
 void qgm_contraction_free(qgm_contraction* c);
+
+/* Not in the paper (a launch-shape choice of this library).  Tile autotuner
+ * for the matrix-core steps of a WIDE complex64 or BF16x3 plan: for each
+ * step shape (ni, nj, nk), largest flops first until 99 % of the plan's
+ * matrix-core flops are covered, candidate tiles (block layout and k per
+ * stage, then ring budget and band) are generated, compiled and timed on the
+ * device as single contractions (qgm_contraction_*; a batch of 64 items with
+ * enough batch bits to fill the GPU, at most 8 GiB of operands, allocated
+ * and freed here; 2 warm-up and 5 timed runs with HIP events on `stream`),
+ * and the fastest is written to the text table at table_path (entries of
+ * other shapes already there are kept).  Plans created with
+ * opts.tile_table_path = table_path then use the tuned tiles.  *n_tuned gets
+ * the number of shapes tuned (0 for plans without matrix-core steps).
+ * Errors: QGM_E_ARG (null, unreadable or unwritable table), QGM_E_HIP. */
+qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* hip_stream, int32_t* n_tuned);
 
 /* One-shot form plan(circuit, bitstring, sliced_vars, order) -> amplitude,
  * the paper's problem statement (compute one amplitude <x|C|0...0> of a

@@ -11,7 +11,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import DECLARED, LIB_PATH, PlanOpts, QgmError, Stats, VarInfo, check, lib  # noqa: F401
+from ._lib import DECLARED, LIB_PATH, PlanOpts, QgmError, Stats, Tile, VarInfo, check, lib  # noqa: F401
 
 QGM_C128 = 0
 QGM_C64 = 1
@@ -261,10 +261,19 @@ def qgm_amplitude(text: str, bitstring, sliced=(), order=None, params=None) -> c
     return complex(out[0], out[1])
 
 
-def qgm_contraction_create(prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False):
+def qgm_contraction_create(prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False, tile=None):
+    """tile: None or (per, lds_budget, jband, layout)."""
     h = C.c_void_p()
-    check(lib.qgm_contraction_create(prec, nb, ni, nj, nk, 1 if vector_only else 0, C.byref(h)))
+    t = None if tile is None else C.byref(Tile(*tile))
+    check(lib.qgm_contraction_create(prec, nb, ni, nj, nk, 1 if vector_only else 0, t, C.byref(h)))
     return h
+
+
+def qgm_plan_tune_tiles(p, table_path: str, stream=None) -> int:
+    """Tune the matrix-core tiles of a WIDE plan on the device; writes the table. Returns the shapes tuned."""
+    n = C.c_int32()
+    check(lib.qgm_plan_tune_tiles(p, table_path.encode(), _stream(stream), C.byref(n)))
+    return n.value
 
 
 def qgm_contraction_info(h):
@@ -285,9 +294,9 @@ def qgm_contraction_free(h) -> None:
 class Contraction:
     """Owning wrapper of one two-operand contraction step (qgm_contraction_*)."""
 
-    def __init__(self, prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False):
+    def __init__(self, prec: int, nb: int, ni: int, nj: int, nk: int, vector_only: bool = False, tile=None):
         self.prec, self.nb, self.ni, self.nj, self.nk = prec, nb, ni, nj, nk
-        self.h = qgm_contraction_create(prec, nb, ni, nj, nk, vector_only)
+        self.h = qgm_contraction_create(prec, nb, ni, nj, nk, vector_only, tile)
         self.matrix_cores, self.elems, self.flops = qgm_contraction_info(self.h)
 
     def run(self, d_mem, n_groups: int, stream=None) -> None:

@@ -29,6 +29,10 @@ class PlanOpts(C.Structure):
                 ("deterministic", C.c_int32), ("reserved0", C.c_int32), ("tile_table_path", C.c_char_p)]
 
 
+class Tile(C.Structure):
+    _fields_ = [("per", C.c_int32), ("lds_budget", C.c_int32), ("jband", C.c_int32), ("layout", C.c_int32)]
+
+
 class Stats(C.Structure):
     _fields_ = [("n_steps", C.c_int32), ("n_const_steps", C.c_int32), ("max_rank", C.c_int32),
                 ("item_elems", C.c_int32), ("n_leaves", C.c_int32), ("k", C.c_int32),
@@ -79,7 +83,8 @@ def _load():
         "qgm_last_error": (C.c_char_p, []),
         "qgm_amplitude": (i32, [C.c_char_p, sz, pu8, pi32, i32, pi32, i32, pd, pd]),
         "qgm_amplitudes_device_noalloc": (i32, [P, P, i32, P, u64, u64, P, P]),
-        "qgm_contraction_create": (i32, [i32, i32, i32, i32, i32, i32, C.POINTER(P)]),
+        "qgm_contraction_create": (i32, [i32, i32, i32, i32, i32, i32, C.POINTER(Tile), C.POINTER(P)]),
+        "qgm_plan_tune_tiles": (i32, [P, C.c_char_p, P, pi32]),
         "qgm_contraction_info": (i32, [P, pi32, C.POINTER(u64), pd]),
         "qgm_contraction_run": (i32, [P, P, C.c_int64, P]),
         "qgm_contraction_free": (None, [P]),
@@ -98,7 +103,7 @@ DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_ci
             "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_level_timing", "qgm_plan_autotune", "qgm_plan_free",
             "qgm_last_error", "qgm_amplitude", "qgm_contraction_create", "qgm_contraction_info",
-            "qgm_contraction_run", "qgm_contraction_free")
+            "qgm_contraction_run", "qgm_contraction_free", "qgm_plan_tune_tiles")
 
 
 def check(status: int) -> None:

@@ -46,6 +46,8 @@ struct qgm_plan {
   std::vector<std::array<hipEvent_t, 4>> runs;  // profiling events, one set per run
   std::vector<std::vector<hipEvent_t>> level_runs;  // WIDE profiling: events around each level launch
   std::vector<uint64_t> level_items;                 // items of the pass those events cover
+  TileTable tiles;                                   // WIDE: matrix-core tile table (opts.tile_table_path)
+  std::string tile_table_path;
   ~qgm_plan() {
     for (auto& r : runs)
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
@@ -274,16 +276,24 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   if (o.deterministic != 0 && o.deterministic != 1) return fail(QGM_E_ARG, "deterministic must be 0 or 1");
   if (o.checkpoint_every < 0) return fail(QGM_E_ARG, "checkpoint_every must be >= 0");
   if (o.checkpoint_every > 0 && !o.gradient) return fail(QGM_E_ARG, "checkpoint_every needs a gradient plan");
-  if (o.checkpoint_every > 0) return fail(QGM_E_UNSUPPORTED, "checkpointed reverse pass not built yet");
-  if (o.tile_table_path) return fail(QGM_E_UNSUPPORTED, "tile tables not built yet");
+  TileTable tiles;
+  std::string tile_path;
+  if (o.tile_table_path) {
+    tile_path = o.tile_table_path;
+    std::string terr;
+    if (!read_tile_table(tile_path, tiles, terr)) return fail(QGM_E_ARG, terr);
+    o.tile_table_path = nullptr;  // the caller's string is not kept
+  }
   auto* p = new qgm_plan();
   p->net = c->net;
   p->sliced = sv;
   p->order = ov;
   p->opts = o;
+  p->tiles = std::move(tiles);
+  p->tile_table_path = tile_path;
   std::string err;
   int code = 0;
-  if (!compile_program(p->net, sv, ov, p->prog, err, code, o.gradient != 0)) {
+  if (!compile_program(p->net, sv, ov, p->prog, err, code, o.gradient != 0, false, o.checkpoint_every)) {
     delete p;
     return fail((qgm_status)code, err);
   }
@@ -351,7 +361,8 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     // per-step generated kernels; the prebuilt step kernel stays the fallback
     if (!std::getenv("QGM_WIDE_PREBUILT")) {
       auto t0 = std::chrono::steady_clock::now();
-      std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels, !o.vector_only);
+      std::string src = generate_wide_source(p->prog, p->wide, o.prec, p->wide_kernels, !o.vector_only,
+                                             p->tiles.empty() ? nullptr : &p->tiles);
       if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
         // debugging aid: keep the generated source
         if (FILE* f = std::fopen((std::string(dir) + "/qgm_wide_" + std::to_string((uintptr_t)p) + ".hip").c_str(), "w")) {
@@ -918,9 +929,12 @@ struct qgm_contraction {
 extern "C" {
 
 qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t nj, int32_t nk, int32_t flags,
-                                  qgm_contraction** out) {
+                                  const qgm_tile* tile, qgm_contraction** out) {
   GUARD_BEGIN
   if (!out) return fail(QGM_E_ARG, "null argument");
+  if (tile && (tile->per < 1 || tile->per > 16 || (tile->per & (tile->per - 1)) || tile->lds_budget < 1024 ||
+               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 3))
+    return fail(QGM_E_ARG, "tile parameters out of range");
   *out = nullptr;
   if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");
   if (nb < 0 || ni < 0 || nj < 0 || nk < 0 || nb + ni + nj > kWideMaxOut || nk > kWideMaxSum)
@@ -963,7 +977,9 @@ qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t 
   w.n_steps = 1;
   std::vector<WideKernel> kernels;
   Program none;
-  const std::string src = generate_wide_source(none, w, prec, kernels, (flags & 1) == 0);
+  TileTable one;
+  if (tile) one[TileKey{prec, ni, nj, nk}] = MfmaTile{tile->per, tile->lds_budget, tile->jband, tile->layout};
+  const std::string src = generate_wide_source(none, w, prec, kernels, (flags & 1) == 0, tile ? &one : nullptr);
   if (const char* dir = std::getenv("QGM_DUMP_DIR")) {
     // debugging aid: keep the generated source
     if (FILE* f = std::fopen((std::string(dir) + "/qgm_contract_" + std::to_string((uintptr_t)c) + ".hip").c_str(), "w")) {
@@ -1031,5 +1047,121 @@ qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups
 }
 
 void qgm_contraction_free(qgm_contraction* c) { delete c; }
+
+qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream_, int32_t* n_tuned) {
+  GUARD_BEGIN
+  if (!p || !table_path || !n_tuned) return fail(QGM_E_ARG, "null argument");
+  *n_tuned = 0;
+  if (p->engine != QGM_ENGINE_WIDE || (p->opts.prec != QGM_C64 && p->opts.prec != QGM_BF16X3) || p->opts.vector_only)
+    return QGM_OK;  // no matrix-core steps
+  hipStream_t stream = (hipStream_t)stream_;
+  // the plan's matrix-core shapes by their flops per item, largest first
+  std::map<TileKey, double> shape_flops;
+  std::map<TileKey, int> shape_nb;
+  for (int si = 0; si < p->wide.n_steps; ++si) {
+    int nb = 0, ni = 0, nj = 0, nk = 0;
+    if (!mfma_step_shape(p->wide, si, p->opts.prec, nb, ni, nj, nk)) continue;
+    const TileKey key{p->opts.prec, ni, nj, nk};
+    shape_flops[key] += std::ldexp(8.0, nb + ni + nj + nk);
+    shape_nb[key] = std::max(shape_nb[key], nb);
+  }
+  std::vector<std::pair<double, TileKey>> order;
+  double total = 0;
+  for (auto& e : shape_flops) {
+    order.push_back({-e.second, e.first});
+    total += e.second;
+  }
+  std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  TileTable table;
+  {
+    std::string terr;
+    FILE* f = std::fopen(table_path, "r");
+    if (f) {
+      std::fclose(f);
+      if (!read_tile_table(table_path, table, terr)) return fail(QGM_E_ARG, terr);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(QGM_E_HIP, "hipEventCreate failed");
+  void* mem = nullptr;
+  size_t mem_bytes = 0;
+  qgm_status st = QGM_OK;
+  double covered = 0;
+  // Time one candidate on a batch that fills the GPU: nb batch bits chosen
+  // so the step has at least 4096 blocks, at most 8 GiB of operands.
+  auto time_tile = [&](const TileKey& key, int nb, const qgm_tile& t, float& ms) -> qgm_status {
+    qgm_contraction* c = nullptr;
+    qgm_status s2 = qgm_contraction_create(key.prec, nb, key.ni, key.nj, key.nk, 0, &t, &c);
+    if (s2) return s2;
+    const size_t need = (size_t)(c->ea + c->eb + c->ec) * 64 * 8;
+    if (need > mem_bytes) {
+      if (mem) (void)hipFree(mem);
+      mem = nullptr;
+      mem_bytes = 0;
+      if (hipMalloc(&mem, need) != hipSuccess) {
+        qgm_contraction_free(c);
+        return fail(QGM_E_HIP, "hipMalloc of tuning operands failed");
+      }
+      mem_bytes = need;
+      if (hipMemsetAsync(mem, 0x3c, need, stream) != hipSuccess) {
+        qgm_contraction_free(c);
+        return fail(QGM_E_HIP, "hipMemsetAsync failed");
+      }
+    }
+    for (int r = 0; r < 7 && !s2; ++r) {
+      if (r == 2 && hipEventRecord(e0, stream) != hipSuccess) s2 = fail(QGM_E_HIP, "hipEventRecord failed");
+      if (!s2) s2 = qgm_contraction_run(c, mem, 1, stream);
+    }
+    if (!s2 && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      s2 = fail(QGM_E_HIP, "event timing failed");
+    qgm_contraction_free(c);
+    return s2;
+  };
+  for (auto& oe : order) {
+    if (st || covered >= 0.99 * total) break;
+    covered += -oe.first;
+    const TileKey key = oe.second;
+    const int nbi = key.ni >= 5 ? key.ni - 5 : 0, nbj = key.nj >= 5 ? key.nj - 5 : 0;
+    int nb = std::max(0, 12 - nbi - nbj);
+    while (nb > 0 && std::ldexp(64.0 * 8.0, nb) * (std::ldexp(1.0, key.ni + key.nk) + std::ldexp(1.0, key.nk + key.nj) +
+                                                 std::ldexp(1.0, key.ni + key.nj)) > 8.0 * (1ull << 30))
+      --nb;
+    // stage 1: block layout x k steps per stage; stage 2: ring budget x band
+    std::vector<int> pers = key.prec == QGM_BF16X3 ? std::vector<int>{2, 4} : std::vector<int>{1, 2, 4};
+    qgm_tile best{2, 53248, 2, 0};
+    float best_ms = 0;
+    bool have = false;
+    for (int layout = 0; layout < 4 && !st; ++layout)
+      for (int per : pers) {
+        if (per > (1 << key.nk)) continue;
+        qgm_tile t{per, 53248, 2, layout};
+        float ms = 0;
+        st = time_tile(key, nb, t, ms);
+        if (st) break;
+        if (!have || ms < best_ms) best = t, best_ms = ms, have = true;
+      }
+    for (int lds : {53248, 81920, 114688})
+      for (int jb = 0; jb <= 3 && !st; ++jb) {
+        qgm_tile t{best.per, lds, jb, best.layout};
+        if (lds == 53248 && jb == 2) continue;  // timed in stage 1
+        float ms = 0;
+        st = time_tile(key, nb, t, ms);
+        if (!st && ms < best_ms) best = t, best_ms = ms;
+      }
+    if (st) break;
+    table[key] = MfmaTile{best.per, best.lds_budget, best.jband, best.layout};
+    ++*n_tuned;
+  }
+  if (mem) (void)hipFree(mem);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  std::string werr;
+  if (!write_tile_table(table_path, table, werr)) return fail(QGM_E_ARG, werr);
+  return QGM_OK;
+  GUARD_END
+}
 
 }  // extern "C"

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <functional>
 #include <sstream>
 #include <string>
@@ -57,13 +58,15 @@ std::string lit(double v) {
 // 4 j blocks, so the operand panels a band shares stay in that XCD's L2.
 // Returns false when the step does not qualify; lds_bytes receives the LDS
 // the step needs.
-bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
-                    const std::vector<const int32_t*>& rec, int& lds_bytes) {
+// Output bits of a two-operand item step split into batch (both operands),
+// row (A only) and column (B only) bits; false unless the step is a
+// complex64 / BF16x3 two-operand contraction of the matrix-core shape.
+static bool mfma_bits(int kind, int r, int ns, int prec, const std::vector<const int32_t*>& rec, std::vector<int>& bb,
+                      std::vector<int>& bi, std::vector<int>& bj) {
   if (kind != ST_ELIM || rec.size() != 2 || rec[0][0] != WOP_ITEM || rec[1][0] != WOP_ITEM) return false;
   if (ns < 1 || (prec != 1 && prec != 2)) return false;
   const int32_t* A = rec[0];
   const int32_t* B = rec[1];
-  std::vector<int> bb, bi, bj;
   for (int j = 0; j < r; ++j) {
     const bool a = A[16 + j] != 0, b = B[16 + j] != 0;
     if (a && b) bb.push_back(j);
@@ -73,23 +76,63 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   }
   for (int j = 0; j < ns; ++j)
     if (A[48 + j] == 0 || B[48 + j] == 0) return false;
-  if (bi.size() < 4 || bj.size() < 4) return false;
-  const int WI = bi.size() >= 5 ? 2 : 1, WJ = bj.size() >= 5 ? 2 : 1, WQ = 4 / (WI * WJ);
+  return bi.size() >= 4 && bj.size() >= 4;
+}
+
+bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni, int& nj, int& nk) {
+  const int32_t* sr = &wide.steps[8 * si];
+  if (sr[7]) return false;
+  std::vector<const int32_t*> rec(sr[4]);
+  for (int i = 0; i < sr[4]; ++i) rec[i] = &wide.ops[(size_t)(sr[6] + i) * kWideOpInts];
+  std::vector<int> bb, bi, bj;
+  if (!mfma_bits(sr[0], sr[2], sr[3], prec, rec, bb, bi, bj)) return false;
+  nb = (int)bb.size();
+  ni = (int)bi.size();
+  nj = (int)bj.size();
+  nk = sr[3];
+  return true;
+}
+
+bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
+                    const std::vector<const int32_t*>& rec, int& lds_bytes, const TileTable* tiles) {
+  std::vector<int> bb, bi, bj;
+  if (!mfma_bits(kind, r, ns, prec, rec, bb, bi, bj)) return false;
+  const int32_t* A = rec[0];
+  const int32_t* B = rec[1];
+  // Tile parameters: a tuned table entry for this shape, else the built-in
+  // choice (2 x 2 tiles of 16 items when both sides have 5 bits, two k per
+  // unit, a ring of at most 52 KiB, bands of four j blocks).
+  MfmaTile tp;
+  if (tiles) {
+    auto it = tiles->find(TileKey{prec, (int)bi.size(), (int)bj.size(), ns});
+    if (it != tiles->end()) tp = it->second;
+  }
+  int WI = bi.size() >= 5 ? 2 : 1, WJ = bj.size() >= 5 ? 2 : 1;
+  if (tp.layout == 1) WI = WJ = 1;                                   // four item groups
+  else if (tp.layout == 2 && bi.size() >= 5) WI = 2, WJ = 1;         // two i tiles x two item groups
+  else if (tp.layout == 3 && bj.size() >= 5) WI = 1, WJ = 2;         // two j tiles x two item groups
+  const int WQ = 4 / (WI * WJ);
   const int li = WI == 2 ? 5 : 4, lj = WJ == 2 ? 5 : 4;  // i / j bits inside a block
   const int nbi = (int)bi.size() - li, nbj = (int)bj.size() - lj, nbb = (int)bb.size();
   const int nqg = 4 / WQ;  // item groups of 16 * WQ items
   const int grid_bits = nbj + nbi + nbb + (nqg == 4 ? 2 : nqg == 2 ? 1 : 0);
   const unsigned long long nb = 1ull << grid_bits;
   const int nk = 1 << ns;
-  const int per = 2;                                  // k steps per unit (one barrier each)
+  // k steps per unit (one barrier each); BF16x3 pairs the k steps
+  int per = std::min(nk, std::max(prec == 2 ? 2 : 1, tp.per));
+  if (prec == 2 && per % 2) per = 2;
   const int nu = nk / per;                            // units
   const int a_bytes = 16 * WI * 16 * WQ * 8;          // A rows of one k
   const int b_bytes = 16 * WJ * 16 * WQ * 8;
   const int stage = per * (a_bytes + b_bytes);
-  const int P = std::max(2, std::min(8, 53248 / stage));  // three blocks per CU
-  lds_bytes = P * stage;
   const int nA = a_bytes / 1024, nB = b_bytes / 1024;  // 1 KiB copies per k
   const int n_ins = per * (nA + nB), per_wave = n_ins / 4;
+  // ring depth: what the LDS budget holds, 2..8 stages, and at most what the
+  // 6-bit load counter can wait for ((P - 2) copies per wave in flight)
+  int P = std::max(2, std::min(8, tp.lds_budget / stage));
+  P = std::min(P, 2 + 63 / std::max(1, per_wave));
+  if (P * stage > 163840) return false;
+  lds_bytes = P * stage;
   // block ranges start at multiples of 8 so that blk & 7 is the XCD
   k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
@@ -103,9 +146,9 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   k.steps.push_back(si);
   k.mfma_steps += 1;
   k.mfma_flops += 8.0 * (double)(1ull << (r + ns));
-  // tile index bits, fastest first: j blocks inside a band of up to 4, i
-  // blocks, the remaining j bits (bands), b bits, item groups
-  const int jband = std::min(nbj, 2);
+  // tile index bits, fastest first: j blocks inside a band of up to
+  // 2^jband, i blocks, the remaining j bits (bands), b bits, item groups
+  const int jband = std::min(nbj, tp.jband);
   std::vector<std::pair<int, int>> bits;  // (kind 0 = j, 1 = i, 2 = b; out bit)
   for (int t = 0; t < jband; ++t) bits.push_back({0, bj[lj + t]});
   for (int t = 0; t < nbi; ++t) bits.push_back({1, bi[li + t]});
@@ -236,30 +279,38 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
         }
     }
   } else {
-    // two k steps per unit: 12 terms for Cr and 12 for Ci in three 4-slot
+    // k steps in pairs: 12 terms for Cr and 12 for Ci in three 4-slot
     // bfloat16 operands each; the A slots are shared by Cr and Ci.
     //   A: (rh rh rl ih | ih il) per k;  B for Cr: (rh rl rh -ih | -il -ih);
     //   B for Ci: (ih il ih rh | rl rh)   (r = real, i = imaginary part)
-    for (int g = 0; g < 4; ++g) {
-      const std::string G = std::to_string(g);
-      o << "    s16x4 A" << G << "_0, A" << G << "_1, A" << G << "_2;\n"
-        << "    bsplit(a0_" << G << ", a1_" << G << ", A" << G << "_0, A" << G << "_1, A" << G << "_2);\n"
-        << "    s16x4 R" << G << "_0, R" << G << "_1, R" << G << "_2, I" << G << "_0, I" << G << "_1, I" << G << "_2;\n"
-        << "    bsplitb(b0_" << G << ", b1_" << G << ", R" << G << "_0, R" << G << "_1, R" << G << "_2, I" << G << "_0, I"
-        << G << "_1, I" << G << "_2);\n";
-    }
-    for (int rg = 0; rg < 4; ++rg)
-      for (int cg = 0; cg < 4; ++cg) {
-        const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
-        const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
-        for (int t = 0; t < 3; ++t) {
-          const std::string a = "A" + std::to_string(rg) + "_" + std::to_string(t);
-          const std::string rr = "R" + std::to_string(cg) + "_" + std::to_string(t);
-          const std::string ii = "I" + std::to_string(cg) + "_" + std::to_string(t);
-          o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << rr << ", " << cr << ", 0, 0, 0);\n"
-            << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << ii << ", " << ci << ", 0, 0, 0);\n";
-        }
+    for (int hp = 0; hp < per / 2; ++hp) {
+      const std::string h0 = std::to_string(2 * hp), h1 = std::to_string(2 * hp + 1);
+      for (int g = 0; g < 4; ++g) {
+        const std::string G = std::to_string(g);
+        const std::string S = std::to_string(hp) + "_" + G;  // pair, group
+        o << "    s16x4 A" << S << "_0, A" << S << "_1, A" << S << "_2;\n"
+          << "    bsplit(a" << h0 << "_" << G << ", a" << h1 << "_" << G << ", A" << S << "_0, A" << S << "_1, A" << S
+          << "_2);\n"
+          << "    s16x4 R" << S << "_0, R" << S << "_1, R" << S << "_2, I" << S << "_0, I" << S << "_1, I" << S << "_2;\n"
+          << "    bsplitb(b" << h0 << "_" << G << ", b" << h1 << "_" << G << ", R" << S << "_0, R" << S << "_1, R" << S
+          << "_2, I" << S << "_0, I" << S << "_1, I" << S << "_2);\n";
       }
+      for (int rg = 0; rg < 4; ++rg)
+        for (int cg = 0; cg < 4; ++cg) {
+          const std::string cr = "cr" + std::to_string(rg) + "_" + std::to_string(cg);
+          const std::string ci = "ci" + std::to_string(rg) + "_" + std::to_string(cg);
+          for (int t = 0; t < 3; ++t) {
+            const std::string T = "_" + std::to_string(t);
+            const std::string a = "A" + std::to_string(hp) + "_" + std::to_string(rg) + T;
+            const std::string rr = "R" + std::to_string(hp) + "_" + std::to_string(cg) + T;
+            const std::string ii = "I" + std::to_string(hp) + "_" + std::to_string(cg) + T;
+            o << "    " << cr << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << rr << ", " << cr
+              << ", 0, 0, 0);\n"
+              << "    " << ci << " = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(" << a << ", " << ii << ", " << ci
+              << ", 0, 0, 0);\n";
+          }
+        }
+    }
   }
   o << "  }\n"
     << "  __builtin_amdgcn_s_waitcnt(" << ((7 << 4) | (15 << 8)) << ");  // no copy left in flight\n";
@@ -281,8 +332,51 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   return true;
 }
 
+bool read_tile_table(const std::string& path, TileTable& t, std::string& err) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) {
+    err = "cannot open tile table " + path;
+    return false;
+  }
+  char line[512];
+  int ln = 0;
+  bool ok = true;
+  while (ok && std::fgets(line, sizeof(line), f)) {
+    ++ln;
+    char* hash = std::strchr(line, '#');
+    if (hash) *hash = 0;
+    int v[8];
+    int n = std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
+    if (n <= 0) continue;  // blank or comment
+    if (n != 8 || v[0] < 0 || v[0] > 2 || v[1] < 4 || v[2] < 4 || v[3] < 1 || v[3] > 16 || v[4] < 1 || v[4] > 16 ||
+        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 3) {
+      err = "tile table " + path + " line " + std::to_string(ln) + ": expected prec ni nj nk per lds_budget jband layout";
+      ok = false;
+      break;
+    }
+    t[TileKey{v[0], v[1], v[2], v[3]}] = MfmaTile{v[4], v[5], v[6], v[7]};
+  }
+  std::fclose(f);
+  return ok;
+}
+
+bool write_tile_table(const std::string& path, const TileTable& t, std::string& err) {
+  FILE* f = std::fopen(path.c_str(), "w");
+  if (!f) {
+    err = "cannot write tile table " + path;
+    return false;
+  }
+  std::fprintf(f, "# qgm matrix-core tile table: prec ni nj nk per lds_budget jband layout\n");
+  for (const auto& e : t)
+    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", e.first.prec, e.first.ni, e.first.nj, e.first.nk, e.second.per,
+                 e.second.lds_budget, e.second.jband, e.second.layout);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) err = "write failed: " + path;
+  return ok;
+}
+
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
-                                 std::vector<WideKernel>& kernels, bool mfma) {
+                                 std::vector<WideKernel>& kernels, bool mfma, const TileTable* tiles) {
   kernels.clear();
   std::ostringstream o;
   o << "typedef " << (prec == 0 ? "double" : "float") << " R;\n"
@@ -426,7 +520,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
         k.bytes += 8.0 * elems;
       }
       int lds_bytes = 0;
-      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes)) {
+      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes, tiles)) {
         level_lds[lev] = std::max(level_lds[lev], lds_bytes);
         continue;
       }

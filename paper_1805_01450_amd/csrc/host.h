@@ -3,6 +3,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -153,8 +154,11 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
 // 4 row and 4 column variables and one summed variable: a batch of complex
 // GEMMs per item, the shape the wide engine runs on the matrix cores.
 bool matrix_core_shape(const Step& st);
+// checkpoint_every = n > 0 (gradient programs): the reverse pass keeps every
+// n-th forward elimination output and recomputes the others it needs.
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false);
+                     Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false,
+                     int checkpoint_every = 0);
 
 // ------------------------------------------------------------ wide engine
 // Descriptors for plans whose tensors are too large for registers or LDS.
@@ -188,8 +192,36 @@ struct WideKernel {
   double flops = 0.0;       // flops per item of all its steps
   double bytes = 0.0;       // algorithmic bytes per item of all its steps (8 B per element)
 };
+// Tile parameters of a matrix-core step (two-operand contraction with ni
+// row, nj column and nk summed bits).  per: k steps per LDS stage (one block
+// barrier each); lds_budget: bytes of LDS the operand ring may take (2..8
+// stages); jband: log2 of the j blocks that run next to each other on one
+// XCD; layout: 0 = built-in (2 x 2 wavefront tiles when both sides have 5
+// bits), 1 = four 16-item groups per block, 2 = two i tiles x two item
+// groups, 3 = two j tiles x two item groups (2 and 3 need 5 bits on that
+// side, else the built-in choice is kept).
+struct MfmaTile {
+  int per = 2;
+  int lds_budget = 53248;
+  int jband = 2;
+  int layout = 0;
+};
+struct TileKey {
+  int prec, ni, nj, nk;
+  bool operator<(const TileKey& o) const {
+    return prec != o.prec ? prec < o.prec : ni != o.ni ? ni < o.ni : nj != o.nj ? nj < o.nj : nk < o.nk;
+  }
+};
+using TileTable = std::map<TileKey, MfmaTile>;
+// Text form, one entry per line: "prec ni nj nk per lds_budget jband layout";
+// '#' starts a comment.  read: false (with err) on a malformed line.
+bool read_tile_table(const std::string& path, TileTable& t, std::string& err);
+// (nb, ni, nj, nk) of wide step si when it runs on the matrix cores in
+// precision prec (1 = complex64, 2 = BF16x3).
+bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni, int& nj, int& nk);
+bool write_tile_table(const std::string& path, const TileTable& t, std::string& err);
 std::string generate_wide_source(const Program& prog, const WideProgram& wide, int prec,
-                                 std::vector<WideKernel>& kernels, bool mfma);
+                                 std::vector<WideKernel>& kernels, bool mfma, const TileTable* tiles = nullptr);
 
 // Straight-line HIP source (kernel "qgm_chain") for the item steps of `prog`;
 // prec 0 = complex128, 1 = complex64.

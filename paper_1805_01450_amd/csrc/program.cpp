@@ -155,7 +155,8 @@ bool matrix_core_shape(const Step& st) {
 }
 
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
-                     Program& prog, std::string& err, int& code, bool gradient, bool combine_consts) {
+                     Program& prog, std::string& err, int& code, bool gradient, bool combine_consts,
+                     int checkpoint_every) {
   prog = Program();
   if (!validate_plan(net, sliced, order, err, code)) return false;
   const int nvars = (int)net.vars.size();
@@ -362,11 +363,11 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   // (repeated while the remaining sum is still large).
   constexpr int kSplitSum = 8, kKeepSum = 6, kSplitRank = 14;
   constexpr int kMaxCombinedRank = 20;  // largest constant tensor made by combining constant factors
-  std::function<int(int, const std::vector<int>&, const std::vector<int>&, const std::vector<int>&, bool, int, int,
-                    int)>
-      emit;
-  emit = [&](int kind, const std::vector<int>& in, const std::vector<int>& out_vars, const std::vector<int>& sum_vars,
-             bool make_const, int grad_slot, int extra_const, int n_extra) -> int {
+  // (the lists are taken by value: callers pass the variables of a tensor in
+  // T, and emit_one appends to T, which may move its elements)
+  std::function<int(int, std::vector<int>, std::vector<int>, std::vector<int>, bool, int, int, int)> emit;
+  emit = [&](int kind, std::vector<int> in, std::vector<int> out_vars, std::vector<int> sum_vars, bool make_const,
+             int grad_slot, int extra_const, int n_extra) -> int {
     const int ns = (int)sum_vars.size(), r = (int)out_vars.size();
     if (ns <= kSplitSum || in.empty()) return emit_one(kind, in, out_vars, sum_vars, make_const, grad_slot,
                                                        extra_const, n_extra);
@@ -551,6 +552,40 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
 
   // ---- reverse mode (gradient programs)
   if (gradient) {
+    // Checkpointing: with checkpoint_every = n > 0 the forward elimination
+    // outputs are cut into segments of n in creation order.  A forward
+    // output stays in item memory for the reverse pass only when its
+    // consumer lies in another segment (or it is an operand of the final
+    // product): a checkpoint.  Any other forward value the reverse pass
+    // needs is recomputed from checkpoints and values of its own segment,
+    // once, by the same step as in the forward pass (same operands in the
+    // same order, so the same values); its memory is free between its last
+    // forward use and the reverse pass over its segment.  Every forward
+    // tensor has one consumer, so the recomputation costs at most one more
+    // forward pass.
+    std::vector<int> fwd_pos(T.size(), -1), consumer_pos(T.size(), -1);
+    for (size_t k = 0; k < fwd_steps.size(); ++k) fwd_pos[fwd_steps[k]] = (int)k;
+    for (size_t k = 0; k < fwd_steps.size(); ++k)
+      for (int x : T[fwd_steps[k]].inputs) consumer_pos[x] = (int)k;
+    std::vector<char> in_rest(T.size(), 0);
+    for (int t : rest) in_rest[t] = 1;
+    auto kept = [&](int t) {
+      if (checkpoint_every <= 0 || t >= (int)fwd_pos.size() || fwd_pos[t] < 0 || in_rest[t] || consumer_pos[t] < 0)
+        return true;
+      return fwd_pos[t] / checkpoint_every != consumer_pos[t] / checkpoint_every;
+    };
+    std::map<int, int> recomputed;
+    std::function<int(int)> value = [&](int t) -> int {
+      if (kept(t)) return t;
+      auto it = recomputed.find(t);
+      if (it != recomputed.end()) return it->second;
+      const Step st = prog.steps[T[t].producer];
+      std::vector<int> in;
+      for (int x : T[t].inputs) in.push_back(value(x));
+      const int id = emit_one(ST_ELIM, in, st.out_vars, st.sum_vars, false, -1, 0, 0);
+      recomputed[t] = id;
+      return id;
+    };
     std::vector<int> adj(T.size(), -1);
     auto grad_out = [&](int t) {
       // d alpha / d theta contribution of RZ factor f: sum_u adj(u) * D_f(u)
@@ -587,7 +622,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
         if (!T[t].grad) continue;
         std::vector<int> ops{adj[o]};
         for (size_t b = 0; b < ins.size(); ++b)
-          if (b != a) ops.push_back(ins[b]);
+          if (b != a) ops.push_back(value(ins[b]));
         std::vector<int> sum;
         for (int u : full)
           if (std::find(T[t].vars.begin(), T[t].vars.end(), u) == T[t].vars.end()) sum.push_back(u);

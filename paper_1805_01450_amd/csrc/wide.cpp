@@ -57,7 +57,15 @@ bool encode_wide(const Program& prog, WideProgram& wide, std::string& err) {
         }
         auto ps = std::find(st.sum_vars.begin(), st.sum_vars.end(), u);
         if (ps == st.sum_vars.end()) {
-          err = "internal: operand variable neither kept nor summed";
+          err = "internal: operand variable " + std::to_string(u) + " of a step (kind " + std::to_string(st.kind) +
+                ", rank " + std::to_string(st.r) + ", summed " + std::to_string(st.ns) + ", operands " +
+                std::to_string(st.m) + ") neither kept nor summed";
+          for (int v2 : st.out_vars) err += " o" + std::to_string(v2);
+          for (int v2 : st.sum_vars) err += " s" + std::to_string(v2);
+          for (const Operand& o2 : st.opnd) {
+            err += " |";
+            for (int v2 : o2.vars) err += " " + std::to_string(v2);
+          }
           return false;
         }
         rec[48 + (ps - st.sum_vars.begin())] = stride_of[j];

@@ -117,3 +117,61 @@ def test_contraction_rejects_bad_shapes():
     with pytest.raises(q.QgmError) as e:
         q.Contraction(7, 1, 4, 4, 1)
     assert e.value.status == -7
+
+
+TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0), (4, 81920, 1, 1),
+         (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1)]
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
+def test_tile_variants_match_builtin_tile(tile, prec):
+    """Every tile parameter set keeps the k order of each output's sum, so the
+    result equals the built-in tile's bit for bit (and meets the bound)."""
+    import torch
+    if prec == q.QGM_BF16X3 and tile[0] == 1:
+        tile = (2,) + tile[1:]
+    shape = (1, 6, 7, 4)
+    c0, got0, want, mag = _run(prec, *shape, 2, False, seed=11)
+    c1 = q.Contraction(prec, *shape, tile=tile)
+    assert c1.matrix_cores
+    # same operands through the variant
+    nb, ni, nj, nk = shape
+    ea, eb = 1 << (nb + ni + nk), 1 << (nb + nk + nj)
+    cdt = np.complex64
+    rng = np.random.default_rng(11)
+    items = 128
+    A = (rng.standard_normal((items, 1 << nb, 1 << nk, 1 << ni))
+         + 1j * rng.standard_normal((items, 1 << nb, 1 << nk, 1 << ni))).astype(cdt)
+    B = (rng.standard_normal((items, 1 << nb, 1 << nj, 1 << nk))
+         + 1j * rng.standard_normal((items, 1 << nb, 1 << nj, 1 << nk))).astype(cdt)
+    mem = np.zeros((2, c1.elems, 64), dtype=cdt)
+    mem[:, :ea, :] = A.reshape(2, 64, ea).transpose(0, 2, 1)
+    mem[:, ea:ea + eb, :] = B.reshape(2, 64, eb).transpose(0, 2, 1)
+    d_mem = torch.from_numpy(mem).to("cuda")
+    note("tile", tile, "prec", prec)
+    c1.run(d_mem, 2)
+    torch.cuda.synchronize()
+    got1 = d_mem.cpu().numpy()[:, ea + eb:, :].transpose(0, 2, 1).reshape(items, 1 << nb, 1 << nj, 1 << ni)
+    assert np.array_equal(got1, got0)
+
+
+def test_plan_tile_tuner_and_table(tmp_path):
+    """qgm_plan_tune_tiles on the 7x7x30 plan writes a table; a plan created
+    with it gives the default plan's amplitudes bit for bit (tiles change
+    neither the k order of a sum nor which products are formed)."""
+    import json
+    import os
+    from workload import generate_circuit, random_bitstrings
+    rec = json.load(open(os.path.join(os.path.dirname(q.__file__), "plans", "7x7x30.json")))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    bits = random_bitstrings(49, 2, 77)
+    for prec in (q.QGM_C64, q.QGM_BF16X3):
+        p = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE)
+        table = str(tmp_path / "tiles.txt")
+        n = q.qgm_plan_tune_tiles(p.h, table)
+        note("tuned shapes", n, open(table).read())
+        assert n >= 1
+        t = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE, tile_table_path=table)
+        assert np.array_equal(t.amplitudes(bits), p.amplitudes(bits))

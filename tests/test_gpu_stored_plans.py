@@ -207,3 +207,26 @@ def test_config4_whole_gradient_vs_oracle(config4_rz):
         note("7x7x30 whole gradient prec", prec, "max err", err.max(), "amp err", abs(amp - alpha) / abs(alpha))
         assert abs(amp - alpha) <= (C128_TOL if prec == q.QGM_C128 else C64_TOL) * abs(alpha)
         assert err.max() <= tol
+
+
+@pytest.mark.parametrize("ck", [2, 4, 8])
+def test_config4_checkpointed_gradient_vs_oracle(config4_rz, ck):
+    """checkpoint_every = n keeps only the forward tensors consumed in another
+    segment of n eliminations and recomputes the rest by the same steps: the
+    gradient equals the fully stored one (same operations on the same values)
+    and the oracle's, with about half the peak item memory."""
+    gold, rec, circ, th, x = config4_rz
+    which = gold["grad_which"]
+    want = np.array([complex(*v) for v in gold["grad_full"]])
+    alpha = complex(*gold["alpha"])
+    g0 = q.Plan(circ, rec["sliced"], rec["order"], gradient=True)
+    g = q.Plan(circ, rec["sliced"], rec["order"], gradient=True, checkpoint_every=ck)
+    note("checkpoint_every", ck, "item elems", g.stats()["item_elems"], "vs", g0.stats()["item_elems"])
+    assert g.stats()["item_elems"] < g0.stats()["item_elems"]
+    a0, d0 = g0.amplitude_grad(x, th)
+    a, d = g.amplitude_grad(x, th)
+    scale = abs(alpha)
+    note("max |checkpointed - stored| / |alpha|", np.max(np.abs(d - d0)) / scale)
+    assert a == a0
+    assert np.max(np.abs(d - d0)) <= 1e-14 * scale
+    assert np.max(np.abs(d[which] - want)) <= 1e-11 * scale

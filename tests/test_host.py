@@ -355,3 +355,73 @@ def test_persistent_generated_kernels_compile():
     with pytest.raises(q.QgmError) as e:
         q.Plan(c, sl, order, persistent=2)
     assert e.value.status == -1
+
+
+def test_tile_table_round_trip_and_errors(tmp_path, monkeypatch):
+    """A plan reads the tile table named by opts.tile_table_path; entries
+    change the generated matrix-core steps; a malformed table is refused."""
+    import glob
+    import json
+    import os
+    rec = json.load(open(os.path.join(ROOT, "paper_1805_01450_amd", "plans", "7x7x30.json")))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path / "a"))
+    os.makedirs(tmp_path / "a")
+    q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE)
+    default = open(glob.glob(str(tmp_path / "a" / "qgm_wide_*.hip"))[0]).read()
+    shapes = set(re.findall(r"\(matrix cores\) b \d+ i (\d+) j (\d+) k (\d+)", default))
+    assert shapes
+    table = tmp_path / "tiles.txt"
+    lines = ["# test table"] + [f"1 {i} {j} {k} 4 81920 1 1" for i, j, k in sorted(shapes)]
+    table.write_text("\n".join(lines) + "\n")
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path / "b"))
+    os.makedirs(tmp_path / "b")
+    p = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, tile_table_path=str(table))
+    tuned = open(glob.glob(str(tmp_path / "b" / "qgm_wide_*.hip"))[0]).read()
+    assert tuned != default and p.stats()["mfma_steps"] >= 1
+    assert "const int wi = 0, wj = 0, wq = w4;" in tuned  # layout 1: four item groups
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 5 5 3 3 81920 1 1\n")  # 3 k per stage is not a power of two
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, tile_table_path=str(bad))
+    assert e.value.status == -1 and "line 1" in str(e.value)
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE,
+               tile_table_path=str(tmp_path / "missing.txt"))
+    assert e.value.status == -1
+
+
+def test_checkpointed_gradient_plans():
+    """checkpoint_every = n: the 7x7x30 RZ gradient plan holds fewer item
+    tensors at its peak, recomputes at most one more forward pass, and still
+    has one GRAD step per angle; the 8x8x40 RZ gradient plan (whose reverse
+    pass once tripped over a moved tensor list) compiles and shrinks too."""
+    import json
+    import os
+    rec = json.load(open(os.path.join(ROOT, "paper_1805_01450_amd", "plans", "7x7x30.json")))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"], rz=True))
+    fwd = q.Plan(c, rec["sliced"], rec["order"], engine=q.QGM_ENGINE_WIDE).stats()
+    full = q.Plan(c, rec["sliced"], rec["order"], gradient=True, engine=q.QGM_ENGINE_WIDE).stats()
+    ck = q.Plan(c, rec["sliced"], rec["order"], gradient=True, checkpoint_every=4, engine=q.QGM_ENGINE_WIDE).stats()
+    assert ck["item_elems"] <= 0.6 * full["item_elems"]
+    assert full["flops_item"] < ck["flops_item"] <= full["flops_item"] + 2 * fwd["flops_item"]
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, rec["sliced"], rec["order"], checkpoint_every=4)  # not a gradient plan
+    assert e.value.status == -1
+    with pytest.raises(q.QgmError) as e:
+        q.Plan(c, rec["sliced"], rec["order"], gradient=True, checkpoint_every=-1)
+    assert e.value.status == -1
+
+
+def test_8x8x40_gradient_plan_compiles(monkeypatch):
+    import json
+    import os
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")  # skip generating kernels: the program is what is checked
+    rec = json.load(open(os.path.join(ROOT, "paper_1805_01450_amd", "plans", "8x8x40.json")))
+    c = q.Circuit(generate_circuit(8, 40, 0, rz=True))
+    full = q.Plan(c, rec["sliced"], rec["order"], gradient=True, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
+    ck = q.Plan(c, rec["sliced"], rec["order"], gradient=True, prec=q.QGM_C64, checkpoint_every=8,
+                engine=q.QGM_ENGINE_WIDE).stats()
+    assert ck["item_elems"] <= 0.5 * full["item_elems"]

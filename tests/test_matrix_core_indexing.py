@@ -193,3 +193,24 @@ def test_matrix_core_step_indexing_block_shapes(shape, prec, tmp_path, monkeypat
     assert n == 1
     if shape == (2, 5, 4, 2):
         assert shapes == {SHAPE_212}
+
+
+TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0), (4, 81920, 1, 1),
+         (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1)]
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("shape", [(2, 5, 5, 3), (1, 6, 7, 4), (3, 4, 6, 2)])
+@pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
+def test_matrix_core_step_indexing_tile_variants(tile, shape, prec, tmp_path, monkeypatch):
+    """Every tile parameter set the autotuner may choose (k steps per stage,
+    ring budget, band, block layout) keeps copies and reads in bounds, each
+    lane on its own item and each summed row read once."""
+    if prec == q.QGM_BF16X3 and tile[0] == 1:
+        tile = (2,) + tile[1:]
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    con = q.Contraction(prec, *shape, tile=tile)
+    assert con.matrix_cores
+    src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+    n, _ = check_source(src, con.elems, max_blocks=16)
+    assert n == 1
