@@ -38,6 +38,9 @@ PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X published dense FP64 matrix-core peak
 PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")  # rocprofv3 HBM byte counters, summarised
 GOLDEN_SLICES = os.path.join(ROOT, "tests", "golden", "stored_plan_slices.json")
+# matrix-core tile table written by paper_1805_01450_amd/plans/make_tiles.py
+# (qgm_plan_tune_tiles on this GPU model)
+TILE_TABLE = os.path.join(ROOT, "paper_1805_01450_amd", "plans", "tiles_mi355x.txt")
 
 # name: (grid n, depth, circuit seed, bitstrings, k, slices timed per bitstring (None = all 2^k),
 #        stored plan name or None (planned here), default steps, default warm-up runs)
@@ -307,6 +310,8 @@ def main():
                     help="wide engine: item memory per pass in GiB (0 = the library default, 96 GiB)")
     ap.add_argument("--precisions", default="c64,bf16x3,c128",
                     help="comma-separated legs; the first is the headline")
+    ap.add_argument("--tiles", default=None,
+                    help="matrix-core tile table (default: the stored tuned table when present; 'none' = built-in)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 5x5x20 extra keys")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -376,11 +381,14 @@ def main():
            "generated": q.QGM_ENGINE_GENERATED}[args.engine]
     precs = {"c64": q.QGM_C64, "bf16x3": q.QGM_BF16X3, "c128": q.QGM_C128}
     legs = [p for p in args.precisions.split(",") if p]
+    tiles = args.tiles if args.tiles is not None else (TILE_TABLE if os.path.exists(TILE_TABLE) else "none")
+    tile_path = None if tiles == "none" else tiles
     ref_slices = golden_slices(plan_name) if (plan_name and n_bs == 1) else {}
     results = {}
     for name in legs:
         plan = q.Plan(circ, sliced, order, prec=precs[name], profile=True, engine=eng,
-                      vector_only=args.vector_only, workspace_cap=int(args.workspace_gib * (1 << 30)))
+                      vector_only=args.vector_only, workspace_cap=int(args.workspace_gib * (1 << 30)),
+                      tile_table_path=tile_path)
         st = plan.stats()
         waves = plan.autotune(n_bs, n_s) if st["engine"] == q.QGM_ENGINE_GENERATED else 1
         r = timed(q, torch, plan, d_bits, d_part, n_s, steps, warmup, stream)
@@ -448,6 +456,7 @@ def main():
                                 + (f"the whole amplitude: all {n_s} slices per step" if n_run is None else
                                    f"{n_s} of the {1 << k} slices per step")),
                    "plan": plan_source, "plan_s": round(t_plan, 2), "sliced_vars": sliced,
+                   "matrix_core_tiles": os.path.relpath(tile_path, ROOT) if tile_path else "built-in",
                    "compile_s": round(st["compile_s"], 1), "max_rank": st["max_rank"],
                    "flops_per_slice": st["flops_item"], "bytes_per_slice": st["bytes_item"],
                    "parallelism": "single GPU"},
