@@ -287,8 +287,22 @@ def extra_5x5x20(q, torch, stream):
     n_items = n_bs << k
     k_ms = min(r["ms_chain"], r["gpu_ms_step"])
     tf = st["flops_item"] * n_items / (k_ms * 1e-3) / 1e12
+    # the same batch with 4 output variables left open: 16 amplitudes per
+    # (bitstring, slice) contraction
+    open_q = [0, 6, 12, 18]
+    po = q.Plan(circ, sliced, order, prec=q.QGM_C64, profile=True, open_qubits=open_q)
+    po.autotune(n_bs, 1 << k)
+    d_part_o = torch.empty((n_bs << len(open_q), 4), dtype=torch.float64, device="cuda")
+    ro = timed(q, torch, po, d_bits, d_part_o, 1 << k, steps, warmup, stream)
+    amps_closed = n_bs / (r["wall"] / steps)
+    amps_open = (n_bs << len(open_q)) / (ro["wall"] / steps)
     return {"workload": f"5x5 grid depth 20 seed 0, 64 random bitstrings x 2^6 slices = {n_items} slice "
                         f"contractions per step (deterministic latency plan)",
+            "amplitudes_per_s": amps_closed,
+            "open_outputs": {"open_qubits": open_q, "amplitudes_per_step": n_bs << len(open_q),
+                             "amplitudes_per_s": amps_open, "ms_per_step": 1e3 * ro["wall"] / steps,
+                             "engine": {1: "interpreter", 2: "generated", 3: "wide"}[po.stats()["engine"]],
+                             "speedup_per_amplitude": amps_open / amps_closed},
             "value": n_items / (r["wall"] / steps), "unit": "slice contractions/s", "steps": steps,
             "ms_per_step": 1e3 * r["wall"] / steps, "engine": "generated", "waves_per_block": waves,
             "kernel": "qgm_chain (generated)", "kernel_ms": k_ms, "achieved_tflops_algorithmic": tf,

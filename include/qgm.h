@@ -90,12 +90,23 @@ typedef struct {
   int32_t deterministic;     /* 0 or 1.  Every engine already returns bit-identical results for
                                 identical inputs (fixed slice-sum order, no atomics in any
                                 sum); 1 documents the caller's reliance on it */
-  int32_t reserved0;
+  int32_t n_open;            /* open outputs: the number of entries of open_qubits (0..10) */
   const char* tile_table_path; /* WIDE matrix-core steps: a tile table written by
                                 qgm_plan_tune_tiles (read at plan creation; the string is
                                 not kept); steps whose shape has an entry use the tuned
                                 tile parameters; NULL = built-in choice.  An unreadable or
                                 malformed table is QGM_E_ARG */
+  const int32_t* open_qubits;  /* n_open distinct qubits whose output variables stay open: they
+                                are neither fixed to the bitstring nor summed, so one
+                                contraction gives 2^n_open amplitudes (the paper's Discussion:
+                                a large slice of amplitudes from one evaluation).  Amplitude e
+                                of bitstring b is <x|C|0> with x = b except x[open_qubits[i]]
+                                = bit i of e; the bitstring's entries at open qubits are
+                                ignored.  Every amplitude output (out, partial, d_partial)
+                                then holds 2^n_open entries per bitstring, b-major.  Not with
+                                gradient = 1 (QGM_E_UNSUPPORTED); a qubit without a variable
+                                of its own (no H, SX or SY) cannot be open (QGM_E_ARG).  The
+                                array is read during qgm_plan_create only */
 } qgm_plan_opts;
 
 /* Per-item chain engines.  AUTO picks GENERATED when the plan's live item
@@ -137,6 +148,7 @@ typedef struct {
   double roof_s_item;     /* chain roofline time per slice contraction: the sum over item
                              steps of max(flops / 157.3 TFLOP/s, bytes / 8 TB/s), MI355X's
                              FP32 and HBM peaks, bytes as in bytes_item */
+  int32_t n_open;         /* open outputs: 2^n_open amplitudes per bitstring */
 } qgm_stats;
 
 /* Circuit text v1, one gate per line, '#' starts a comment:
@@ -204,6 +216,12 @@ qgm_status qgm_plan_slices(const qgm_circuit* c, int32_t k_req, int32_t target_r
  *     whose peak item memory fits a 64-item group in 96 GiB (complex128).
  *     *k_out gives the chosen k.  Fails with QGM_E_WORKSPACE when no k
  *     fits;
+ *   QGM_PLAN_BNB: after the min-fill restarts (half the final ordering's
+ *     budget), a branch-and-bound search over orderings (the QuickBB scheme
+ *     of Section "The variable elimination ordering", see qgm_order_search)
+ *     from the best of them, 200 search nodes per second of the other half,
+ *     3 children per node on graphs of more than 20 vertices; with k_req = 0
+ *     the whole budget goes to the ordering.  Sum-of-2^deg objective only;
  *   QGM_PLAN_DETERMINISTIC: the budget counts work instead of wall-clock
  *     time (320 min-fill restarts per second of budget, at most 128 per ordering; SEARCH makes
  *     exactly 8 attempts), so every host returns the same plan for the
@@ -215,11 +233,27 @@ enum {
   QGM_PLAN_SEARCH = 8,
   QGM_PLAN_WIDE_TIME = 16,
   QGM_PLAN_CHOOSE_K = 32,
-  QGM_PLAN_DETERMINISTIC = 64
+  QGM_PLAN_DETERMINISTIC = 64,
+  QGM_PLAN_BNB = 128
 };
 qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t target_rank, double time_budget_s,
                               uint64_t seed, int32_t flags, int32_t* sliced_out, int32_t* k_out, int32_t* order_out,
                               int32_t* n_order_out);
+/* Branch and bound over elimination orderings (the QuickBB scheme of
+ * Section "The variable elimination ordering"): depth-first over the next
+ * vertex to eliminate, children in min-fill order, a branch pruned when the
+ * minor-min-width of the remaining graph shows it cannot beat the best
+ * ordering found so far.  Graph: the free variables with the sliced ones
+ * removed.  Objective: (width, cost) compared lexicographically, width =
+ * max deg(v) and cost = sum 2^deg(v) at elimination.  init_order (a
+ * permutation of the free non-sliced variables) is the first incumbent;
+ * the search stops after max_nodes nodes; beam > 0 tries only that many
+ * children per node (<= 0: all, and then *complete = 1 means the result is
+ * optimal).  order_out gets n_order ids.  Errors: QGM_E_SLICE, QGM_E_ORDER as
+ * for qgm_plan_create, QGM_E_ARG. */
+qgm_status qgm_order_search(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* init_order,
+                            int32_t n_order, int64_t max_nodes, int32_t beam, int32_t* order_out, double* cost,
+                            int32_t* width, int32_t* complete);
 /* Cost (sum of 2^deg(v)) and width (max deg(v)) of eliminating `order` after
  * removing the sliced vertices (Section "Variable elimination", cost model).
  * Errors: QGM_E_SLICE, QGM_E_ORDER as for qgm_plan_create. */

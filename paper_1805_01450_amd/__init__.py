@@ -79,6 +79,18 @@ def qgm_plan_slices(c, k_req: int = -1, target_rank: int = 0, time_budget_s: flo
     return list(sl[: k.value]), list(order[: n.value])
 
 
+QGM_PLAN_BNB = 128
+
+
+def qgm_order_search(c, sliced, init_order, max_nodes: int, beam: int = 0):
+    """Branch and bound over orderings: (order, cost, width, complete)."""
+    out = (C.c_int32 * max(1, len(init_order)))()
+    cost, width, complete = C.c_double(), C.c_int32(), C.c_int32()
+    check(lib.qgm_order_search(c, _i32(sliced), len(sliced), _i32(init_order), len(init_order), max_nodes, beam, out,
+                               C.byref(cost), C.byref(width), C.byref(complete)))
+    return list(out[:len(init_order)]), cost.value, width.value, bool(complete.value)
+
+
 def qgm_order_cost(c, sliced, order):
     cost, width = C.c_double(), C.c_int32()
     check(lib.qgm_order_cost(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(cost), C.byref(width)))
@@ -88,8 +100,11 @@ def qgm_order_cost(c, sliced, order):
 def qgm_plan_create(c, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0, profile: bool = False,
                     engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
                     vector_only: bool = False, checkpoint_every: int = 0, persistent: bool = False,
-                    deterministic: bool = False, tile_table_path: str | None = None):
+                    deterministic: bool = False, tile_table_path: str | None = None, open_qubits=()):
     opts = PlanOpts()
+    oq = _i32(open_qubits)
+    opts.n_open = len(open_qubits)
+    opts.open_qubits = C.cast(oq, C.POINTER(C.c_int32)) if len(open_qubits) else None
     opts.checkpoint_every = checkpoint_every
     opts.persistent = int(persistent)
     opts.deterministic = int(deterministic)
@@ -135,10 +150,15 @@ def _host_inputs(bitstrings, params):
     return bs, par
 
 
+def _n_amp(p) -> int:
+    return 1 << qgm_plan_stats(p)["n_open"]
+
+
 def qgm_amplitudes(p, bitstrings, params, workspace, stream=None) -> np.ndarray:
-    """Host arrays in, complex128 numpy array out; workspace is a CUDA uint8 tensor."""
+    """Host arrays in, complex128 numpy array out (n_bs x 2^n_open entries,
+    bitstring-major); workspace is a CUDA uint8 tensor."""
     bs, par = _host_inputs(bitstrings, params)
-    out = np.empty(2 * bs.shape[0], dtype=np.float64)
+    out = np.empty(2 * bs.shape[0] * _n_amp(p), dtype=np.float64)
     check(lib.qgm_amplitudes(p, bs.ctypes.data_as(C.POINTER(C.c_uint8)), bs.shape[0],
                              None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)),
                              _ptr(workspace), workspace.numel(), _stream(stream),
@@ -147,9 +167,9 @@ def qgm_amplitudes(p, bitstrings, params, workspace, stream=None) -> np.ndarray:
 
 
 def qgm_amplitudes_range(p, bitstrings, params, s_begin: int, s_end: int, workspace, stream=None) -> np.ndarray:
-    """(n_bs, 4) float64: sum re, sum im, compensation re, compensation im."""
+    """(n_bs x 2^n_open, 4) float64: sum re, sum im, compensation re, compensation im."""
     bs, par = _host_inputs(bitstrings, params)
-    out = np.empty(4 * bs.shape[0], dtype=np.float64)
+    out = np.empty(4 * bs.shape[0] * _n_amp(p), dtype=np.float64)
     check(lib.qgm_amplitudes_range(p, bs.ctypes.data_as(C.POINTER(C.c_uint8)), bs.shape[0],
                                    None if par is None else par.ctypes.data_as(C.POINTER(C.c_double)),
                                    s_begin, s_end, _ptr(workspace), workspace.numel(), _stream(stream),
@@ -342,15 +362,16 @@ class Plan:
     def __init__(self, circuit: Circuit, sliced, order, prec: int = QGM_C128, workspace_cap: int = 0,
                  profile: bool = False, engine: int = QGM_ENGINE_AUTO, gradient: bool = False, waves: int = 0,
                  vector_only: bool = False, checkpoint_every: int = 0, persistent: bool = False,
-                 deterministic: bool = False, tile_table_path: str | None = None):
+                 deterministic: bool = False, tile_table_path: str | None = None, open_qubits=()):
         self.circuit = circuit
+        self.open_qubits = [int(x) for x in open_qubits]
         self.sliced = list(sliced)
         self.order = list(order)
         self.prec = prec
         self.gradient = gradient
         self.h = qgm_plan_create(circuit.h, self.sliced, self.order, prec, workspace_cap, profile, engine,
                                  gradient, waves, vector_only, checkpoint_every, persistent, deterministic,
-                                 tile_table_path)
+                                 tile_table_path, self.open_qubits)
         self._ws = None
 
     @property

@@ -26,7 +26,8 @@ class PlanOpts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("profile", C.c_int32), ("workspace_cap", C.c_size_t),
                 ("engine", C.c_int32), ("gradient", C.c_int32), ("waves", C.c_int32),
                 ("vector_only", C.c_int32), ("checkpoint_every", C.c_int32), ("persistent", C.c_int32),
-                ("deterministic", C.c_int32), ("reserved0", C.c_int32), ("tile_table_path", C.c_char_p)]
+                ("deterministic", C.c_int32), ("n_open", C.c_int32), ("tile_table_path", C.c_char_p),
+                ("open_qubits", C.POINTER(C.c_int32))]
 
 
 class Tile(C.Structure):
@@ -39,7 +40,7 @@ class Stats(C.Structure):
                 ("flops_item", C.c_double), ("flops_const", C.c_double), ("bytes_item", C.c_double),
                 ("cost", C.c_double), ("engine", C.c_int32), ("waves", C.c_int32), ("compile_s", C.c_double),
                 ("launches", C.c_int32), ("mfma_steps", C.c_int32), ("flops_mfma", C.c_double),
-                ("roof_s_item", C.c_double)]
+                ("roof_s_item", C.c_double), ("n_open", C.c_int32)]
 
 
 def _load():
@@ -65,6 +66,7 @@ def _load():
         "qgm_plan_slices": (i32, [P, i32, i32, dbl, u64, pi32, pi32, pi32, pi32]),
         "qgm_plan_slices_ex": (i32, [P, i32, i32, dbl, u64, i32, pi32, pi32, pi32, pi32]),
         "qgm_order_cost": (i32, [P, pi32, i32, pi32, i32, pd, pi32]),
+        "qgm_order_search": (i32, [P, pi32, i32, pi32, i32, C.c_int64, i32, pi32, pd, pi32, pi32]),
         "qgm_plan_create": (i32, [P, pi32, i32, pi32, i32, C.POINTER(PlanOpts), C.POINTER(P)]),
         "qgm_plan_stats": (i32, [P, C.POINTER(Stats)]),
         "qgm_workspace_size": (i32, [P, i32, u64, C.POINTER(sz)]),
@@ -98,7 +100,7 @@ def _load():
 
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
-            "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
+            "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_order_search", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
             "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_amplitudes_device_noalloc",
             "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_level_timing", "qgm_plan_autotune", "qgm_plan_free",

@@ -84,7 +84,7 @@ struct Staging {
   size_t bits, params, partial, gpartial, total;
 };
 
-Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool grads) {
+Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool grads, int n_open = 0) {
   Staging st;
   size_t off = ws.total;
   st.bits = off;
@@ -92,7 +92,7 @@ Staging staging(const WsLayout& ws, int n_bs, int n_qubits, int n_params, bool g
   st.params = off;
   off = align256(off + (size_t)std::max(1, n_params) * sizeof(double));
   st.partial = off;
-  off = align256(off + (size_t)std::max(1, n_bs) * 4 * sizeof(double));
+  off = align256(off + ((size_t)std::max(1, n_bs) << n_open) * 4 * sizeof(double));
   st.gpartial = off;
   if (grads) off = align256(off + (size_t)std::max(1, n_bs) * std::max(1, n_params) * 4 * sizeof(double));
   st.total = off;
@@ -104,6 +104,13 @@ qgm_status ensure_device(qgm_plan* p) {
   int rc = dev_upload(p->prog, p->code, p->engine == QGM_ENGINE_WIDE ? &p->wide : nullptr, p->dev, err,
                       &p->wide_code, &p->wide_kernels);
   if (rc) return fail((qgm_status)rc, err);
+  // constants of plans without angles: contracted once, here, not per run
+  // (the generated kernels fold them at compile time)
+  if (p->net.n_params == 0 && p->engine != QGM_ENGINE_GENERATED && !p->dev.cst_cached &&
+      !std::getenv("QGM_NO_CONST_CACHE")) {
+    rc = dev_cache_constants(p->prog, p->dev, p->opts.prec, p->engine == QGM_ENGINE_WIDE, err);
+    if (rc) return fail((qgm_status)rc, err);
+  }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->dev.device)
     return fail(QGM_E_ARG, "plan was uploaded to device " + std::to_string(p->dev.device) +
@@ -255,6 +262,32 @@ qgm_status qgm_order_cost(const qgm_circuit* c, const int32_t* sliced_vars, int3
   GUARD_END
 }
 
+qgm_status qgm_order_search(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* init_order,
+                            int32_t n_order, int64_t max_nodes, int32_t beam, int32_t* order_out, double* cost,
+                            int32_t* width, int32_t* complete) {
+  GUARD_BEGIN
+  if (!c || !order_out || !cost || !width || !complete || max_nodes < 1) return fail(QGM_E_ARG, "bad argument");
+  std::vector<int> sv, ov;
+  qgm_status s = validate_plan_inputs(c->net, sliced_vars, k, init_order, n_order, sv, ov);
+  if (s) return s;
+  std::string err;
+  int code = 0;
+  if (!validate_plan(c->net, sv, ov, err, code)) return fail((qgm_status)code, err);
+  std::vector<int> vov;
+  Graph g = model_graph(c->net, vov);
+  std::vector<char> removed(g.n, 0);
+  for (int v : sv) removed[vov[v]] = 1;
+  std::vector<int> o;
+  for (int v : ov) o.push_back(vov[v]);
+  BnbResult r = bnb_order(g, removed, o, (long)max_nodes, beam);
+  for (size_t i = 0; i < r.order.size(); ++i) order_out[i] = c->net.free_vars[r.order[i]];
+  *cost = r.cost.cost;
+  *width = r.cost.width;
+  *complete = r.complete ? 1 : 0;
+  return QGM_OK;
+  GUARD_END
+}
+
 qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* order,
                            int32_t n_order, const qgm_plan_opts* opts, qgm_plan** out) {
   GUARD_BEGIN
@@ -274,6 +307,10 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   if (o.vector_only != 0 && o.vector_only != 1) return fail(QGM_E_ARG, "vector_only must be 0 or 1");
   if (o.persistent != 0 && o.persistent != 1) return fail(QGM_E_ARG, "persistent must be 0 or 1");
   if (o.deterministic != 0 && o.deterministic != 1) return fail(QGM_E_ARG, "deterministic must be 0 or 1");
+  if (o.n_open < 0 || o.n_open > 10 || (o.n_open > 0 && !o.open_qubits))
+    return fail(QGM_E_ARG, "n_open must be 0..10 with open_qubits given");
+  std::vector<int> open_q(o.open_qubits, o.open_qubits + o.n_open);
+  o.open_qubits = nullptr;  // the caller's array is not kept
   if (o.checkpoint_every < 0) return fail(QGM_E_ARG, "checkpoint_every must be >= 0");
   if (o.checkpoint_every > 0 && !o.gradient) return fail(QGM_E_ARG, "checkpoint_every needs a gradient plan");
   TileTable tiles;
@@ -293,7 +330,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
   p->tile_table_path = tile_path;
   std::string err;
   int code = 0;
-  if (!compile_program(p->net, sv, ov, p->prog, err, code, o.gradient != 0, false, o.checkpoint_every)) {
+  if (!compile_program(p->net, sv, ov, p->prog, err, code, o.gradient != 0, false, o.checkpoint_every, open_q)) {
     delete p;
     return fail((qgm_status)code, err);
   }
@@ -320,7 +357,7 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     // the wide engine loads constants from memory: their factors are
     // combined per step first (a different grouping of the same products)
     Program combined;
-    if (compile_program(p->net, sv, ov, combined, err, code, false, true)) p->prog = std::move(combined);
+    if (compile_program(p->net, sv, ov, combined, err, code, false, true, 0, open_q)) p->prog = std::move(combined);
   }
   // the cap applies to the program that runs (after the wide engine's
   // regrouping, which changes its item memory)
@@ -424,6 +461,7 @@ qgm_status qgm_plan_stats(const qgm_plan* p, qgm_stats* out) {
   s.flops_const = p->prog.flops_const;
   s.bytes_item = p->prog.bytes_item;
   s.roof_s_item = p->prog.roof_s_item;
+  s.n_open = p->prog.n_open;
   s.cost = p->cost;
   s.engine = p->engine;
   s.compile_s = p->compile_s;
@@ -453,7 +491,7 @@ qgm_status qgm_workspace_size(const qgm_plan* pc, int32_t n_bs, uint64_t n_slice
   WsLayout ws;
   LaunchCfg cfg;
   if ((s = layout_for(p, n_bs, n_slices, ws, cfg))) return s;
-  *bytes = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0).total;
+  *bytes = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0, p->prog.n_open).total;
   return QGM_OK;
   GUARD_END
 }
@@ -618,7 +656,7 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bits, int32_t n_bs, 
     if ((s = ensure_device(p))) return s;
     if ((s = layout_for(p, n_bs, s_end - s_begin, ws, cfg))) return s;
   }
-  Staging st = staging(ws, n_bs, nq, p->net.n_params, p->prog.n_grad_slots > 0);
+  Staging st = staging(ws, n_bs, nq, p->net.n_params, p->prog.n_grad_slots > 0, p->prog.n_open);
   if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace holds " + std::to_string(ws_bytes) +
                                                              " bytes, run needs " + std::to_string(st.total));
   char* base = (char*)d_ws;
@@ -633,8 +671,8 @@ qgm_status qgm_amplitudes_range(qgm_plan* p, const uint8_t* bits, int32_t n_bs, 
                             p->net.n_params > 0 ? (const double*)(base + st.params) : nullptr, s_begin, s_end, d_ws,
                             ws.total, stream, (double*)(base + st.partial));
   if (s) return s;
-  if (hipMemcpyAsync(partial, base + st.partial, (size_t)n_bs * 4 * sizeof(double), hipMemcpyDeviceToHost,
-                     stream) != hipSuccess)
+  if (hipMemcpyAsync(partial, base + st.partial, ((size_t)n_bs << p->prog.n_open) * 4 * sizeof(double),
+                     hipMemcpyDeviceToHost, stream) != hipSuccess)
     return fail(QGM_E_HIP, "result download failed");
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return fail(QGM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
@@ -646,11 +684,11 @@ qgm_status qgm_amplitudes(qgm_plan* p, const uint8_t* bits, int32_t n_bs, const 
                           size_t ws_bytes, void* stream, double* out) {
   GUARD_BEGIN
   if (!p || n_bs < 0 || (n_bs > 0 && !out)) return fail(QGM_E_ARG, "bad argument");
-  std::vector<double> part((size_t)std::max(1, n_bs) * 4);
+  std::vector<double> part(((size_t)std::max(1, n_bs) << p->prog.n_open) * 4);
   qgm_status s = qgm_amplitudes_range(p, bits, n_bs, params, 0, 1ull << p->sliced.size(), d_ws, ws_bytes, stream,
                                       part.data());
   if (s) return s;
-  for (int b = 0; b < n_bs; ++b) {
+  for (int b = 0; b < (n_bs << p->prog.n_open); ++b) {
     out[2 * b] = part[4 * b] + part[4 * b + 2];
     out[2 * b + 1] = part[4 * b + 1] + part[4 * b + 3];
   }
@@ -805,7 +843,7 @@ qgm_status qgm_plan_autotune(qgm_plan* p, int32_t n_bs, uint64_t n_slices, void*
   WsLayout ws;
   LaunchCfg cfg;
   if ((s = layout_for(p, n_bs, n_slices, ws, cfg))) return s;
-  Staging st = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0);
+  Staging st = staging(ws, n_bs, p->net.n_qubits, p->net.n_params, p->prog.n_grad_slots > 0, p->prog.n_open);
   if (ws_bytes < st.total) return fail(QGM_E_WORKSPACE, "workspace smaller than qgm_workspace_size");
   char* base = (char*)d_ws;
   if (hipMemsetAsync(base + st.bits, 0, st.partial - st.bits, stream) != hipSuccess)
@@ -1129,7 +1167,11 @@ qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream
                                                  std::ldexp(1.0, key.ni + key.nj)) > 8.0 * (1ull << 30))
       --nb;
     // stage 1: block layout x k steps per stage; stage 2: ring budget x band
-    std::vector<int> pers = key.prec == QGM_BF16X3 ? std::vector<int>{2, 4} : std::vector<int>{1, 2, 4};
+    // BF16x3 keeps two k per stage: more pairs per stage hold more split
+    // operands live than two waves per SIMD have registers for, which the
+    // level kernels of a plan (every step of a level in one kernel) pay for
+    // even where a lone contraction does not
+    std::vector<int> pers = key.prec == QGM_BF16X3 ? std::vector<int>{2} : std::vector<int>{1, 2, 4};
     qgm_tile best{2, 53248, 2, 0};
     float best_ms = 0;
     bool have = false;

@@ -518,7 +518,11 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
       if (op.is_const)
         for (int e = 0; e < (1 << op.vars.size()); ++e) br.const_ref(op.storage + e);
     if (st.kind == ST_FINAL) {
-      br.emit_products(st, ref, [](int) { return std::string("amp"); }, false);
+      // open outputs: 2^r amplitudes per item
+      if (st.r > 0)
+        br.emit_products(st, ref, [](int c) { return "amp_" + std::to_string(c); }, false);
+      else
+        br.emit_products(st, ref, [](int) { return std::string("amp"); }, false);
     } else if (st.kind == ST_GRAD) {
       const std::string g = "g" + std::to_string(st.grad_slot);
       br.emit_products(st, ref, [&](int) { return g; }, true);
@@ -551,7 +555,11 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
     }
     seq.insert(seq.end(), later.begin(), later.end());
   }
-  o << "  C2 amp;\n";
+  const int n_amp = 1 << prog.n_open;  // amplitudes per item (open outputs)
+  if (prog.n_open == 0)
+    o << "  C2 amp;\n";
+  else
+    for (int c = 0; c < n_amp; ++c) o << "  C2 amp_" << c << ";\n";
   // the packed row is formed before the first step that reads it
   bool packed = false;
   auto need_bits = [&](int i) {
@@ -605,20 +613,28 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
   }
   // fused slice sum of the block's 64 slices: the compensated butterfly that
   // the reduction kernels use for each chunk of 64 slices
-  o << "  if (!fused) {\n"
-    << "    if (valid) res[sl * n_bs + b] = amp;\n"
-    << "    " << leave << "\n"
-    << "  }\n"
-    << "  double sr = (double)amp.x, si = (double)amp.y, cr = 0.0, ci = 0.0;\n"
-    << "  wave_sum(sr, cr);\n"
-    << "  wave_sum(si, ci);\n"
-    << "  if (lane == 0) {\n"
-    << "    const unsigned long long chunk = item / 64ull;\n"
-    << "    part[4 * chunk + 0] = sr;\n"
-    << "    part[4 * chunk + 1] = si;\n"
-    << "    part[4 * chunk + 2] = cr;\n"
-    << "    part[4 * chunk + 3] = ci;\n"
-    << "  }\n";
+  if (prog.n_open > 0) {
+    // open outputs: every amplitude goes to the per-item results (the
+    // slice sum runs in the reduction kernel; blocks never fuse it)
+    for (int c = 0; c < n_amp; ++c)
+      o << "  if (valid) res[((sl * n_bs + b) << " << prog.n_open << ") + " << c << "] = amp_" << c << ";\n";
+    o << "  " << leave << "\n";
+  } else {
+    o << "  if (!fused) {\n"
+      << "    if (valid) res[sl * n_bs + b] = amp;\n"
+      << "    " << leave << "\n"
+      << "  }\n"
+      << "  double sr = (double)amp.x, si = (double)amp.y, cr = 0.0, ci = 0.0;\n"
+      << "  wave_sum(sr, cr);\n"
+      << "  wave_sum(si, ci);\n"
+      << "  if (lane == 0) {\n"
+      << "    const unsigned long long chunk = item / 64ull;\n"
+      << "    part[4 * chunk + 0] = sr;\n"
+      << "    part[4 * chunk + 1] = si;\n"
+      << "    part[4 * chunk + 2] = cr;\n"
+      << "    part[4 * chunk + 3] = ci;\n"
+      << "  }\n";
+  }
   if (!persistent) {
     o << "}\n";
     return head.str() + item_head.str() + blockhead.str() + o.str();

@@ -556,10 +556,21 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const unsigned long long tiles = 1ull << (r - L);
       const unsigned long long nb = (tiles + 3) / 4;
       k.steps.push_back(si);
+      // Blocks are dealt to the XCDs round robin (block index mod 8), each
+      // XCD with its own L2.  With 8 or more blocks the step's range starts
+      // at a multiple of 8 and XCD x runs the x-th eighth of the tiles, so
+      // tiles that share operand rows (neighbours in the reuse order above)
+      // run on one XCD and find those rows in its L2.
+      const bool xcd = nb >= 8 && nb % 8 == 0;
+      if (xcd) k.blocks = (k.blocks + 7) & ~7ull;
       o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
-        << "  // step " << si << "\n"
-        << "  const unsigned long long t = (blk - " << k.blocks << "ull) * 4ull + wv;\n"
-        << "  if (t >= " << tiles << "ull) return;\n";
+        << "  // step " << si << "\n";
+      if (xcd)
+        o << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
+          << "  const unsigned long long t = ((g & 7ull) * " << nb / 8 << "ull + (g >> 3)) * 4ull + wv;\n";
+      else
+        o << "  const unsigned long long t = (blk - " << k.blocks << "ull) * 4ull + wv;\n";
+      o << "  if (t >= " << tiles << "ull) return;\n";
       k.blocks += nb;
       // per-operand base offsets from the tile index
       for (int i = 0; i < m; ++i) {
@@ -573,8 +584,9 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
               << rec[i][7 + d] << "ll)";
         o << ";\n";
       }
-      if (kind == ST_ELIM) {
-        o << "  const long long ob = " << out << "ll";
+      if (kind == ST_ELIM || kind == ST_FINAL) {
+        // (FINAL: the element index of the amplitude among the item's 2^r)
+        o << "  const long long ob = " << (kind == ST_ELIM ? out : 0) << "ll";
         for (int k2 = L; k2 < r; ++k2)
           o << " + (long long)((t >> " << (k2 - L) << ") & 1ull) * " << (1ll << perm[k2]) << "ll";
         o << ";\n";
@@ -634,7 +646,10 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
             if ((lo >> j) & 1) lo_off += 1ll << perm[j];
           o << "  gm[(ob + " << lo_off << "ll) * 64ll + lane] = a" << lo << ";\n";
         } else if (kind == ST_FINAL) {
-          o << "  if (valid) res[sl * n_bs + b] = a" << lo << ";\n";
+          long long lo_off = 0;
+          for (int j = 0; j < L; ++j)
+            if ((lo >> j) & 1) lo_off += 1ll << perm[j];
+          o << "  if (valid) res[((sl * n_bs + b) << " << r << ") + ob + " << lo_off << "ll] = a" << lo << ";\n";
         } else {
           o << "  if (valid) gres[(" << slot << "ull * n_s + sl) * n_bs + b] = a" << lo << ";\n";
         }
@@ -642,6 +657,9 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       o << "  return;\n  }\n";
     }
     o << "}\n";
+    // a multiple of 8 blocks per 64-item group keeps the XCD of a block
+    // index the same in every group row of the grid
+    if (k.blocks >= 8) k.blocks = (k.blocks + 7) & ~7ull;
     kernels.push_back(k);
   }
   // constant steps (no fixed variable): one thread per output element,

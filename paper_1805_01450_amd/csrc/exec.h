@@ -56,6 +56,11 @@ struct DevProgram {
   void* chain_fn = nullptr;  // hipFunction_t "qgm_chain"
   int chain_waves = 1;       // wavefronts per block of the generated kernel
   int chain_persistent = 0;  // 1: the generated kernel pulls chunks from a work queue (resident grid)
+  // Constant area computed once per plan (plans without RZ angles): the raw
+  // tables and every constant step, contracted at upload; runs then read it
+  // instead of rebuilding the constants in their workspace.
+  void* cst_cache = nullptr;
+  int cst_cached = 0;
 };
 
 // Precision of the slice contraction: 0 = complex128, 1 = complex64.
@@ -99,5 +104,8 @@ int dev_run(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, con
             const uint8_t* d_bits, const double* d_params, void* d_ws, void* stream, double* d_partial,
             double* d_grad_partial, void* const* events, std::string& err);
 int dev_query(int& n_cu, size_t& max_lds, std::string& err);
+// Contract the constant steps of a plan without RZ angles once into
+// plan-owned device memory (synchronous, on a private stream).
+int dev_cache_constants(const Program& prog, DevProgram& dp, int prec, int wide, std::string& err);
 
 }  // namespace qgm

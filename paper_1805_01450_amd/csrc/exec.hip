@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) prologue_kernel(const double* __restrict_
                                                        const uint8_t* __restrict__ bits, int n_bs, int n_qubits,
                                                        uint64_t* __restrict__ packed, unsigned* __restrict__ counter) {
   const int tid = threadIdx.x;
-  if (tid == 0) *counter = 0u;
+  if (tid == 0 && counter) *counter = 0u;
   for (int b = tid; b < n_bs; b += blockDim.x) {
     uint64_t w = 0;
     for (int q = 0; q < n_qubits; ++q) w |= (uint64_t)(bits[(size_t)b * n_qubits + q] & 1) << q;
@@ -194,8 +194,8 @@ __global__ void __launch_bounds__(64) chain_kernel(const DevStep* __restrict__ s
             acc.x += prod.x;
             acc.y += prod.y;
           }
-          if (st.kind == 2) {
-            if (valid) res[sl * (uint64_t)n_bs + b] = acc;
+          if (st.kind == 2) {  // rank r: 2^r amplitudes per item (open outputs)
+            if (valid) res[((sl * (uint64_t)n_bs + b) << st.r) + c] = acc;
           } else if (st.kind == 3) {
             if (valid) gres[((uint64_t)st.grad_slot * n_s + sl) * (uint64_t)n_bs + b] = acc;
           } else {
@@ -433,6 +433,41 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
   return 0;
 }
 
+namespace {
+template <typename R>
+int cache_constants_typed(const Program& prog, DevProgram& dp, int wide, std::string& err) {
+  const size_t bytes = std::max<size_t>((size_t)std::max(prog.n_const, 1) * sizeof(cx<R>), 256);
+  HIP_OK(hipMalloc(&dp.cst_cache, bytes));
+  hipStream_t st = nullptr;
+  HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  auto* cst = (cx<R>*)dp.cst_cache;
+  // no bitstrings: the prologue writes the raw tables and runs the constant
+  // steps (the interpreter's); the wide engine's constant kernels follow
+  hipLaunchKernelGGL(prologue_kernel<R>, dim3(1), dim3(256), 0, st, (const double*)dp.raw, (const int*)dp.rawp,
+                     (const int*)dp.rawb, (const int*)dp.rawd, prog.n_raw, (const double*)nullptr,
+                     (const DevStep*)dp.steps, wide ? 0 : dp.n_const_steps, (const uint32_t*)dp.optab, cst,
+                     (const uint8_t*)nullptr, 0, 0, (uint64_t*)nullptr, (unsigned*)nullptr);
+  int rc = 0;
+  if (wide && wide_launch_steps<R>(dp.wide, 0, 0, cst, nullptr, 0, nullptr, 0, 0, 1, 0, nullptr, nullptr, true, st))
+    rc = -6;
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  if (rc || e != hipSuccess) {
+    err = "constant steps at upload failed";
+    return -6;
+  }
+  dp.cst_cached = 1;
+  return 0;
+}
+}  // namespace
+
+int dev_cache_constants(const Program& prog, DevProgram& dp, int prec, int wide, std::string& err) {
+  if (dp.cst_cached) return 0;
+  return prec == 0 ? cache_constants_typed<double>(prog, dp, wide, err)
+                   : prec == 2 ? cache_constants_typed<bfx3>(prog, dp, wide, err)
+                               : cache_constants_typed<float>(prog, dp, wide, err);
+}
+
 void dev_free(DevProgram& dp) {
   void* ps[] = {dp.raw, dp.rawp, dp.rawb, dp.rawd, dp.slot_param, dp.steps, dp.leaves, dp.optab};
   for (void* p : ps)
@@ -442,6 +477,7 @@ void dev_free(DevProgram& dp) {
   if (dp.wide.const_list) (void)hipFree(dp.wide.const_list);
   if (dp.wide.module) (void)hipModuleUnload((hipModule_t)dp.wide.module);
   if (dp.wide.ops) (void)hipFree(dp.wide.ops);
+  if (dp.cst_cache) (void)hipFree(dp.cst_cache);
   dp = DevProgram();
 }
 
@@ -449,7 +485,7 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   const size_t el = cfg.prec == 0 ? 16 : 8;
   const uint64_t n_items = (uint64_t)cfg.n_bs * cfg.n_s;
   const uint64_t n_chunks = (n_items + kLanes - 1) / kLanes;
-  ws.fused = (cfg.generated && cfg.n_s % kLanes == 0) ? 1 : 0;
+  ws.fused = (cfg.generated && cfg.n_s % kLanes == 0 && prog.n_open == 0) ? 1 : 0;
   size_t lds = (size_t)prog.item_elems * kLanes * el;
   if (cfg.generated) lds = 0;
   // 64 bytes of headroom for the kernel's static LDS (the work-queue slot)
@@ -485,8 +521,8 @@ int dev_layout(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, 
   off = align256(off + (size_t)std::max(prog.n_const, 1) * el);
   ws.bits = off;
   off = align256(off + (size_t)std::max(cfg.n_bs, 1) * 8);
-  ws.res = off;
-  off = align256(off + (size_t)std::max<uint64_t>(n_items, 1) * el);
+  ws.res = off;  // 2^n_open amplitudes per item (open outputs)
+  off = align256(off + ((size_t)std::max<uint64_t>(n_items, 1) << prog.n_open) * el);
   ws.gres = off;
   off = align256(off + (size_t)prog.n_grad_slots * n_items * el);
   ws.counter = off;
@@ -523,9 +559,13 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
     if (events) (void)hipEventRecord((hipEvent_t)events[i], stream);
   };
   const uint64_t n_items = (uint64_t)cfg.n_bs * cfg.n_s;
+  // amplitudes per call: 2^n_open per bitstring, item results laid out as
+  // [slice][bitstring][amplitude], so each amplitude reduces like a bitstring
+  const int n_amp_bs = cfg.n_bs << prog.n_open;
   auto* packed = (uint64_t*)(base + ws.bits);
   auto* counter = (unsigned*)(base + ws.counter);
-  auto* cst = (cx<R>*)(base + ws.cst);
+  // plans without angles read the constants contracted at upload
+  auto* cst = dp.cst_cached ? (cx<R>*)dp.cst_cache : (cx<R>*)(base + ws.cst);
   auto* res = (cx<R>*)(base + ws.res);
   auto* gres = (cx<R>*)(base + ws.gres);
   auto* scr = (cx<R>*)(base + ws.scratch);
@@ -541,20 +581,22 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
   };
   mark(0);
   // The generated kernel reads the FP64 tables and the bitstring bytes itself.
+  // (with cached constants only the bitstrings are packed)
   if (!cfg.generated || n_items == 0)
     hipLaunchKernelGGL(prologue_kernel<R>, dim3(1), dim3(256), 0, stream, (const double*)dp.raw, (const int*)dp.rawp,
-                       (const int*)dp.rawb, (const int*)dp.rawd, prog.n_raw, d_params, (const DevStep*)dp.steps,
-                       cfg.wide ? 0 : dp.n_const_steps, (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs,
-                       cfg.n_qubits, packed, counter);
-  if (cfg.wide && wide_launch_steps<R>(dp.wide, 0, 0, cst, nullptr, 0, packed, cfg.n_bs, cfg.s_begin, cfg.n_s,
-                                       n_items, res, gres, true, stream)) {
+                       (const int*)dp.rawb, (const int*)dp.rawd, dp.cst_cached ? 0 : prog.n_raw, d_params,
+                       (const DevStep*)dp.steps, (cfg.wide || dp.cst_cached) ? 0 : dp.n_const_steps,
+                       (const uint32_t*)dp.optab, cst, d_bits, cfg.n_bs, cfg.n_qubits, packed, counter);
+  if (cfg.wide && !dp.cst_cached &&
+      wide_launch_steps<R>(dp.wide, 0, 0, cst, nullptr, 0, packed, cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, res,
+                           gres, true, stream)) {
     err = "wide constant steps: launch failed";
     return -6;
   }
   mark(1);
   if (n_items == 0) {
     mark(2);
-    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(n_amp_bs), dim3(64), 0, stream, res, n_amp_bs, cfg.n_s, d_partial);
     grad_reduce();
     mark(3);
     HIP_OK(hipGetLastError());
@@ -571,7 +613,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
       }
     }
     mark(2);
-    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(n_amp_bs), dim3(64), 0, stream, res, n_amp_bs, cfg.n_s, d_partial);
     grad_reduce();
     mark(3);
   } else if (cfg.generated) {
@@ -606,7 +648,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
                                  1, 0, stream, args, nullptr));
     mark(2);
     if (!ws.fused)
-      hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+      hipLaunchKernelGGL(reduce_kernel<R>, dim3(n_amp_bs), dim3(64), 0, stream, res, n_amp_bs, cfg.n_s, d_partial);
     else if (per_bs > 1)
       hipLaunchKernelGGL(combine_kernel, red_grid, dim3(64), 0, stream, chunks, cfg.n_bs, per_bs, d_partial);
     grad_reduce();
@@ -622,7 +664,7 @@ int run_typed(const Program& prog, const DevProgram& dp, const LaunchCfg& cfg, c
                          first, dp.n_steps, (const DevLeaf*)dp.leaves, (const uint32_t*)dp.optab, cst, packed,
                          cfg.n_bs, cfg.s_begin, cfg.n_s, n_items, counter, res, gres, scr, prog.item_elems);
     mark(2);
-    hipLaunchKernelGGL(reduce_kernel<R>, dim3(cfg.n_bs), dim3(64), 0, stream, res, cfg.n_bs, cfg.n_s, d_partial);
+    hipLaunchKernelGGL(reduce_kernel<R>, dim3(n_amp_bs), dim3(64), 0, stream, res, n_amp_bs, cfg.n_s, d_partial);
     grad_reduce();
     mark(3);
   }

@@ -67,6 +67,18 @@ struct OrderCost {
 };
 OrderCost order_cost(const Graph& g, const std::vector<int>& order, const std::vector<char>& removed);
 std::vector<int> min_fill_order(const Graph& g, const std::vector<char>& removed, uint64_t seed, int randomize);
+// Branch and bound over elimination orderings of the graph without the
+// removed vertices (QuickBB scheme): objective (width, sum 2^deg)
+// lexicographic, incumbent `init`, at most max_nodes search nodes, beam
+// children per node (<= 0: all; the search is then exact when complete).
+struct BnbResult {
+  std::vector<int> order;
+  OrderCost cost;
+  long nodes = 0;
+  bool complete = false;
+};
+BnbResult bnb_order(const Graph& g, const std::vector<char>& removed, const std::vector<int>& init, long max_nodes,
+                    int beam);
 // flags bit 0: recompute the ordering after every removal (instead of
 // keeping the first ordering throughout).
 bool plan_slices(const Network& net, int k_req, int target_rank, double time_budget_s, uint64_t seed,
@@ -132,6 +144,7 @@ struct Program {
   int n_const_steps = 0;
   int max_rank = 0;
   int n_grad_slots = 0;          // gradient programs: one slot per RZ gate
+  int n_open = 0;                // open outputs: the final step has rank n_open (2^n_open amplitudes per item)
   std::vector<int> grad_param;   // slot -> parameter index
   double flops_item = 0, flops_const = 0;
   double bytes_item = 0;         // algorithmic bytes per item at 8 B per element
@@ -156,9 +169,11 @@ bool validate_plan(const Network& net, const std::vector<int>& sliced, const std
 bool matrix_core_shape(const Step& st);
 // checkpoint_every = n > 0 (gradient programs): the reverse pass keeps every
 // n-th forward elimination output and recomputes the others it needs.
+// open_qubits: qubits whose output variables stay open (the final step has
+// rank open_qubits.size(); bit i of its element index is open_qubits[i]).
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                      Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false,
-                     int checkpoint_every = 0);
+                     int checkpoint_every = 0, const std::vector<int>& open_qubits = {});
 
 // ------------------------------------------------------------ wide engine
 // Descriptors for plans whose tensors are too large for registers or LDS.

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <random>
 
 #include "host.h"
@@ -181,6 +182,125 @@ std::vector<int> min_fill_order(const Graph& g0, const std::vector<char>& remove
     --left;
   }
   return order;
+}
+
+// Minor-min-width of the graph on the `alive` vertices: repeatedly contract
+// a vertex of minimum degree into its minimum-degree neighbour (dropping it
+// when isolated); the largest minimum degree met bounds the width of every
+// elimination ordering from below (a minor's treewidth never exceeds the
+// graph's, and every graph's treewidth is at least its minimum degree).
+static int minor_min_width(Graph g, std::vector<char> alive) {
+  int lb = 0;
+  for (;;) {
+    int v = -1, dv = 1 << 30;
+    for (int u = 0; u < g.n; ++u) {
+      if (!alive[u]) continue;
+      const int d = popcount_row(g.row(u), g.words);
+      if (d < dv) v = u, dv = d;
+    }
+    if (v < 0) break;
+    lb = std::max(lb, dv);
+    if (dv == 0) {
+      alive[v] = 0;
+      continue;
+    }
+    // neighbour of minimum degree; v's edges move to it
+    int w = -1, dw = 1 << 30;
+    const uint64_t* rv = g.row(v);
+    for (int x = 0; x < g.words; ++x) {
+      uint64_t bits = rv[x];
+      while (bits) {
+        const int u = x * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int d = popcount_row(g.row(u), g.words);
+        if (d < dw) w = u, dw = d;
+      }
+    }
+    std::vector<uint64_t> nb(rv, rv + g.words);
+    for (int x = 0; x < g.words; ++x) {
+      uint64_t bits = nb[x];
+      while (bits) {
+        const int u = x * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        if (u != w) g.add_edge(u, w);
+      }
+    }
+    drop(g, v);
+    alive[v] = 0;
+  }
+  return lb;
+}
+
+// Branch and bound over elimination orderings, the QuickBB scheme the paper
+// uses (Section "The variable elimination ordering"): depth-first over the
+// next vertex to eliminate, children in min-fill order, a node pruned when
+// the minor-min-width of what is left shows it cannot beat the incumbent.
+// Objective: (width, cost) compared lexicographically, width = max deg(v)
+// and cost = sum 2^deg(v) at elimination.  Anytime: the incumbent starts as
+// `init` and the search stops after max_nodes nodes; beam > 0 tries only
+// that many children per node (all otherwise, which makes the search exact
+// when it completes).
+BnbResult bnb_order(const Graph& g0, const std::vector<char>& removed, const std::vector<int>& init,
+                    long max_nodes, int beam) {
+  BnbResult res;
+  res.order = init;
+  res.cost = order_cost(g0, init, removed);
+  Graph g = g0;
+  std::vector<char> alive(g.n, 0);
+  int left = 0;
+  for (int v = 0; v < g.n; ++v) {
+    if (removed[v]) {
+      drop(g, v);
+    } else {
+      alive[v] = 1;
+      ++left;
+    }
+  }
+  auto better = [](int w, double c, const OrderCost& b) { return w < b.width || (w == b.width && c < b.cost); };
+  std::vector<int> path;
+  path.reserve(left);
+  long nodes = 0;
+  bool stopped = false;
+  std::function<void(Graph&, int, double, int)> dfs = [&](Graph& cur, int width, double cost, int remaining) {
+    if (stopped) return;
+    if (++nodes > max_nodes) {
+      stopped = true;
+      return;
+    }
+    if (remaining == 0) {
+      if (better(width, cost, res.cost)) {
+        res.cost = OrderCost{cost, width};
+        res.order = path;
+      }
+      return;
+    }
+    const int lbw = std::max(width, minor_min_width(cur, alive));
+    // every remaining step costs at least 2^0, one of them at least 2^lbw
+    const double lbc = cost + std::max((double)remaining, std::ldexp(1.0, lbw) + remaining - 1);
+    if (!better(lbw, lbc, res.cost)) return;
+    std::vector<std::pair<long, int>> kids;
+    for (int v = 0; v < cur.n; ++v)
+      if (alive[v]) kids.push_back({(long)fill_in(cur, v) * 4096 + popcount_row(cur.row(v), cur.words), v});
+    std::sort(kids.begin(), kids.end());
+    if (beam > 0 && (int)kids.size() > beam) kids.resize(beam);
+    for (auto& kv : kids) {
+      const int v = kv.second;
+      Graph next = cur;
+      const int d = eliminate(next, v);
+      alive[v] = 0;
+      path.push_back(v);
+      if (better(std::max(width, d), cost + std::ldexp(1.0, d), res.cost)) dfs(next, std::max(width, d),
+                                                                                 cost + std::ldexp(1.0, d),
+                                                                                 remaining - 1);
+      path.pop_back();
+      alive[v] = 1;
+      if (stopped) return;
+    }
+  };
+  dfs(g, 0, 0.0, left);
+  res.nodes = std::min(nodes, max_nodes);
+  res.complete = !stopped;
+  return res;
 }
 
 }  // namespace qgm
@@ -390,7 +510,20 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
   }
   double b1 = k_req == 0 ? 0.0 : time_budget_s * 0.6;
   const int objective = (flags & 4) ? OBJ_LATENCY : (flags & 2) ? OBJ_BYTES : OBJ_COST;
-  std::vector<int> order1 = best_order(g, removed, seed + 17, b1, nullptr, objective, &net, &vov, det);
+  const bool bnb = (flags & 128) != 0 && objective == OBJ_COST;
+  if (bnb && k_req == 0) b1 = time_budget_s;  // the whole budget goes to the final ordering
+  std::vector<int> order1 = best_order(g, removed, seed + 17, bnb ? b1 / 2 : b1, nullptr, objective, &net, &vov, det);
+  if (bnb) {
+    // QGM_PLAN_BNB: branch and bound from the best min-fill ordering, a
+    // node count in proportion to the other half of the budget (so the
+    // same on every host); beam of 3 children per node on large graphs
+    constexpr double kBnbNodesPerSecond = 200.0;
+    int left = 0;
+    for (int v = 0; v < g.n; ++v) left += !removed[v];
+    const long nodes = std::max(1L, (long)(b1 / 2 * kBnbNodesPerSecond));
+    BnbResult r = bnb_order(g, removed, order1, nodes, left <= 20 ? 0 : 3);
+    order1 = r.order;
+  }
   sliced_vars.clear();
   for (int p : picks) sliced_vars.push_back(net.free_vars[p]);
   order_vars.clear();

@@ -156,14 +156,34 @@ bool matrix_core_shape(const Step& st) {
 
 bool compile_program(const Network& net, const std::vector<int>& sliced, const std::vector<int>& order,
                      Program& prog, std::string& err, int& code, bool gradient, bool combine_consts,
-                     int checkpoint_every) {
+                     int checkpoint_every, const std::vector<int>& open_qubits) {
   prog = Program();
   if (!validate_plan(net, sliced, order, err, code)) return false;
   const int nvars = (int)net.vars.size();
+  // Open outputs: the output variables of these qubits are neither fixed
+  // nor summed; the final product keeps them, bit i of its element index
+  // being the output of open_qubits[i] (2^j amplitudes per contraction).
+  std::vector<char> is_open(nvars, 0);
+  std::vector<int> open_vars;
+  for (int q : open_qubits) {
+    if (q < 0 || q >= net.n_qubits || net.output_var[q] < 0 || is_open[net.output_var[q]]) {
+      err = "open qubit " + std::to_string(q) + " is out of range, repeated, or has no variable of its own";
+      code = -1;
+      return false;
+    }
+    is_open[net.output_var[q]] = 1;
+    open_vars.push_back(net.output_var[q]);
+  }
+  if (!open_vars.empty() && gradient) {
+    err = "open outputs and gradients cannot be combined";
+    code = -7;
+    return false;
+  }
+  prog.n_open = (int)open_vars.size();
   std::vector<int> fixed_src(nvars, -1), fixed_bit(nvars, -1);
   for (int q = 0; q < net.n_qubits; ++q) {
     int v = net.output_var[q];
-    if (v >= 0) {
+    if (v >= 0 && !is_open[v]) {
       fixed_src[v] = 0;
       fixed_bit[v] = q;
     }
@@ -408,7 +428,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
         }
       S.clear();
       out.clear();
-      for (int u : vv) (cnt_in[u] == count[u] ? S : out).push_back(u);
+      for (int u : vv) (cnt_in[u] == count[u] && !is_open[u] ? S : out).push_back(u);
       std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
       std::sort(S.begin(), S.end(), [&](int a, int b) { return pos[a] < pos[b]; });
     };
@@ -508,7 +528,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
         for (int w : un) {
           const int c_in = (int)(std::find(T[ba].vars.begin(), T[ba].vars.end(), w) != T[ba].vars.end()) +
                            (int)(std::find(T[bb].vars.begin(), T[bb].vars.end(), w) != T[bb].vars.end());
-          (c_in == count[w] ? p_sum : p_out).push_back(w);
+          (c_in == count[w] && !is_open[w] ? p_sum : p_out).push_back(w);
         }
         std::sort(p_out.begin(), p_out.end(), [&](int x, int y) { return pos[x] < pos[y]; });
         std::sort(p_sum.begin(), p_sum.end(), [&](int x, int y) { return pos[x] < pos[y]; });
@@ -540,14 +560,16 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   std::vector<int> rest;
   for (size_t i = 0; i < T.size(); ++i) {
     if (!T[i].alive) continue;
-    if (!T[i].vars.empty()) {
+    bool only_open = true;
+    for (int u : T[i].vars) only_open = only_open && is_open[u];
+    if (!only_open) {
       err = "internal: variable left after elimination";
       code = -3;
       return false;
     }
     rest.push_back((int)i);
   }
-  emit(ST_FINAL, rest, {}, {}, false, -1, two_tab, n_two);
+  emit(ST_FINAL, rest, open_vars, {}, false, -1, two_tab, n_two);
   const std::vector<int> fwd_steps = elim_created;  // forward tensors, creation order
 
   // ---- reverse mode (gradient programs)

@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(256) wide_step_kernel(const int* __restrict__ 
     }
     if (kind == ST_ELIM)
       gmem[(uint64_t)(out + c) * 64 + lane] = acc;
-    else if (kind == ST_FINAL) {
-      if (valid) res[sl * (uint64_t)n_bs + b] = acc;
+    else if (kind == ST_FINAL) {  // rank r: 2^r amplitudes per item (open outputs)
+      if (valid) res[((sl * (uint64_t)n_bs + b) << r) + c] = acc;
     } else if (kind == ST_GRAD) {
       if (valid) gres[((uint64_t)slot * n_s + sl) * (uint64_t)n_bs + b] = acc;
     }

@@ -425,3 +425,78 @@ def test_8x8x40_gradient_plan_compiles(monkeypatch):
     ck = q.Plan(c, rec["sliced"], rec["order"], gradient=True, prec=q.QGM_C64, checkpoint_every=8,
                 engine=q.QGM_ENGINE_WIDE).stats()
     assert ck["item_elems"] <= 0.5 * full["item_elems"]
+
+
+def test_open_output_plans_compile():
+    """opts.open_qubits: plans keep those outputs open on every engine, the
+    final step has rank j, and 2^j amplitudes cost less than 2^j runs."""
+    text = generate_circuit(5, 20, 0)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=6, time_budget_s=0.2, flags=q.QGM_PLAN_DETERMINISTIC)
+    closed = q.Plan(c, sl, order, engine=q.QGM_ENGINE_INTERPRETER).stats()
+    for eng in (q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED, q.QGM_ENGINE_WIDE):
+        st = q.Plan(c, sl, order, prec=q.QGM_C64, engine=eng, open_qubits=[3, 7, 12]).stats()
+        assert st["n_open"] == 3 and st["engine"] == eng
+    op = q.Plan(c, sl, order, engine=q.QGM_ENGINE_INTERPRETER, open_qubits=[3, 7, 12]).stats()
+    assert closed["flops_item"] < op["flops_item"] < 8 * closed["flops_item"]
+
+
+def _small_circuit(seed, n_sx=9):
+    """3 qubits: H layer, then CZ and SX / SY gates at random, enough to give
+    about n_sx free variables."""
+    rng = np.random.default_rng(seed)
+    lines = ["qubits 3"] + [f"0 H {qb}" for qb in range(3)]
+    cyc = 1
+    placed = 0
+    while placed < n_sx:
+        a, b = rng.choice(3, 2, replace=False)
+        lines.append(f"{cyc} CZ {a} {b}")
+        cyc += 1
+        qb = int(rng.integers(3))
+        lines.append(f"{cyc} {'SX' if rng.integers(2) else 'SY'} {qb}")
+        cyc += 1
+        placed += 1
+    return "\n".join(lines)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_order_search_is_exact_on_small_graphs(seed):
+    """qgm_order_search with all children tried and a complete search gives
+    the best (width, sum 2^deg) over every ordering, found here by brute
+    force with the oracle's own cost function."""
+    import itertools
+    text = _small_circuit(seed)
+    c = q.Circuit(text)
+    net = build_network(text)
+    outs = [v.id for v in net.variables if v.is_output]
+    edges = net.graph_edges(exclude=outs)
+    free = net.free_vars
+    assert 6 <= len(free) <= 9
+    best = None
+    for perm in itertools.permutations(free):
+        cost, width = oracle_order_cost(free, edges, list(perm))
+        if best is None or (width, cost) < best:
+            best = (width, cost)
+    init = list(reversed(free))  # a poor first incumbent
+    order, cost, width, complete = q.qgm_order_search(c.h, [], init, 10 ** 7, beam=0)
+    assert complete and sorted(order) == sorted(free)
+    assert (width, cost) == best
+    assert oracle_order_cost(free, edges, order) == (cost, width)
+
+
+def test_order_search_anytime_and_planner_flag():
+    """On a large graph the search is anytime: never worse than its
+    incumbent, and the QGM_PLAN_BNB plans are valid and deterministic."""
+    text = generate_circuit(6, 25, 0)
+    c = q.Circuit(text)
+    sl, order = c.plan_slices(k_req=4, time_budget_s=0.2, flags=q.QGM_PLAN_DETERMINISTIC)
+    c0, w0 = q.qgm_order_cost(c.h, sl, order)
+    o2, c2, w2, complete = q.qgm_order_search(c.h, sl, order, 300, beam=3)
+    assert not complete and (w2, c2) <= (w0, c0)
+    assert q.qgm_order_cost(c.h, sl, o2) == (c2, w2)
+    f = q.QGM_PLAN_BNB | q.QGM_PLAN_DETERMINISTIC
+    a = c.plan_slices(k_req=4, time_budget_s=1.0, flags=f)
+    b = c.plan_slices(k_req=4, time_budget_s=1.0, flags=f)
+    assert a == b
+    net = build_network(text)
+    assert sorted(a[1] + a[0]) == sorted(net.free_vars)
