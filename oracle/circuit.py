@@ -7,8 +7,8 @@ of one- and two-qubit gates (Eq. (1)).  Text format, one gate per line::
     grid R C                       (optional, informational)
     <cycle> <GATE> <q0> [<q1>] [<param_index>]
 
-GATE in {H, CZ, T, SX, SY, RZ, I}; CZ has two qubits, RZ one qubit and a
-parameter index.  Gates are applied in ascending cycle, and within a cycle
+GATE in {H, CZ, T, SX, SY, RZ, I, CX, ISWAP, SQISW}; CZ, CX, ISWAP and
+SQISW have two qubits (q0 first), RZ one qubit and a parameter index.  Gates are applied in ascending cycle, and within a cycle
 in the order written (they act on distinct qubits, so they commute).
 """
 from __future__ import annotations
@@ -16,6 +16,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 ONE_QUBIT = {"H", "T", "SX", "SY", "I"}
+TWO_QUBIT = {"CZ", "CX", "ISWAP", "SQISW"}
 
 
 @dataclass
@@ -48,12 +49,12 @@ def parse_circuit(text: str) -> Circuit:
             continue
         cyc = int(tok[0])
         name = tok[1]
-        if name == "CZ":
+        if name in TWO_QUBIT:
             if len(tok) != 4:
-                raise ValueError(f"line {lineno}: CZ needs two qubits")
+                raise ValueError(f"line {lineno}: {name} needs two qubits")
             qs = (int(tok[2]), int(tok[3]))
             if qs[0] == qs[1]:
-                raise ValueError(f"line {lineno}: CZ on one qubit")
+                raise ValueError(f"line {lineno}: {name} on one qubit")
             g = Gate(cyc, name, qs)
         elif name == "RZ":
             if len(tok) != 4:

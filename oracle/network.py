@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .circuit import Circuit, parse_circuit
-from .gates import gate_matrix
+from .gates import TWO_QUBIT_NONDIAG, gate_matrix
 
 INPUT = -1  # marker for the constant input index i_0 = 0
 
@@ -106,6 +106,21 @@ def build_network(circuit, params=None) -> Network:
                 net.param_var[g.param] = cur[q]
             vs, t = _restrict((cur[q],), d, fixed_input)
             net.factors.append((vs, t))
+        elif g.name in TWO_QUBIT_NONDIAG:
+            # a two-qubit gate that is not diagonal: a new variable on each
+            # qubit (the lower qubit's first) and one factor over the two new
+            # and the two old variables (the K4 gadget of Fig. "tensornodes")
+            a, b = g.qubits
+            new = {}
+            for q in sorted((a, b)):
+                v = len(net.variables)
+                net.variables.append(Variable(v, q, g.cycle))
+                new[q] = v
+            u = gate_matrix(g.name).reshape(2, 2, 2, 2)  # [out b, out a, in b, in a]
+            table = np.transpose(u, (1, 0, 3, 2))  # [out a, out b, in a, in b]
+            vs, t = _restrict((new[a], new[b], cur[a], cur[b]), table, fixed_input)
+            net.factors.append((vs, t))
+            cur[a], cur[b] = new[a], new[b]
         else:  # H, SX, SY: new variable
             q = g.qubits[0]
             v = len(net.variables)

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 
 from .circuit import Circuit, parse_circuit
-from .gates import gate_matrix
+from .gates import TWO_QUBIT_NONDIAG, gate_matrix
 
 
 def _apply_1q(psi: np.ndarray, n: int, q: int, u: np.ndarray) -> np.ndarray:
@@ -35,6 +35,21 @@ def _apply_cz(psi: np.ndarray, n: int, a: int, b: int) -> None:
     v[:, 1, :, 1, :] *= -1.0
 
 
+def _apply_2q(psi: np.ndarray, n: int, a: int, b: int, u: np.ndarray) -> np.ndarray:
+    """u is 4 x 4 over index bit(a) + 2 bit(b), [out, in]."""
+    t = psi.reshape([2] * n)  # axis n - 1 - q is qubit q
+    ax_a, ax_b = n - 1 - a, n - 1 - b
+    t = np.moveaxis(t, (ax_a, ax_b), (-2, -1))  # [..., bit a, bit b]
+    shp = t.shape
+    v = t.reshape(-1, 2, 2)
+    # flat index bit(a) + 2 bit(b) -> [bit b][bit a]
+    u4 = u.reshape(2, 2, 2, 2)  # [out b, out a, in b, in a]
+    w = np.einsum("yxvu,nuv->nxy", u4, v)  # v[n, a, b]; result [n, out a, out b]
+    t = w.reshape(shp)
+    t = np.moveaxis(t, (-2, -1), (ax_a, ax_b))
+    return np.ascontiguousarray(t).reshape(-1)
+
+
 def sv_state(circuit, params=None) -> np.ndarray:
     """Full output state C|0...0> as a complex128 vector of length 2^N."""
     c = parse_circuit(circuit) if isinstance(circuit, str) else circuit
@@ -45,6 +60,8 @@ def sv_state(circuit, params=None) -> np.ndarray:
     for g in c.gates:
         if g.name == "CZ":
             _apply_cz(psi, n, g.qubits[0], g.qubits[1])
+        elif g.name in TWO_QUBIT_NONDIAG:
+            psi = _apply_2q(psi, n, g.qubits[0], g.qubits[1], gate_matrix(g.name))
         elif g.name in ("T", "I", "RZ"):
             theta = None if g.param < 0 else float(params[g.param])
             m = gate_matrix(g.name, theta)

@@ -398,3 +398,89 @@ def test_porter_thomas_second_moment():
     p = (2.0 ** 16) * np.abs(psi) ** 2
     assert abs(p.mean() - 1.0) < 1e-12
     assert abs((p ** 2).mean() - 2.0) < 0.1
+
+
+# ---------------------------------------------- two-qubit non-diagonal gates
+def _random_2q_circuit(seed, n=4, cycles=10, gate="CX"):
+    rng = np.random.default_rng(seed)
+    lines = [f"qubits {n}"] + [f"0 H {q}" for q in range(n)]
+    for cyc in range(1, cycles + 1):
+        a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+        lines.append(f"{2 * cyc - 1} {gate} {a} {b}")
+        q = int(rng.integers(n))
+        lines.append(f"{2 * cyc} {['SX', 'SY', 'T'][int(rng.integers(3))]} {q}")
+    return "\n".join(lines)
+
+
+def _expand(text, rule):
+    """Replace each two-qubit gate line by the lines rule(a, b) returns, the
+    cycles renumbered so every replacement gate gets a cycle of its own."""
+    out, cyc = [], 0
+    for line in text.splitlines():
+        tok = line.split()
+        if tok[0] == "qubits":
+            out.append(line)
+            continue
+        if len(tok) == 4 and tok[1] in ("CX", "ISWAP"):
+            for g in rule(int(tok[2]), int(tok[3])):
+                cyc += 1
+                out.append(f"{cyc} {g}")
+        else:
+            cyc += 1
+            out.append(f"{cyc} " + " ".join(tok[1:]))
+    return "\n".join(out)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cx_is_h_cz_h(seed):
+    """CX(a -> b) = (H on b) CZ(a, b) (H on b): the gadget of a non-diagonal
+    two-qubit gate against one-qubit gadgets and the diagonal CZ."""
+    text = _random_2q_circuit(seed, cycles=6, gate="CX")
+    ref = _expand(text, lambda a, b: [f"H {b}", f"CZ {a} {b}", f"H {b}"])
+    xs = [tuple((i >> q) & 1 for q in range(4)) for i in range(16)]
+    want = oracle.sv_amplitudes(ref, xs)
+    assert np.max(np.abs(oracle.sv_amplitudes(text, xs) - want)) < 1e-14
+    for x in xs[:4]:
+        assert abs(oracle.ve_amplitude(text, x) - want[xs.index(x)]) < 1e-14
+        assert abs(oracle.brute_amplitude(text, x) - want[xs.index(x)]) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_iswap_is_sqisw_twice(seed):
+    text = _random_2q_circuit(seed, gate="ISWAP")
+    ref = _expand(text, lambda a, b: [f"SQISW {a} {b}", f"SQISW {a} {b}"])
+    xs = [tuple((i >> q) & 1 for q in range(4)) for i in range(16)]
+    assert np.max(np.abs(oracle.sv_amplitudes(text, xs) - oracle.sv_amplitudes(ref, xs))) < 1e-14
+    for x in xs[::5]:
+        assert abs(oracle.ve_amplitude(text, x) - oracle.ve_amplitude(ref, x)) < 1e-14
+
+
+def test_two_qubit_gates_closed_forms():
+    """Worked by hand: SX SX = X on qubit 0, then CX(0 -> 1) gives |11>;
+    ISWAP on |q0 = 1, q1 = 0> gives i |q0 = 0, q1 = 1>; SQISW on |00> keeps
+    it."""
+    xs = [(a, b) for b in (0, 1) for a in (0, 1)]  # (x0, x1)
+    for route in ("sv", "ve", "brute"):
+        def amp(text, x):
+            if route == "sv":
+                return oracle.sv_amplitudes(text, [x])[0]
+            return (oracle.ve_amplitude if route == "ve" else oracle.brute_amplitude)(text, x)
+        t1 = "qubits 2\n0 SX 0\n1 SX 0\n2 CX 0 1\n"
+        assert [amp(t1, x) for x in xs] == pytest.approx([0, 0, 0, 1], abs=1e-15)
+        t2 = "qubits 2\n0 SX 0\n1 SX 0\n2 ISWAP 0 1\n"
+        assert [amp(t2, x) for x in xs] == pytest.approx([0, 0, 1j, 0], abs=1e-15)
+        t3 = "qubits 2\n0 SQISW 0 1\n"
+        assert [amp(t3, x) for x in xs] == pytest.approx([1, 0, 0, 0], abs=1e-15)
+
+
+def test_two_qubit_gadget_is_k4():
+    """A two-qubit gate that is not diagonal creates a variable on each of its
+    qubits and one factor over the new and the old variables: in the graph
+    the four form a clique (Fig. "tensornodes")."""
+    text = "qubits 2\n0 H 0\n0 H 1\n1 ISWAP 0 1\n2 SX 0\n3 SX 1\n"
+    net = build_network(text)
+    # H: 0, 1; ISWAP: 2 (qubit 0), 3 (qubit 1); SX: 4, 5 (outputs)
+    assert [(v.id, v.qubit) for v in net.variables] == [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0), (5, 1)]
+    edges = net.graph_edges()
+    assert {(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)} <= edges
+    assert (2, 4) in edges and (3, 5) in edges and (0, 4) not in edges
