@@ -24,9 +24,10 @@
  *   - Device workspace and HIP stream belong to the caller.
  *   - Bitstrings are bytes 0/1, row-major (n_bs rows of n_qubits); x[q] is
  *     the value of qubit q.  Amplitudes are FP64 (re, im) pairs.
- *   - Variable ids: variables are created by non-diagonal one-qubit gates
- *     taken by ascending cycle, then ascending qubit, and numbered 0, 1, ...
- *     in that order; the output variable of a qubit is its last variable.
+ *   - Variable ids: variables are created by non-diagonal gates taken by
+ *     ascending cycle, then ascending (lowest) qubit, and numbered 0, 1, ...
+ *     in that order; a non-diagonal two-qubit gate creates two, the lower
+ *     qubit's first; the output variable of a qubit is its last variable.
  *   - Slice s fixes sliced_vars[j] to bit j of s.
  */
 #ifndef QGM_H
@@ -155,11 +156,15 @@ typedef struct {
  *   qubits N            (N <= 64)
  *   grid R C            (optional)
  *   <cycle> <GATE> <q0> [<q1>] [<param_index>]
- * GATE in {H, CZ, T, SX, SY, RZ, I}.  CZ takes two qubits, RZ one qubit and
- * a parameter index into the params array of the amplitude calls.  Gates of
- * one cycle must act on distinct qubits.  Matrices: H = [[1,1],[1,-1]]/sqrt2,
- * SX and SY the principal square roots of X and Y, T = diag(1, e^{i pi/4}),
- * RZ(t) = diag(e^{-it/2}, e^{it/2}), CZ = diag(1,1,1,-1).
+ * GATE in {H, CZ, T, SX, SY, RZ, I, CX, ISWAP, SQISW}.  CZ, CX, ISWAP and
+ * SQISW take two qubits, RZ one qubit and a parameter index into the params
+ * array of the amplitude calls.  Gates of one cycle must act on distinct
+ * qubits.  Matrices: H = [[1,1],[1,-1]]/sqrt2, SX and SY the principal square
+ * roots of X and Y, T = diag(1, e^{i pi/4}), RZ(t) = diag(e^{-it/2},
+ * e^{it/2}), CZ = diag(1,1,1,-1); CX has control q0 and target q1, ISWAP maps
+ * |01> to i|10> and |10> to i|01>, SQISW is its principal square root.  The
+ * non-diagonal two-qubit gates give one four-variable factor (two new
+ * variables, two old ones: the gadget of Fig. "tensornodes").
  * (Clock cycles C_1..C_d of Eq. (1); gates of Fig. 2 and Rule 3.)
  * Errors: QGM_E_ARG (null), QGM_E_PARSE (message names the line). */
 qgm_status qgm_circuit_parse(const char* text, size_t len, qgm_circuit** out);

@@ -20,6 +20,9 @@ bool gate_kind(const std::string& s, GateKind& k) {
   else if (s == "RZ") k = G_RZ;
   else if (s == "I") k = G_I;
   else if (s == "CZ") k = G_CZ;
+  else if (s == "CX") k = G_CX;
+  else if (s == "ISWAP") k = G_ISWAP;
+  else if (s == "SQISW") k = G_SQISW;
   else return false;
   return true;
 }
@@ -48,6 +51,30 @@ void nondiag_matrix(GateKind k, double u[2][2][2]) {
   } else {
     double m[2][2][2] = {{{0.5, 0.5}, {-0.5, -0.5}}, {{0.5, 0.5}, {0.5, 0.5}}};
     std::memcpy(u, m, sizeof(m));
+  }
+}
+
+bool two_qubit(GateKind k) { return k == G_CZ || k == G_CX || k == G_ISWAP || k == G_SQISW; }
+
+// Non-diagonal two-qubit gate matrices U[out][in], (re, im), over the index
+// bit(q0) + 2 bit(q1):
+//   CX: control q0, target q1, |c t> -> |c, t xor c>
+//   ISWAP: |01> -> i|10>, |10> -> i|01>, |00> and |11> unchanged
+//   SQISW: the square root of ISWAP, (1/sqrt 2)[[1, i], [i, 1]] on {|01>, |10>}
+void nondiag2_matrix(GateKind k, double u[4][4][2]) {
+  std::memset(u, 0, sizeof(double) * 32);
+  if (k == G_CX) {
+    for (int c = 0; c < 2; ++c)
+      for (int t = 0; t < 2; ++t) u[c + 2 * (t ^ c)][c + 2 * t][0] = 1.0;
+    return;
+  }
+  const double h = 0.70710678118654752440;
+  u[0][0][0] = u[3][3][0] = 1.0;
+  if (k == G_ISWAP) {
+    u[2][1][1] = u[1][2][1] = 1.0;
+  } else {
+    u[1][1][0] = u[2][2][0] = h;
+    u[2][1][1] = u[1][2][1] = h;
   }
 }
 
@@ -87,12 +114,12 @@ bool parse_circuit(const char* text, size_t len, Network& net, std::string& err)
     g.param = -1;
     if (!to_int(tok[0], g.cycle) || g.cycle < 0) return fail("bad cycle");
     if (tok.size() < 2 || !gate_kind(tok[1], g.kind)) return fail("unknown gate");
-    size_t want = (g.kind == G_CZ || g.kind == G_RZ) ? 4 : 3;
+    size_t want = (two_qubit(g.kind) || g.kind == G_RZ) ? 4 : 3;
     if (tok.size() != want) return fail("wrong number of fields for " + tok[1]);
     if (!to_int(tok[2], g.q0) || g.q0 < 0 || g.q0 >= nq) return fail("qubit out of range");
-    if (g.kind == G_CZ) {
+    if (two_qubit(g.kind)) {
       if (!to_int(tok[3], g.q1) || g.q1 < 0 || g.q1 >= nq) return fail("qubit out of range");
-      if (g.q1 == g.q0) return fail("CZ on a single qubit");
+      if (g.q1 == g.q0) return fail(tok[1] + " on a single qubit");
     } else if (g.kind == G_RZ) {
       if (!to_int(tok[3], g.param) || g.param < 0 || g.param > (1 << 24)) return fail("bad parameter index");
       net.n_params = std::max(net.n_params, g.param + 1);
@@ -152,6 +179,41 @@ void build_network(Network& net) {
         f.tab[2 * b + 1] = 0.0;
       }
       net.factors.push_back(f);
+    } else if (g.kind == G_CX || g.kind == G_ISWAP || g.kind == G_SQISW) {
+      // Not diagonal: a new variable on each qubit (the lower qubit's
+      // first) and one factor over the new and the old variables, U[new
+      // a, new b][old a, old b] (the K4 gadget of Fig. "tensornodes").  An
+      // old index that is still the input constant 0 is fixed at 0.
+      double m[4][4][2];
+      nondiag2_matrix(g.kind, m);
+      const int a = g.q0, b = g.q1;
+      int nv[2];
+      for (int q : {std::min(a, b), std::max(a, b)}) {
+        const int v = (int)net.vars.size();
+        net.vars.push_back(Var{v, q, g.cycle, 0});
+        nv[q == a ? 0 : 1] = v;
+      }
+      const int old[2] = {cur[a], cur[b]};
+      f.nv = 0;
+      f.var[f.nv++] = nv[0];
+      f.var[f.nv++] = nv[1];
+      int old_bit[2] = {-1, -1};  // position of the old variable in f.var, or -1 (fixed at 0)
+      for (int j = 0; j < 2; ++j)
+        if (old[j] >= 0) {
+          old_bit[j] = f.nv;
+          f.var[f.nv++] = old[j];
+        }
+      for (int e = 0; e < (1 << f.nv); ++e) {
+        const int out = (e & 1) + 2 * ((e >> 1) & 1);
+        int in = 0;
+        for (int j = 0; j < 2; ++j)
+          if (old_bit[j] >= 0) in |= ((e >> old_bit[j]) & 1) << j;
+        f.tab[2 * e] = m[out][in][0];
+        f.tab[2 * e + 1] = m[out][in][1];
+      }
+      net.factors.push_back(f);
+      cur[a] = nv[0];
+      cur[b] = nv[1];
     } else if (g.kind == G_I) {
       continue;  // identity: no factor
     } else if (g.kind == G_T || g.kind == G_RZ) {

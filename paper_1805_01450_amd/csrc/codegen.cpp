@@ -169,10 +169,13 @@ double step_cost(const Program& prog, const Step& st) {
     double c = 0;
     if (L.ndep == 0) return 0;
     for (int e = 0; e < (1 << st.r); ++e) {
-      const int base = L.table + ((e & 1) ? L.free_stride[0] : 0) + ((e & 2) ? L.free_stride[1] : 0);
-      const int alt = base + L.dep_stride[0] + (L.ndep > 1 ? L.dep_stride[1] : 0);
+      int base = L.table, alt = L.table;
+      for (int j = 0; j < L.nfree; ++j)
+        if ((e >> j) & 1) base += L.free_stride[j];
+      alt = base;
+      for (int j = 0; j < L.ndep; ++j) alt += L.dep_stride[j];
       c += (prog.raw[2 * base] != prog.raw[2 * alt] || prog.raw[2 * base + 1] != prog.raw[2 * alt + 1]) ? 2.0 : 0.0;
-      if (L.ndep > 1) c += 2.0;
+      c += 2.0 * (L.ndep - 1);
     }
     return c;
   }
@@ -492,19 +495,23 @@ std::string generate_chain_source(const Program& prog, int prec, int n_qubits, i
   auto emit_step = [&](Branch& br, const Step& st) {
     if (st.kind == ST_LEAF) {
       const Leaf& L = prog.leaves[st.leaf];
-      std::string d[2];
+      std::string d[4];
       for (int j = 0; j < L.ndep; ++j)
         d[j] = std::string("((") + (L.dep_src[j] ? "s" : "xb") + " >> " + std::to_string(L.dep_bit[j]) + ") & 1ull) != 0ull";
       for (int c = 0; c < (1 << st.r); ++c) {
-        int base = L.table + ((c & 1) ? L.free_stride[0] : 0) + ((c & 2) ? L.free_stride[1] : 0);
+        int base = L.table;
+        for (int j = 0; j < L.nfree; ++j)
+          if ((c >> j) & 1) base += L.free_stride[j];
         auto T = [&](int k) { return br.const_ref(k); };
-        std::string v;
-        if (L.ndep == 1) {
-          v = "sel(" + d[0] + ", " + T(base + L.dep_stride[0]) + ", " + T(base) + ")";
-        } else {
-          v = "sel(" + d[1] + ", sel(" + d[0] + ", " + T(base + L.dep_stride[0] + L.dep_stride[1]) + ", " +
-              T(base + L.dep_stride[1]) + "), sel(" + d[0] + ", " + T(base + L.dep_stride[0]) + ", " + T(base) + "))";
-        }
+        // the entry at the item's fixed bits: a select per fixed variable,
+        // the last one outermost
+        std::function<std::string(int, int)> pick = [&](int j, int off) -> std::string {
+          if (j < 0) return T(base + off);
+          return "sel(" + d[j] + ", " + pick(j - 1, off + L.dep_stride[j]) + ", " + pick(j - 1, off) + ")";
+        };
+        // (built before the statement: a table reference may first emit the
+        // declaration it needs)
+        const std::string v = pick(L.ndep - 1, 0);
         o << "  const C2 " << tvar(st.out_tid, c) << " = " << v << ";\n";
       }
       return;

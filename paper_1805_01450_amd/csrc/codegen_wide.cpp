@@ -556,20 +556,9 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const unsigned long long tiles = 1ull << (r - L);
       const unsigned long long nb = (tiles + 3) / 4;
       k.steps.push_back(si);
-      // Blocks are dealt to the XCDs round robin (block index mod 8), each
-      // XCD with its own L2.  With 8 or more blocks the step's range starts
-      // at a multiple of 8 and XCD x runs the x-th eighth of the tiles, so
-      // tiles that share operand rows (neighbours in the reuse order above)
-      // run on one XCD and find those rows in its L2.
-      const bool xcd = nb >= 8 && nb % 8 == 0;
-      if (xcd) k.blocks = (k.blocks + 7) & ~7ull;
       o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
-        << "  // step " << si << "\n";
-      if (xcd)
-        o << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
-          << "  const unsigned long long t = ((g & 7ull) * " << nb / 8 << "ull + (g >> 3)) * 4ull + wv;\n";
-      else
-        o << "  const unsigned long long t = (blk - " << k.blocks << "ull) * 4ull + wv;\n";
+        << "  // step " << si << "\n"
+        << "  const unsigned long long t = (blk - " << k.blocks << "ull) * 4ull + wv;\n";
       o << "  if (t >= " << tiles << "ull) return;\n";
       k.blocks += nb;
       // per-operand base offsets from the tile index
@@ -580,8 +569,8 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
             o << " + (long long)((t >> " << (k2 - L) << ") & 1ull) * " << rec[i][16 + perm[k2]] << "ll";
         if (rec[i][0] == WOP_LEAF)
           for (int d = 0; d < rec[i][2]; ++d)
-            o << " + (long long)(((" << (rec[i][3 + d] ? "s" : "xb") << " >> " << rec[i][5 + d] << ") & 1ull) * "
-              << rec[i][7 + d] << "ll)";
+            o << " + (long long)(((" << (rec[i][3 + d] ? "s" : "xb") << " >> " << rec[i][7 + d] << ") & 1ull) * "
+              << rec[i][11 + d] << "ll)";
         o << ";\n";
       }
       if (kind == ST_ELIM || kind == ST_FINAL) {
@@ -657,9 +646,6 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       o << "  return;\n  }\n";
     }
     o << "}\n";
-    // a multiple of 8 blocks per 64-item group keeps the XCD of a block
-    // index the same in every group row of the grid
-    if (k.blocks >= 8) k.blocks = (k.blocks + 7) & ~7ull;
     kernels.push_back(k);
   }
   // constant steps (no fixed variable): one thread per output element,

@@ -31,10 +31,11 @@ struct DevStep {
   int kind, out, r, ns, m, ops, leaf, grad_slot;
 };
 
+// A leaf: up to four free variables (strides fs) and four fixed ones
+// (source 0 = output bit, 1 = slice bit; bit; stride ds).
 struct DevLeaf {
-  int nfree, fs0, fs1, ndep;
-  int src0, bit0, ds0, src1;
-  int bit1, ds1, table, pad;
+  int nfree, ndep, table, pad;
+  int fs[4], src[4], bit[4], ds[4];
 };
 
 template <typename R>
@@ -161,17 +162,14 @@ __global__ void __launch_bounds__(64) chain_kernel(const DevStep* __restrict__ s
       if (st.kind == 0) {
         const DevLeaf L = leaves[st.leaf];
         int lane_off = 0;
-        if (L.ndep > 0) {
-          uint64_t w = L.src0 ? s : xb;
-          lane_off += (int)((w >> L.bit0) & 1) * L.ds0;
-        }
-        if (L.ndep > 1) {
-          uint64_t w = L.src1 ? s : xb;
-          lane_off += (int)((w >> L.bit1) & 1) * L.ds1;
+        for (int j = 0; j < L.ndep; ++j) {
+          const uint64_t w = L.src[j] ? s : xb;
+          lane_off += (int)((w >> L.bit[j]) & 1) * L.ds[j];
         }
         const int nc = 1 << st.r;
         for (int c = 0; c < nc; ++c) {
-          int off = L.table + lane_off + (c & 1) * L.fs0 + ((c >> 1) & 1) * L.fs1;
+          int off = L.table + lane_off;
+          for (int j = 0; j < L.nfree; ++j) off += ((c >> j) & 1) * L.fs[j];
           mem[(size_t)(st.out + c) * kLanes + lane] = cst[off];
         }
       } else {
@@ -412,8 +410,17 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
   std::vector<DevLeaf> dl(prog.leaves.size());
   for (size_t i = 0; i < prog.leaves.size(); ++i) {
     const Leaf& L = prog.leaves[i];
-    dl[i] = DevLeaf{L.nfree, L.free_stride[0], L.free_stride[1], L.ndep, L.dep_src[0], L.dep_bit[0],
-                    L.dep_stride[0], L.dep_src[1], L.dep_bit[1], L.dep_stride[1], L.table, 0};
+    DevLeaf d{};
+    d.nfree = L.nfree;
+    d.ndep = L.ndep;
+    d.table = L.table;
+    for (int j = 0; j < 4; ++j) {
+      d.fs[j] = j < L.nfree ? L.free_stride[j] : 0;
+      d.src[j] = j < L.ndep ? L.dep_src[j] : 0;
+      d.bit[j] = j < L.ndep ? L.dep_bit[j] : 0;
+      d.ds[j] = j < L.ndep ? L.dep_stride[j] : 0;
+    }
+    dl[i] = d;
   }
   auto up = [&](void** dst, const void* src, size_t bytes) -> int {
     HIP_OK(hipMalloc(dst, std::max<size_t>(bytes, 16)));

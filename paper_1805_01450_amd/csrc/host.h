@@ -9,7 +9,7 @@
 
 namespace qgm {
 
-enum GateKind { G_H = 0, G_SX, G_SY, G_T, G_RZ, G_I, G_CZ };
+enum GateKind { G_H = 0, G_SX, G_SY, G_T, G_RZ, G_I, G_CZ, G_CX, G_ISWAP, G_SQISW };
 
 struct Gate {
   int cycle;
@@ -25,14 +25,15 @@ struct Var {
   int id, qubit, cycle, is_output;
 };
 
-// A factor over at most two variables.  Table entry b = sum_j bit(var_j) << j.
+// A factor over at most four variables (four: the gadget of a two-qubit
+// gate that is not diagonal).  Table entry b = sum_j bit(var_j) << j.
 // param >= 0 marks an RZ(theta_param) diagonal whose table is made on the
 // device from the angle.
 struct Factor {
   int nv;
-  int var[2];
+  int var[4];
   int param;
-  double tab[8];  // re, im pairs
+  double tab[32];  // re, im pairs
 };
 
 struct Network {
@@ -90,13 +91,13 @@ enum : uint32_t { OP_CONST = 0x80000000u };
 
 struct Leaf {
   int factor;        // index into net.factors, or -1 for a delta(x_q, 0) leaf
-  int nfree;         // free variables (0..2)
-  int free_var[2];
-  int free_stride[2];
-  int ndep;          // fixed variables the table is indexed at (0..2)
-  int dep_src[2];    // 0 = output bit (qubit), 1 = slice bit
-  int dep_bit[2];
-  int dep_stride[2];
+  int nfree;         // free variables (0..4)
+  int free_var[4];
+  int free_stride[4];
+  int ndep;          // fixed variables the table is indexed at (0..4)
+  int dep_src[4];    // 0 = output bit (qubit), 1 = slice bit
+  int dep_bit[4];
+  int dep_stride[4];
   int table;         // element offset of the raw table in the constant area
 };
 

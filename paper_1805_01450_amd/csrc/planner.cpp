@@ -38,12 +38,13 @@ Graph model_graph(const Network& net, std::vector<int>& vertex_of_var) {
   for (size_t i = 0; i < net.free_vars.size(); ++i) vertex_of_var[net.free_vars[i]] = (int)i;
   Graph g;
   g.init((int)net.free_vars.size());
-  for (const Factor& f : net.factors) {
-    if (f.nv == 2) {
-      int a = vertex_of_var[f.var[0]], b = vertex_of_var[f.var[1]];
-      if (a >= 0 && b >= 0) g.add_edge(a, b);
-    }
-  }
+  // two variables are adjacent when a factor holds both (a clique per factor)
+  for (const Factor& f : net.factors)
+    for (int i = 0; i < f.nv; ++i)
+      for (int j = i + 1; j < f.nv; ++j) {
+        int a = vertex_of_var[f.var[i]], b = vertex_of_var[f.var[j]];
+        if (a >= 0 && b >= 0) g.add_edge(a, b);
+      }
   return g;
 }
 

@@ -2,9 +2,9 @@
 //
 // Operand record (kWideOpInts int32):
 //   [0] kind (WOP_ITEM, WOP_CONST, WOP_LEAF)   [1] base element offset
-//   [2] number of fixed-bit dependencies (leaves)
-//   [3..4] dependency source (0 = output bit, 1 = slice bit)
-//   [5..6] dependency bit   [7..8] dependency stride in the table
+//   [2] number of fixed-bit dependencies (leaves, at most 4)
+//   [3..6] dependency source (0 = output bit, 1 = slice bit)
+//   [7..10] dependency bit   [11..14] dependency stride in the table
 //   [16 .. 16+32) stride per output bit of the step
 //   [48 .. 48+16) stride per summed bit of the step
 // Element offset of an operand at output index c and summed index s:
@@ -39,8 +39,8 @@ bool encode_wide(const Program& prog, WideProgram& wide, std::string& err) {
         rec[2] = L.ndep;
         for (int j = 0; j < L.ndep; ++j) {
           rec[3 + j] = L.dep_src[j];
-          rec[5 + j] = L.dep_bit[j];
-          rec[7 + j] = L.dep_stride[j];
+          rec[7 + j] = L.dep_bit[j];
+          rec[11 + j] = L.dep_stride[j];
         }
         for (size_t j = 0; j < o.vars.size(); ++j) stride_of[j] = L.free_stride[j];
       } else {

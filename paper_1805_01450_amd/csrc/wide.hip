@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) wide_step_kernel(const int* __restrict__ 
           long long d = 0;
           for (int j = 0; j < op[2]; ++j) {
             const uint64_t w = op[3 + j] ? s : xb;
-            d += (long long)((w >> op[5 + j]) & 1) * op[7 + j];
+            d += (long long)((w >> op[7 + j]) & 1) * op[11 + j];
           }
           v = cst[off + d];
         }

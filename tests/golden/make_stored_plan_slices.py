@@ -18,6 +18,7 @@ method like any caller's order).
   slice identity d alpha_s / d theta_j of a seeded subset of 16 angles.
 
     python tests/golden/make_stored_plan_slices.py [--only NAME ...]
+    python tests/golden/make_stored_plan_slices.py --whole 8x8x40-k8 --workers 6 --state FILE
 
 Values are stored as JSON floats (repr, exact round trip).
 """
@@ -151,10 +152,63 @@ def config4_entry(log):
     return out
 
 
+def _whole_slice(job):
+    name, s, max_width = job
+    global MAX_WIDTH
+    MAX_WIDTH = max_width
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+    rec = load_plan(name)
+    c = rec["circuit"]
+    text = generate_circuit(c["n"], c["depth"], c["seed"])
+    x = random_bitstrings(c["n"] ** 2, 1, c["seed"] + 1000)[0]
+    v, _ = slice_value(text, x, build_network(text), rec["sliced"], rec["order"], s)
+    return s, [v.real, v.imag]
+
+
+def whole_entry(name, log, workers, state_path, max_width=26):
+    """The whole amplitude of a stored plan: every slice (each split so no
+    tensor exceeds 2^max_width entries), summed exactly.  Slice values are
+    kept in state_path as they finish, so an interrupted run resumes."""
+    import multiprocessing as mp
+    rec = load_plan(name)
+    done = {}
+    if state_path and os.path.exists(state_path):
+        with open(state_path) as f:
+            done = {int(k): v for k, v in json.load(f).items()}
+    todo = [s for s in range(1 << rec["k"]) if s not in done]
+    t0 = time.time()
+    with mp.get_context("fork").Pool(workers) as pool:
+        for s, v in pool.imap_unordered(_whole_slice, [(name, s, max_width) for s in todo]):
+            done[s] = v
+            if state_path:
+                with open(state_path, "w") as f:
+                    json.dump(done, f)
+            log(f"{name} whole: slice {s} done, {len(done)} of {1 << rec['k']} ({time.time() - t0:.0f} s)")
+    vals = [done[s] for s in range(1 << rec["k"])]
+    alpha = [math.fsum(v[0] for v in vals), math.fsum(v[1] for v in vals)]
+    c = rec["circuit"]
+    return {"circuit": c, "bitstring_seed": c["seed"] + 1000, "k": rec["k"], "alpha": alpha,
+            "slices": {str(s): done[s] for s in (0, (1 << rec["k"]) - 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", nargs="*", default=None, help="entries to (re)compute; others are kept")
+    ap.add_argument("--whole", default=None, help="stored plan whose whole amplitude is computed (all slices)")
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--state", default=None, help="file keeping finished slices of --whole (resumable)")
     args = ap.parse_args()
+    if args.whole:
+        data = {}
+        if os.path.exists(OUT):
+            with open(OUT) as f:
+                data = json.load(f)
+        data[args.whole + "-whole"] = whole_entry(args.whole, lambda m: print(m, flush=True), args.workers,
+                                                  args.state)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1)
+        return
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as f:

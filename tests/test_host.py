@@ -500,3 +500,33 @@ def test_order_search_anytime_and_planner_flag():
     assert a == b
     net = build_network(text)
     assert sorted(a[1] + a[0]) == sorted(net.free_vars)
+
+
+def _two_qubit_circuit(seed, n=9, cycles=14):
+    """H layer, then random CX / ISWAP / SQISW / CZ pairs and one-qubit gates."""
+    rng = np.random.default_rng(seed)
+    lines = [f"qubits {n}"] + [f"0 H {q}" for q in range(n)]
+    for cyc in range(1, cycles + 1):
+        a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+        lines.append(f"{2 * cyc - 1} {['CX', 'ISWAP', 'SQISW', 'CZ'][int(rng.integers(4))]} {a} {b}")
+        q = int(rng.integers(n))
+        lines.append(f"{2 * cyc} {['SX', 'SY', 'T'][int(rng.integers(3))]} {q}")
+    # a gate on an untouched qubit: its old index is still the input 0
+    lines.append(f"{2 * cycles + 1} CX 0 1")
+    return "\n".join(lines)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_two_qubit_gates_variables_and_graph_match_oracle(seed):
+    text = _two_qubit_circuit(seed)
+    c = q.Circuit(text)
+    net = build_network(text)
+    assert c.vars() == [(v.id, v.qubit, v.cycle, int(v.is_output)) for v in net.variables]
+    outs = [v.id for v in net.variables if v.is_output]
+    assert set(c.graph()) == net.graph_edges(exclude=outs)
+    sl, order = c.plan_slices(k_req=2, time_budget_s=0.1, flags=q.QGM_PLAN_DETERMINISTIC)
+    for eng in (q.QGM_ENGINE_INTERPRETER, q.QGM_ENGINE_GENERATED, q.QGM_ENGINE_WIDE):
+        assert q.Plan(c, sl, order, engine=eng).stats()["engine"] == eng
+    with pytest.raises(q.QgmError) as e:
+        q.Circuit("qubits 2\n0 CX 1 1\n")
+    assert e.value.status == -2 and "single qubit" in str(e.value)
