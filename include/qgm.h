@@ -438,13 +438,22 @@ const char* qgm_last_error(void);
  * QGM_E_UNSUPPORTED (precision, compile failure), QGM_E_HIP. */
 typedef struct qgm_contraction qgm_contraction;
 /* Tile parameters of a matrix-core step (see qgm_plan_tune_tiles):
- *   per: k steps per LDS stage, one block barrier each (power of two; BF16x3
- *     uses pairs, so at least 2);
+ *   per: k steps per LDS stage, one block barrier each (power of two; the
+ *     16-item BF16x3 forms use pairs, so at least 2; in the per-item BF16x3
+ *     form one step is four complex k, one 16 x 16 x 32 MFMA pair);
  *   lds_budget: bytes of LDS the operand ring may use (2..8 stages);
- *   jband: log2 of the j blocks that run next to each other on one XCD;
- *   layout: 0 = built-in (2 x 2 wavefront tiles when both sides have 5 or
- *     more bits), 1 = four 16-item groups per block, 2 = two i tiles x two
- *     item groups, 3 = two j tiles x two item groups. */
+ *   jband: log2 of the j blocks that run next to each other on one XCD
+ *     (16-item forms only);
+ *   layout: complex64, and BF16x3 steps that sum fewer than 2 bits: 0 =
+ *     built-in (2 x 2 wavefront tiles when both sides have 5 or more bits),
+ *     1 = four 16-item groups per block, 2 = two i tiles x two item groups,
+ *     3 = two j tiles x two item groups.  BF16x3: 0 = the per-item form
+ *     (one item per wavefront, up to 64 x 64 outputs of it), 4, 5, 6 = that
+ *     form with at most 32 rows, 32 columns, or both; 1 to 3 = the 16-item
+ *     forms above, 7 = their built-in choice.  In the per-item form jband 1
+ *     stores results straight from registers instead of through LDS.
+ *   Built in for BF16x3: the per-item form with two K steps per stage and
+ *   a 64 KiB ring when the step sums 5 or more bits, else layout 7. */
 typedef struct {
   int32_t per, lds_budget, jband, layout;
 } qgm_tile;

@@ -971,7 +971,7 @@ qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t 
   GUARD_BEGIN
   if (!out) return fail(QGM_E_ARG, "null argument");
   if (tile && (tile->per < 1 || tile->per > 16 || (tile->per & (tile->per - 1)) || tile->lds_budget < 1024 ||
-               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 3))
+               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 7))
     return fail(QGM_E_ARG, "tile parameters out of range");
   *out = nullptr;
   if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");
@@ -1166,32 +1166,61 @@ qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream
     while (nb > 0 && std::ldexp(64.0 * 8.0, nb) * (std::ldexp(1.0, key.ni + key.nk) + std::ldexp(1.0, key.nk + key.nj) +
                                                  std::ldexp(1.0, key.ni + key.nj)) > 8.0 * (1ull << 30))
       --nb;
-    // stage 1: block layout x k steps per stage; stage 2: ring budget x band
-    // BF16x3 keeps two k per stage: more pairs per stage hold more split
-    // operands live than two waves per SIMD have registers for, which the
-    // level kernels of a plan (every step of a level in one kernel) pay for
-    // even where a lone contraction does not
-    std::vector<int> pers = key.prec == QGM_BF16X3 ? std::vector<int>{2} : std::vector<int>{1, 2, 4};
     qgm_tile best{2, 53248, 2, 0};
     float best_ms = 0;
     bool have = false;
-    for (int layout = 0; layout < 4 && !st; ++layout)
-      for (int per : pers) {
-        if (per > (1 << key.nk)) continue;
-        qgm_tile t{per, 53248, 2, layout};
-        float ms = 0;
-        st = time_tile(key, nb, t, ms);
+    if (key.prec == QGM_BF16X3 && key.nk >= 2) {
+      // the per-item form: row / column tile (layouts 0, 4, 5, 6) x K steps
+      // per stage, and the 16-item forms (7 = built-in, 1 to 3); then the
+      // ring budget of the winner (the per-item block order has no band)
+      for (int layout : {0, 4, 5, 6})
+        for (int per : {1, 2}) {
+          if (st || 4 * per > (1 << key.nk)) continue;
+          qgm_tile t{per, 65536, 0, layout};
+          float ms = 0;
+          st = time_tile(key, nb, t, ms);
+          if (!st && (!have || ms < best_ms)) best = t, best_ms = ms, have = true;
+        }
+      for (int layout : {7, 1, 2, 3}) {
         if (st) break;
-        if (!have || ms < best_ms) best = t, best_ms = ms, have = true;
-      }
-    for (int lds : {53248, 81920, 114688})
-      for (int jb = 0; jb <= 3 && !st; ++jb) {
-        qgm_tile t{best.per, lds, jb, best.layout};
-        if (lds == 53248 && jb == 2) continue;  // timed in stage 1
+        qgm_tile t{2, 53248, 2, layout};
         float ms = 0;
         st = time_tile(key, nb, t, ms);
         if (!st && ms < best_ms) best = t, best_ms = ms;
       }
+      const bool per_item = best.layout == 0 || (best.layout >= 4 && best.layout <= 6);
+      for (int lds : per_item ? std::vector<int>{32768, 49152, 98304} : std::vector<int>{81920, 114688}) {
+        if (st) break;
+        qgm_tile t{best.per, lds, per_item ? 0 : best.jband, best.layout};
+        float ms = 0;
+        st = time_tile(key, nb, t, ms);
+        if (!st && ms < best_ms) best = t, best_ms = ms;
+      }
+    } else {
+      // stage 1: block layout x k steps per stage; stage 2: ring budget x
+      // band.  BF16x3 keeps two k per stage: more pairs per stage hold more
+      // split operands live than two waves per SIMD have registers for,
+      // which the level kernels of a plan (every step of a level in one
+      // kernel) pay for even where a lone contraction does not
+      std::vector<int> pers = key.prec == QGM_BF16X3 ? std::vector<int>{2} : std::vector<int>{1, 2, 4};
+      for (int layout = 0; layout < 4 && !st; ++layout)
+        for (int per : pers) {
+          if (per > (1 << key.nk)) continue;
+          qgm_tile t{per, 53248, 2, layout};
+          float ms = 0;
+          st = time_tile(key, nb, t, ms);
+          if (st) break;
+          if (!have || ms < best_ms) best = t, best_ms = ms, have = true;
+        }
+      for (int lds : {53248, 81920, 114688})
+        for (int jb = 0; jb <= 3 && !st; ++jb) {
+          qgm_tile t{best.per, lds, jb, best.layout};
+          if (lds == 53248 && jb == 2) continue;  // timed in stage 1
+          float ms = 0;
+          st = time_tile(key, nb, t, ms);
+          if (!st && ms < best_ms) best = t, best_ms = ms;
+        }
+    }
     if (st) break;
     table[key] = MfmaTile{best.per, best.lds_budget, best.jband, best.layout};
     ++*n_tuned;

@@ -11,7 +11,6 @@
 // an output row are independent and issued together.
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <sstream>
@@ -93,6 +92,267 @@ bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni
   return true;
 }
 
+// BF16x3 steps in the per-item 16 x 16 x 32 form (v_mfma_f32_16x16x32_bf16,
+// the full-rate bfloat16 shape of gfx950).  Its operands are one 16 x 16
+// GEMM tile of one matrix, so a wavefront owns one item: a block's four
+// wavefronts take four neighbouring items (a 32-byte piece of each operand
+// row) and the same TM x TN output tile of each (TM = 16 WM rows, TN = 16 WN
+// columns, up to 64 x 64).  Lane l of an operand holds row (A) or column
+// (B) l % 16 and eight consecutive k slots 8 (l / 16) .. 8 (l / 16) + 7; the
+// result register e of lane l is row 4 (l / 16) + e, column l % 16.
+// Complex k values map to slot groups: the 8 slots of lane group l / 16
+// belong to complex k = 4 t + l / 16 of K step t.  With x = hi + lo (hi and
+// lo rounded to bfloat16), the slots hold
+//   A:          (ar_hi, ai_hi, ar_lo, ai_lo, ar_hi, ai_hi, ar_lo, ai_lo)
+//   B for Cr:   (br_hi, -bi_hi, br_hi, -bi_hi, br_lo, -bi_lo, 0, 0)
+//   B for Ci:   (bi_hi,  br_hi, bi_hi,  br_hi, bi_lo,  br_lo, 0, 0)
+// so one MFMA pair forms, for four complex k, the six products hi*hi +
+// lo*hi + hi*lo of ar br - ai bi and of ar bi + ai br: the BF16x3 terms,
+// lo*lo dropped.  The A slots are the two pack-converts of the element,
+// used twice; the B slots cost four pack-converts.
+// Operand rows reach LDS through global_load_lds (16 bytes per lane = two
+// items) in a ring of P stages of K_u complex k; LDS row slot s (32 bytes,
+// four items) keeps its two item pairs swapped when bit 3 of s is set, so
+// the 16 rows a lane group reads land on 16 different 8-byte bank pairs.
+// Tiles are numbered with the four item quads of a 128-byte line fastest
+// (they read the same lines at the same time), then j tiles, i tiles, b
+// bits and the four lines of a row; each XCD takes a contiguous range.
+static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int out, int r, int ns,
+                             const int32_t* A, const int32_t* B, const std::vector<int>& bb, const std::vector<int>& bi,
+                             const std::vector<int>& bj, const MfmaTile& tp, bool from_table, int& lds_bytes) {
+  const int ni = (int)bi.size(), nj = (int)bj.size();
+  if (ni < 4 || nj < 4 || ns < 2) return false;
+  int WM = std::min(4, 1 << (ni - 4)), WN = std::min(4, 1 << (nj - 4));
+  if (tp.layout == 4) WM = std::min(WM, 2);
+  else if (tp.layout == 5) WN = std::min(WN, 2);
+  else if (tp.layout == 6) WM = std::min(WM, 2), WN = std::min(WN, 2);
+  const int nk = 1 << ns;
+  // complex k per stage: 4 per K step, times the table's steps per stage
+  // (at most the whole sum), and more when the copies of a stage do not
+  // split evenly over the four wavefronts (32 rows per copy); a short sum
+  // takes narrower tiles instead
+  auto min_ku = [&]() {
+    int v = 4;
+    while (((16 * (WM + WN)) * v / 32) % 4) v *= 2;
+    return v;
+  };
+  while (min_ku() > nk && (WM > 1 || WN > 1)) {
+    if (WM >= WN) WM /= 2;
+    else WN /= 2;
+  }
+  int ku = std::max(min_ku(), std::min(nk, 4 * std::max(1, std::min(4, from_table ? tp.per : 1))));
+  if (ku > nk) return false;
+  const int TM = 16 * WM, TN = 16 * WN;
+  const int li = 4 + (WM == 4 ? 2 : WM == 2 ? 1 : 0), lj = 4 + (WN == 4 ? 2 : WN == 2 ? 1 : 0);
+  const int nbi = ni - li, nbj = nj - lj, nbb = (int)bb.size();
+  // results from registers straight to HBM (table jband 1) or through LDS
+  const bool direct_stores = from_table && tp.jband == 1;
+  const int kub = ku == 4 ? 2 : ku == 8 ? 3 : ku == 16 ? 4 : 5;
+  const int nu = nk / ku;
+  const int stage = (TM + TN) * ku * 32;
+  const int n_ins = (TM + TN) * ku / 32, per_wave = n_ins / 4;
+  int P = std::max(2, std::min(8, (from_table ? tp.lds_budget : 65536) / stage));
+  P = std::min(P, 2 + 63 / std::max(1, per_wave));
+  if (P * stage > 163840) return false;
+  lds_bytes = P * stage;
+  // tile index bits, fastest first: item quads inside a 128-byte line, j
+  // tiles, i tiles, b bits, the line of the 512-byte row
+  std::vector<std::pair<int, int>> bits;  // (0 = j, 1 = i, 2 = b, 3 = item quad; bit)
+  bits.push_back({3, 0});
+  bits.push_back({3, 1});
+  for (int t = 0; t < nbj; ++t) bits.push_back({0, bj[lj + t]});
+  for (int t = 0; t < nbi; ++t) bits.push_back({1, bi[li + t]});
+  for (int t = 0; t < nbb; ++t) bits.push_back({2, bb[t]});
+  bits.push_back({3, 2});
+  bits.push_back({3, 3});
+  const unsigned long long nb = 1ull << bits.size();
+  k.blocks = (k.blocks + 7) & ~7ull;
+  o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
+    << "  // step " << si << " (matrix cores, per item) b " << nbb << " i " << ni << " j " << nj << " k " << ns << "\n"
+    << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
+    << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
+  k.blocks += nb;
+  k.steps.push_back(si);
+  k.mfma_steps += 1;
+  k.mfma_flops += 8.0 * (double)(1ull << (r + ns));
+  auto sum_of = [&](const std::function<long long(int, int)>& stride) {
+    std::string e;
+    for (size_t p = 0; p < bits.size(); ++p) {
+      if (bits[p].first == 3) continue;
+      const long long s = stride(bits[p].first, bits[p].second);
+      if (s) e += " + (long long)((tx >> " + std::to_string(p) + ") & 1ull) * " + std::to_string(s) + "ll";
+    }
+    return e;
+  };
+  const size_t qhi = bits.size() - 2;
+  auto idx_off = [&](const int32_t* X, const std::vector<int>& v, const std::string& x, int nbits) {
+    std::string e;
+    for (int t = 0; t < nbits; ++t)
+      e += " + (long long)(((" + x + ") >> " + std::to_string(t) + ") & 1) * " + std::to_string(X[16 + v[t]]) + "ll";
+    return e;
+  };
+  // k offset of the low kub bits (inside a stage) and of the stage index
+  auto koff = [&](const int32_t* X, const std::string& kv, int t0, int t1) {
+    std::string e;
+    for (int t = t0; t < t1 && t < ns; ++t)
+      e += " + (long long)(((" + kv + ") >> " + std::to_string(t - t0) + ") & 1) * " + std::to_string(X[48 + t]) + "ll";
+    return e;
+  };
+  o << "  const int lid = threadIdx.x & 63, w4 = (int)wv;\n"
+    << "  const long long itb = (long long)(((tx >> " << qhi << ") & 3ull) * 16ull + (tx & 3ull) * 4ull);\n"
+    << "  const long long ba = " << A[1] << "ll" << sum_of([&](int kd, int b) { return kd == 0 ? 0ll : (long long)A[16 + b]; })
+    << ";\n"
+    << "  const long long bbk = " << B[1] << "ll" << sum_of([&](int kd, int b) { return kd == 1 ? 0ll : (long long)B[16 + b]; })
+    << ";\n"
+    << "  const long long lo = " << out << "ll" << sum_of([&](int, int b) { return 1ll << b; }) << ";\n";
+  // copies: instruction c = 4 q + wave covers row slots 32 c .. 32 c + 31;
+  // lane l fills half l & 1 of slot 32 c + l / 2 with item pair
+  // (l & 1) ^ bit 3 of the slot.  Slots 0 .. ku TM - 1 are A rows (k major),
+  // then ku TN B rows.
+  for (int q = 0; q < per_wave; ++q) {
+    const std::string Q = std::to_string(q);
+    o << "  const int sl" << Q << " = " << 32 * 4 * q << " + 32 * w4 + (lid >> 1);\n"
+      << "  const bool isa" << Q << " = sl" << Q << " < " << ku * TM << ";\n"
+      << "  const int sr" << Q << " = isa" << Q << " ? sl" << Q << " : sl" << Q << " - " << ku * TM << ";\n"
+      << "  const int kl" << Q << " = isa" << Q << " ? sr" << Q << " / " << TM << " : sr" << Q << " / " << TN << ";\n"
+      << "  const int rw" << Q << " = isa" << Q << " ? sr" << Q << " % " << TM << " : sr" << Q << " % " << TN << ";\n"
+      << "  const long long eo" << Q << " = isa" << Q << " ? ba" << idx_off(A, bi, "rw" + Q, li) << koff(A, "kl" + Q, 0, kub)
+      << " : bbk" << idx_off(B, bj, "rw" + Q, lj) << koff(B, "kl" + Q, 0, kub) << ";\n"
+      << "  const long long src" << Q << " = itb + 2 * ((lid & 1) ^ ((sl" << Q << " >> 3) & 1));\n";
+  }
+  auto issue = [&](const std::string& unit, const std::string& stg) {
+    o << "    {\n"
+      << "    const long long ka = 0ll" << koff(A, unit, kub, ns) << ";\n"
+      << "    const long long kb = 0ll" << koff(B, unit, kub, ns) << ";\n";
+    for (int q = 0; q < per_wave; ++q) {
+      const std::string Q = std::to_string(q);
+      o << "    __builtin_amdgcn_global_load_lds((const void*)(gm + (eo" << Q << " + (isa" << Q
+        << " ? ka : kb)) * 64ll + src" << Q << "), (__attribute__((address_space(3))) void*)(lds + (" << stg << ") * "
+        << stage << " + " << 4 * 1024 * q << " + 1024 * w4), 16, 0, 0);\n";
+    }
+    o << "    }\n";
+  };
+  for (int f = 0; f < WM; ++f)
+    for (int g = 0; g < WN; ++g)
+      o << "  f32x4 cr" << f << "_" << g << " = {}, ci" << f << "_" << g << " = {};\n";
+  for (int s = 0; s < P - 1; ++s) issue(std::to_string(std::min(s, nu - 1)), std::to_string(s));
+  // lane read offsets: slot (4 t + l / 16) TM + 16 f + l % 16 of A, item pair
+  // w4 / 2 (swapped by bit 3 of l), item w4 & 1 of the pair
+  o << "  const int rdx = 32 * (lid & 15) + 16 * ((w4 >> 1) ^ ((lid >> 3) & 1)) + 8 * (w4 & 1);\n"
+    << "  const int rda = rdx + " << 32 * TM << " * (lid >> 4);\n"
+    << "  const int rdb = rdx + " << 32 * TN << " * (lid >> 4) + " << 32 * ku * TM << ";\n";
+  const int N = (P - 2) * per_wave;
+  const int wait_imm = (N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14);
+  o << "  for (int u = 0; u < " << nu << "; ++u) {\n"
+    << "    __builtin_amdgcn_s_waitcnt(" << wait_imm << ");\n"
+    << "    __asm__ volatile(\"\" ::: \"memory\");  // LDS reads of unit u - 1 stay above the barrier\n"
+    << "    __builtin_amdgcn_s_barrier();  // every wave's copies of unit u are in LDS\n"
+    << "    __asm__ volatile(\"\" ::: \"memory\");  // and this unit's reads below it\n"
+    << "    {\n"
+    << "    const int un = u + " << P - 1 << " < " << nu << " ? u + " << P - 1 << " : " << nu - 1 << ";\n";
+  issue("un", "(u + " + std::to_string(P - 1) + ") % " + std::to_string(P));
+  o << "    }\n"
+    << "    const char* sb = lds + (u % " << P << ") * " << stage << ";\n";
+  for (int t = 0; t < ku / 4; ++t) {
+    const std::string T = std::to_string(t);
+    for (int f = 0; f < WM; ++f) {
+      const std::string F = T + "_" + std::to_string(f);
+      o << "    const C2 a" << F << " = *(const C2*)(sb + rda + " << 32 * (4 * t * TM + 16 * f) << ");\n"
+        << "    const unsigned ap" << F << " = pk(a" << F << ".x, a" << F << ".y);\n"
+        << "    const unsigned al" << F << " = pk(a" << F << ".x - lowf(ap" << F << "), a" << F << ".y - highf(ap" << F
+        << "));\n"
+        << "    const bf16x8 A" << F << " = __builtin_bit_cast(bf16x8, (u32x4){ap" << F << ", al" << F << ", ap" << F
+        << ", al" << F << "});\n";
+    }
+    for (int g = 0; g < WN; ++g) {
+      const std::string G = T + "_" + std::to_string(g);
+      o << "    const C2 b" << G << " = *(const C2*)(sb + rdb + " << 32 * (4 * t * TN + 16 * g) << ");\n"
+        << "    const unsigned bq" << G << " = pk(b" << G << ".x, -b" << G << ".y);\n"
+        << "    const unsigned bs" << G << " = pk(b" << G << ".y, b" << G << ".x);\n"
+        << "    const float brl" << G << " = b" << G << ".x - lowf(bq" << G << "), bil" << G << " = b" << G
+        << ".y - lowf(bs" << G << ");\n"
+        << "    const bf16x8 R" << G << " = __builtin_bit_cast(bf16x8, (u32x4){bq" << G << ", bq" << G << ", pk(brl" << G
+        << ", -bil" << G << "), 0u});\n"
+        << "    const bf16x8 I" << G << " = __builtin_bit_cast(bf16x8, (u32x4){bs" << G << ", bs" << G << ", pk(bil" << G
+        << ", brl" << G << "), 0u});\n";
+    }
+    for (int f = 0; f < WM; ++f)
+      for (int g = 0; g < WN; ++g) {
+        const std::string C = std::to_string(f) + "_" + std::to_string(g);
+        const std::string F = T + "_" + std::to_string(f), G = T + "_" + std::to_string(g);
+        o << "    cr" << C << " = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A" << F << ", R" << G << ", cr" << C
+          << ", 0, 0, 0);\n"
+          << "    ci" << C << " = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A" << F << ", I" << G << ", ci" << C
+          << ", 0, 0, 0);\n";
+      }
+  }
+  o << "  }\n"
+    << "  __builtin_amdgcn_s_waitcnt(" << ((7 << 4) | (15 << 8)) << ");  // no copy left in flight\n";
+  // results: register e of tile (f, g) is row 16 f + 4 (l / 16) + e, column
+  // 16 g + l % 16, item itb + w4
+  auto fg_off = [&](int f, int g) {
+    long long off = 0;
+    if (f & 1) off += 1ll << bi[4];
+    if (f & 2) off += 1ll << bi[5];
+    if (g & 1) off += 1ll << bj[4];
+    if (g & 2) off += 1ll << bj[5];
+    return off;
+  };
+  if (!direct_stores) {
+    // Through LDS, ncb 16 x 16 tiles at a time: each wavefront writes its
+    // item's values as [element][4 items] (8 bytes each, item slot w4 ^
+    // ((element >> 3) & 3) so that a lane group's writes spread over the
+    // banks); then each thread stores 16 bytes (two items of one element),
+    // neighbouring threads the two halves of one element's 32-byte piece.
+    int ncb = 1;  // tiles per round: a power of two that divides WM WN
+    while (2 * ncb <= WM * WN && 2 * ncb * 8192 <= lds_bytes) ncb *= 2;
+    o << "  const int wre = 64 * (lid >> 4);\n"
+      << "  const int tt = threadIdx.x;\n"
+      << "  const long long seo = lo" << " + (long long)((tt >> 5) & 1) * " << (1ll << bi[0]) << "ll + (long long)((tt >> 6) & 1) * "
+      << (1ll << bi[1]) << "ll + (long long)((tt >> 7) & 1) * " << (1ll << bi[2]) << "ll";
+    for (int t = 0; t < 4; ++t) o << " + (long long)((tt >> " << t + 1 << ") & 1) * " << (1ll << bj[t]) << "ll";
+    o << ";\n"
+      << "  const long long sit = itb + 2 * ((tt & 1) ^ ((tt >> 5) & 1));\n"
+      << "  const bool sws = (tt >> 4) & 1;\n";
+    for (int c0 = 0; c0 < WM * WN; c0 += ncb) {
+      o << "  __syncthreads();\n";
+      for (int cb = 0; cb < ncb; ++cb) {
+        const int f = (c0 + cb) / WN, g = (c0 + cb) % WN;
+        const std::string C = std::to_string(f) + "_" + std::to_string(g);
+        for (int e = 0; e < 4; ++e)
+          o << "  *(C2*)(lds + ((" << 256 * cb + 16 * e << " + wre + (lid & 15)) * 4 + (w4 ^ ((" << 2 * e
+            << " + ((lid >> 3) & 1)) & 3))) * 8) = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+      }
+      o << "  __syncthreads();\n";
+      for (int it = 0; it < 2 * ncb; ++it) {
+        const int cb = it >> 1, f = (c0 + cb) / WN, g = (c0 + cb) % WN;
+        long long off = fg_off(f, g) + ((it & 1) ? 1ll << bi[3] : 0);
+        o << "  {\n"
+          << "  const f32x4 v = *(const f32x4*)(lds + " << 4096 * it << " + 16 * tt);\n"
+          << "  *(f32x4*)(gm + (seo + " << off << "ll) * 64ll + sit) = sws ? (f32x4){v[2], v[3], v[0], v[1]} : v;\n"
+          << "  }\n";
+      }
+    }
+  } else {
+    o << "  const long long so = lo" << " + (long long)((lid >> 4) & 1) * " << (1ll << bi[2]) << "ll + (long long)((lid >> 5) & 1) * "
+      << (1ll << bi[3]) << "ll";
+    for (int t = 0; t < 4; ++t) o << " + (long long)((lid >> " << t << ") & 1) * " << (1ll << bj[t]) << "ll";
+    o << ";\n"
+      << "  const long long sit = itb + w4;\n";
+    for (int f = 0; f < WM; ++f)
+      for (int g = 0; g < WN; ++g)
+        for (int e = 0; e < 4; ++e) {
+          long long off = fg_off(f, g);
+          if (e & 1) off += 1ll << bi[0];
+          if (e & 2) off += 1ll << bi[1];
+          const std::string C = std::to_string(f) + "_" + std::to_string(g);
+          o << "  gm[(so + " << off << "ll) * 64ll + sit] = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+        }
+  }
+  o << "  return;\n  }\n";
+  return true;
+}
+
 bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
                     const std::vector<const int32_t*>& rec, int& lds_bytes, const TileTable* tiles) {
   std::vector<int> bb, bi, bj;
@@ -103,10 +363,22 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   // choice (2 x 2 tiles of 16 items when both sides have 5 bits, two k per
   // unit, a ring of at most 52 KiB, bands of four j blocks).
   MfmaTile tp;
+  bool from_table = false;
   if (tiles) {
     auto it = tiles->find(TileKey{prec, (int)bi.size(), (int)bj.size(), ns});
-    if (it != tiles->end()) tp = it->second;
+    if (it != tiles->end()) tp = it->second, from_table = true;
   }
+  // BF16x3: the full-rate per-item form (table layouts 0, 4, 5, 6) or the
+  // 16-item forms (1, 2, 3; 7 = their built-in choice).  Built in: the
+  // per-item form, two K steps per stage, for sums of 32 or more k (on
+  // shorter sums, where the results' stores dominate, the 16-item forms
+  // store whole 128-byte lines and were as fast or faster).
+  if (prec == 2) {
+    const bool per_item = from_table ? tp.layout == 0 || (tp.layout >= 4 && tp.layout <= 6) : ns >= 5;
+    const MfmaTile t16 = from_table ? tp : MfmaTile{2, 65536, 0, 0};
+    if (per_item && emit_mfma16_step(o, k, si, out, r, ns, A, B, bb, bi, bj, t16, true, lds_bytes)) return true;
+  }
+  if (tp.layout >= 4) tp.layout = 0;
   int WI = bi.size() >= 5 ? 2 : 1, WJ = bj.size() >= 5 ? 2 : 1;
   if (tp.layout == 1) WI = WJ = 1;                                   // four item groups
   else if (tp.layout == 2 && bi.size() >= 5) WI = 2, WJ = 1;         // two i tiles x two item groups
@@ -349,7 +621,7 @@ bool read_tile_table(const std::string& path, TileTable& t, std::string& err) {
     int n = std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
     if (n <= 0) continue;  // blank or comment
     if (n != 8 || v[0] < 0 || v[0] > 2 || v[1] < 4 || v[2] < 4 || v[3] < 1 || v[3] > 16 || v[4] < 1 || v[4] > 16 ||
-        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 3) {
+        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 7) {
       err = "tile table " + path + " line " + std::to_string(ln) + ": expected prec ni nj nk per lds_budget jband layout";
       ok = false;
       break;
@@ -408,6 +680,9 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
          "static __device__ __forceinline__ unsigned pk(float a, float b) { "
          "return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2)); }\n"
          "static __device__ __forceinline__ float lowf(unsigned p) { return __uint_as_float(p << 16); }\n"
+         "static __device__ __forceinline__ float highf(unsigned p) { return __uint_as_float(p & 0xFFFF0000u); }\n"
+         "typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;\n"
+         "typedef unsigned u32x4 __attribute__((ext_vector_type(4)));\n"
          "static __device__ __forceinline__ s16x4 v4(unsigned lo, unsigned hi) { "
          "return __builtin_bit_cast(s16x4, (unsigned long long)lo | ((unsigned long long)hi << 32)); }\n"
          // A slots (rh rh rl ih | ih il) per k, k = p then q

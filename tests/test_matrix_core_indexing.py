@@ -144,7 +144,197 @@ def check_step(body, S, E, lds_size, group_c2, max_blocks=None):
     return nu
 
 
-STEP = re.compile(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores\)[^\n]*\n"
+COPY16 = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(gm \+ \(eo(\d+) \+ \(isa\d+ \? ka : kb\)\) \* 64ll "
+                    r"\+ src\d+\), \(__attribute__\(\(address_space\(3\)\)\) void\*\)\(lds \+ \((.*?)\) \* (\d+) \+ "
+                    r"(\d+) \+ 1024 \* w4\), 16, 0, 0\);")
+K_LINE = re.compile(r"const long long (ka|kb) = (.*);$")
+READ16 = re.compile(r"const C2 ([ab])(\d+)_(\d+) = \*\(const C2\*\)\(sb \+ (rda|rdb) \+ (\d+)\);$")
+
+
+def check_step16(body, S, E, lds_size, group_c2, max_blocks=None):
+    """The per-item form (one item per wavefront, 16 x 16 x 32 operands):
+    replays the ring and checks that lane l of wavefront w reads, for K step
+    t and row tile f (column tile g), the slot a copy of the same unit filled
+    with item itb + w, row 16 f + l % 16 (column 16 g + l % 16) and local k
+    4 t + l / 16, in both operands; copies and reads stay in bounds; every
+    (row, column) of the tile is stored once per item."""
+    lines = [l.strip() for l in body.split("\n")]
+    blocks = np.arange(S, E, dtype=np.int64)
+    if max_blocks is not None and E - S > max_blocks:
+        blocks = np.concatenate([blocks[:max_blocks // 2], blocks[-(max_blocks // 2):]])
+    blk = np.repeat(blocks, 256)
+    th = np.tile(np.arange(256, dtype=np.int64), len(blocks))
+    env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
+
+    def ev(e):
+        return np.asarray(eval(_py_expr(e), env)) + np.zeros_like(blk)
+
+    i_loop = next(i for i, l in enumerate(lines) if l.startswith("for (int u = 0;"))
+    for l in lines[:i_loop]:
+        m = re.match(r"const (?:unsigned long long|long long|unsigned|int|bool) (.*);$", l)
+        if m and not K_LINE.match(l):
+            for part in re.split(r", (?=[a-z]\w* = )", m.group(1)):
+                name, e = part.split(" = ", 1)
+                env[name.strip()] = ev(e)
+    nu = int(re.search(r"for \(int u = 0; u < (\d+); \+\+u\)", body).group(1))
+    m = re.search(r"const char\* sb = lds \+ \(u % (\d+)\) \* (\d+);", body)
+    P, stage = int(m.group(1)), int(m.group(2))
+    lid, w4 = env["lid"], env["w4"]
+    ring = {}
+    kk = {}
+
+    def copy(line, st, unit):
+        m = COPY16.match(line)
+        q_ = m.group(1)
+        isa = env["isa" + q_].astype(bool)
+        g = (env["eo" + q_] + np.where(isa, kk["ka"], kk["kb"])) * 64 + env["src" + q_]
+        lo = st * int(m.group(3)) + int(m.group(4)) + 1024 * w4 + 16 * lid
+        assert lo.min() >= 0 and lo.max() + 16 <= lds_size
+        assert g.min() >= 0 and g.max() + 1 < group_c2
+        meta = np.stack([isa.astype(np.int64), env["kl" + q_], env["rw" + q_]], 1)
+        ring.setdefault(st, []).append((unit, g, lo, meta))
+
+    loop = lines[i_loop:]
+    for l in lines[:i_loop]:  # prologue: literal unit and stage
+        mk = K_LINE.match(l)
+        if mk:
+            kk[mk.group(1)] = ev(mk.group(2))
+            unit = int(re.search(r"\(\(\((\d+)\) >> \d+\) & 1\)", mk.group(2)).group(1)) if "(((" in mk.group(2) else 0
+        if COPY16.match(l):
+            copy(l, int(COPY16.match(l).group(2)), unit)
+    body_copies = [l for l in loop if K_LINE.match(l) or l.startswith("__builtin_amdgcn_global_load_lds")]
+    reads = [l for l in loop if READ16.match(l)]
+    item = env["itb"] + w4
+    seen_k = {}
+    for u in range(nu):
+        env["u"] = u
+        env["un"] = min(u + P - 1, nu - 1)
+        st = u % P
+        slot = {}
+        for (un, g, lo, meta) in ring.get(st, []):
+            if un == u:
+                for c in range(2):
+                    for key, gg, mm in zip(zip(blk.tolist(), (lo + 8 * c).tolist()), (g + c).tolist(), meta.tolist()):
+                        slot[key] = (gg, mm)
+        for l in reads:
+            m = READ16.match(l)
+            ab, t, fg = m.group(1), int(m.group(2)), int(m.group(3))
+            off = env[m.group(4)] + int(m.group(5)) + st * stage
+            assert off.min() >= 0 and off.max() + 8 <= lds_size
+            got = [slot.get(k_, None) for k_ in zip(blk.tolist(), off.tolist())]
+            assert all(x is not None for x in got), "operand read of a slot this unit did not fill"
+            gidx = np.array([x[0] for x in got])
+            meta = np.array([x[1] for x in got])
+            assert ((gidx % 64) == item).all(), "operand read of another item"
+            assert (meta[:, 0] == (1 if ab == "a" else 0)).all(), "operand read of the other operand"
+            assert (meta[:, 1] == 4 * t + (lid >> 4)).all(), "k slot of another lane group"
+            assert (meta[:, 2] == 16 * fg + (lid & 15)).all(), "row or column of another lane"
+            seen_k.setdefault((ab, fg), []).append(gidx // 64)
+        st2 = (u + P - 1) % P
+        ring[st2] = []
+        for l in body_copies:
+            mk = K_LINE.match(l)
+            if mk:
+                kk[mk.group(1)] = ev(mk.group(2))
+            else:
+                copy(l, st2, env["un"])
+    for r in seen_k.values():
+        r = np.stack(r, 0)
+        assert all(len(np.unique(r[:, c])) == r.shape[0] for c in range(0, r.shape[1], 61)), \
+            "a summed row read twice or not at all"
+    if not any(l.startswith("gm[(so + ") for l in lines):
+        return nu  # results through LDS: check_epilogue16
+    for l in lines:  # the result offsets, set after the loop
+        m = re.match(r"const long long (so|sit) = (.*);$", l)
+        if m:
+            env[m.group(1)] = ev(m.group(2))
+    stores = np.concatenate([ev(re.match(r"gm\[\((so \+ \d+ll)\) \* 64ll \+ sit\]", l).group(1)) * 64 + env["sit"]
+                             for l in lines if l.startswith("gm[(so + ")])
+    assert len(np.unique(stores)) == len(stores) and stores.min() >= 0 and stores.max() < group_c2
+    return nu
+
+
+def _result_map(body, S, n_blocks, lds_size=None):
+    """Where each accumulator register (block, thread, tile, register) of a
+    per-item step lands in the group's memory, evaluated from the generated
+    result code: direct stores, or the LDS staging (writes, barrier, 16-byte
+    reads and stores), replayed chunk by chunk."""
+    lines = [l.strip() for l in body.split("\n")]
+    blocks = np.arange(S, S + n_blocks, dtype=np.int64)
+    blk = np.repeat(blocks, 256)
+    th = np.tile(np.arange(256, dtype=np.int64), len(blocks))
+    env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
+
+    def ev(e):
+        return np.asarray(eval(_py_expr(e), env)) + np.zeros_like(blk)
+
+    for l in lines:
+        m = re.match(r"const (?:unsigned long long|long long|unsigned|int|bool) (.*);$", l)
+        if m and not K_LINE.match(l) and "=" in m.group(1) and "*(const" not in l:
+            for part in re.split(r", (?=[a-z]\w* = )", m.group(1)):
+                name, e = part.split(" = ", 1)
+                try:
+                    env[name.strip()] = ev(e)
+                except NameError:
+                    pass  # loop-local names (u, un, ...)
+    out = {}
+    direct = [l for l in lines if l.startswith("gm[(so + ")]
+    if direct:
+        for l in direct:
+            m = re.match(r"gm\[\((so \+ \d+ll)\) \* 64ll \+ sit\] = C2\{cr(\d+_\d+)\[(\d)\], ci\2\[\3\]\};$", l)
+            g = ev(m.group(1)) * 64 + env["sit"]
+            for b_, t_, gg in zip(blk.tolist(), th.tolist(), g.tolist()):
+                key = (b_, t_, m.group(2), int(m.group(3)))
+                assert key not in out
+                out[key] = gg
+        return out
+    i_epi = next(i for i, l in enumerate(lines) if l.startswith("const int wre"))
+    lds = {}
+    for l in lines[i_epi:]:
+        if l == "__syncthreads();":
+            continue
+        m = re.match(r"\*\(C2\*\)\(lds \+ (.*)\) = C2\{cr(\d+_\d+)\[(\d)\], ci\2\[\3\]\};$", l)
+        if m:
+            a = ev(m.group(1))
+            assert a.min() >= 0 and (lds_size is None or a.max() + 8 <= lds_size)
+            for b_, t_, aa in zip(blk.tolist(), th.tolist(), a.tolist()):
+                assert (b_, aa) not in lds or lds[(b_, aa)][0] == "read", "LDS slot written twice in one chunk"
+                lds[(b_, aa)] = ("acc", (b_, t_, m.group(2), int(m.group(3))))
+            continue
+        m = re.match(r"const f32x4 v = \*\(const f32x4\*\)\(lds \+ (\d+) \+ 16 \* tt\);$", l)
+        if m:
+            a = int(m.group(1)) + 16 * env["tt"]
+            cur = []
+            for b_, aa in zip(blk.tolist(), a.tolist()):
+                lo8, hi8 = lds.get((b_, aa)), lds.get((b_, aa + 8))
+                assert lo8 and hi8 and lo8[0] == "acc" and hi8[0] == "acc", "read of an LDS slot not written"
+                cur.append((lo8[1], hi8[1]))
+                lds[(b_, aa)] = ("read", None)
+                lds[(b_, aa + 8)] = ("read", None)
+            continue
+        m = re.match(r"\*\(f32x4\*\)\(gm \+ \((seo \+ \d+ll)\) \* 64ll \+ sit\) = sws \? .* : v;$", l)
+        if m:
+            g = ev(m.group(1)) * 64 + env["sit"]
+            for (lo8, hi8), gg, sw in zip(cur, g.tolist(), env["sws"].astype(bool).tolist()):
+                for key, dst in ((hi8, gg), (lo8, gg + 1)) if sw else ((lo8, gg), (hi8, gg + 1)):
+                    assert key not in out
+                    out[key] = dst
+    return out
+
+
+def check_epilogue16(src_lds, src_direct, n_blocks=4):
+    """The LDS-staged results of a per-item step go where the direct stores
+    put them, every accumulator register exactly once."""
+    m1, m2 = STEP.search(src_lds), STEP.search(src_direct)
+    assert m1.group(4) and m2.group(4) and m1.group(1) == m2.group(1)
+    lds_size = int(re.search(r"char lds\[(\d+)\]", src_lds).group(1))
+    got = _result_map(m1.group(5), int(m1.group(1)), n_blocks, lds_size)
+    want = _result_map(m2.group(5), int(m2.group(1)), n_blocks)
+    assert len(want) == n_blocks * 256 * 4 * len({k[2] for k in want})
+    assert got == want
+
+
+STEP = re.compile(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores(, per item)?\)[^\n]*\n"
                   r"(.*?)\n  return;\n  \}", re.S)
 
 
@@ -153,9 +343,13 @@ def check_source(src, group_elems, max_blocks=None):
     shapes = set()
     for m in steps:
         lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
-        nu = check_step(m.group(4), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
+        if m.group(4):
+            nu = check_step16(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
+            shapes.add("per item")
+        else:
+            nu = check_step(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
+            shapes.add(re.search(r"const int wi = (.*?), wj = (.*?), wq = (.*?);", m.group(5)).groups())
         assert nu >= 1
-        shapes.add(re.search(r"const int wi = (.*?), wj = (.*?), wq = (.*?);", m.group(4)).groups())
     return len(steps), shapes
 
 
@@ -180,7 +374,7 @@ def test_matrix_core_step_indexing_stored_plans(plan, max_blocks, prec, tmp_path
     assert n == st["mfma_steps"] >= 1
 
 
-@pytest.mark.parametrize("shape", [(2, 5, 5, 3), (2, 5, 4, 2), (2, 4, 5, 2), (1, 4, 4, 1), (0, 4, 6, 4)])
+@pytest.mark.parametrize("shape", [(2, 5, 5, 3), (2, 5, 4, 2), (2, 4, 5, 2), (1, 4, 4, 1), (0, 4, 6, 4), (1, 6, 6, 5)])
 @pytest.mark.parametrize("prec", [q.QGM_C64, q.QGM_BF16X3])
 def test_matrix_core_step_indexing_block_shapes(shape, prec, tmp_path, monkeypatch):
     """Single contractions (qgm_contraction_create) that take every block
@@ -191,12 +385,23 @@ def test_matrix_core_step_indexing_block_shapes(shape, prec, tmp_path, monkeypat
     src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
     n, shapes = check_source(src, con.elems)
     assert n == 1
-    if shape == (2, 5, 4, 2):
+    if shape == (2, 5, 4, 2) and prec == q.QGM_C64:
         assert shapes == {SHAPE_212}
+    if prec == q.QGM_BF16X3 and shape[3] >= 5:  # built in: the per-item form for sums of 5 or more bits
+        assert shapes == {"per item"}
+        # the same step with the results stored straight from registers
+        for f in glob.glob(str(tmp_path / "qgm_contract_*.hip")):
+            os.remove(f)
+        q.Contraction(prec, *shape, tile=(2, 65536, 1, 0))
+        direct = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+        assert "gm[(so + " in direct and "gm[(so + " not in src
+        check_epilogue16(src, direct)
 
 
 TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0), (4, 81920, 1, 1),
-         (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1)]
+         (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1),
+         # BF16x3 per-item form: narrower row / column tiles (layouts 4 to 6)
+         (1, 98304, 0, 4), (2, 49152, 0, 5), (1, 32768, 0, 6)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -214,3 +419,27 @@ def test_matrix_core_step_indexing_tile_variants(tile, shape, prec, tmp_path, mo
     src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
     n, _ = check_source(src, con.elems, max_blocks=16)
     assert n == 1
+
+
+PER_ITEM_TILES = [(2, 65536, 0, 0), (4, 65536, 1, 0), (2, 98304, 0, 4), (4, 32768, 0, 5), (1, 49152, 1, 6)]
+
+
+@pytest.mark.parametrize("tile", PER_ITEM_TILES)
+@pytest.mark.parametrize("shape", [(2, 6, 7, 2), (1, 5, 6, 3), (0, 6, 6, 5)])
+def test_per_item_form_variants(tile, shape, tmp_path, monkeypatch):
+    """BF16x3 per-item form: every K steps per stage (more than the sum
+    holds, too), ring budget, result path (jband 1: direct stores) and row /
+    column tile compiles, keeps copies and reads in bounds, and puts the
+    results where the direct stores do."""
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    con = q.Contraction(q.QGM_BF16X3, *shape, tile=tile)
+    assert con.matrix_cores
+    src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+    n, shapes = check_source(src, con.elems, max_blocks=16)
+    assert n == 1 and shapes == {"per item"}
+    if tile[2] != 1:
+        for f in glob.glob(str(tmp_path / "qgm_contract_*.hip")):
+            os.remove(f)
+        q.Contraction(q.QGM_BF16X3, *shape, tile=(tile[0], tile[1], 1, tile[3]))
+        direct = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+        check_epilogue16(src, direct)
