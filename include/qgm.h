@@ -450,8 +450,10 @@ typedef struct qgm_contraction qgm_contraction;
  *     3 = two j tiles x two item groups.  BF16x3: 0 = the per-item form
  *     (one item per wavefront, up to 64 x 64 outputs of it), 4, 5, 6 = that
  *     form with at most 32 rows, 32 columns, or both; 1 to 3 = the 16-item
- *     forms above, 7 = their built-in choice.  In the per-item form jband 1
- *     stores results straight from registers instead of through LDS.
+ *     forms above, 7 = their built-in choice; 8 + (0, 4, 5, 6) = the
+ *     per-item form with eight items (wavefronts) per block instead of
+ *     four.  In the per-item form jband 1 stores results straight from
+ *     registers instead of through LDS.
  *   Built in for BF16x3: the per-item form with two K steps per stage and
  *   a 64 KiB ring when the step sums 5 or more bits, else layout 7. */
 typedef struct {

@@ -971,7 +971,7 @@ qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t 
   GUARD_BEGIN
   if (!out) return fail(QGM_E_ARG, "null argument");
   if (tile && (tile->per < 1 || tile->per > 16 || (tile->per & (tile->per - 1)) || tile->lds_budget < 1024 ||
-               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 7))
+               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 15))
     return fail(QGM_E_ARG, "tile parameters out of range");
   *out = nullptr;
   if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");
@@ -1077,7 +1077,7 @@ qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups
   void* a_res = d_mem;
   void* a_gres = d_mem;
   void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
-  hipError_t e = hipModuleLaunchKernel(c->fn, (unsigned)c->kern.blocks, (unsigned)n_groups, 1, 256, 1, 1, 0,
+  hipError_t e = hipModuleLaunchKernel(c->fn, (unsigned)c->kern.blocks, (unsigned)n_groups, 1, (unsigned)c->kern.threads, 1, 1, 0,
                                        (hipStream_t)stream, args, nullptr);
   if (e != hipSuccess) return fail(QGM_E_HIP, std::string("contraction launch: ") + hipGetErrorString(e));
   return QGM_OK;
@@ -1170,13 +1170,14 @@ qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream
     float best_ms = 0;
     bool have = false;
     if (key.prec == QGM_BF16X3 && key.nk >= 2) {
-      // the per-item form: row / column tile (layouts 0, 4, 5, 6) x K steps
-      // per stage, and the 16-item forms (7 = built-in, 1 to 3); then the
-      // ring budget of the winner (the per-item block order has no band)
-      for (int layout : {0, 4, 5, 6})
+      // the per-item form: row / column tile (layouts 0, 4, 5, 6; + 8 for
+      // eight items per block) x K steps per stage, and the 16-item forms (7
+      // = built-in, 1 to 3); then the ring budget of the winner (the
+      // per-item block order has no band)
+      for (int layout : {0, 4, 5, 6, 8, 12, 13, 14})
         for (int per : {1, 2}) {
           if (st || 4 * per > (1 << key.nk)) continue;
-          qgm_tile t{per, 65536, 0, layout};
+          qgm_tile t{per, layout & 8 ? 131072 : 65536, 0, layout};
           float ms = 0;
           st = time_tile(key, nb, t, ms);
           if (!st && (!have || ms < best_ms)) best = t, best_ms = ms, have = true;
@@ -1188,8 +1189,11 @@ qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream
         st = time_tile(key, nb, t, ms);
         if (!st && ms < best_ms) best = t, best_ms = ms;
       }
-      const bool per_item = best.layout == 0 || (best.layout >= 4 && best.layout <= 6);
-      for (int lds : per_item ? std::vector<int>{32768, 49152, 98304} : std::vector<int>{81920, 114688}) {
+      const bool per_item = (best.layout & 7) == 0 || ((best.layout & 7) >= 4 && (best.layout & 7) <= 6);
+      const std::vector<int> budgets = !per_item ? std::vector<int>{81920, 114688}
+                                       : best.layout & 8 ? std::vector<int>{65536, 98304, 163840}
+                                                         : std::vector<int>{32768, 49152, 98304};
+      for (int lds : budgets) {
         if (st) break;
         qgm_tile t{best.per, lds, per_item ? 0 : best.jband, best.layout};
         float ms = 0;

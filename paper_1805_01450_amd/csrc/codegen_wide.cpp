@@ -117,11 +117,14 @@ bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni
 // Tiles are numbered with the four item quads of a 128-byte line fastest
 // (they read the same lines at the same time), then j tiles, i tiles, b
 // bits and the four lines of a row; each XCD takes a contiguous range.
-static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int out, int r, int ns,
+static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int out, int r, int ns, int IT,
                              const int32_t* A, const int32_t* B, const std::vector<int>& bb, const std::vector<int>& bi,
                              const std::vector<int>& bj, const MfmaTile& tp, bool from_table, int& lds_bytes) {
   const int ni = (int)bi.size(), nj = (int)bj.size();
-  if (ni < 4 || nj < 4 || ns < 2) return false;
+  if (ni < 4 || nj < 4 || ns < 2 || (IT != 4 && IT != 8)) return false;
+  // IT items per block, one per wavefront: an operand row slot holds
+  // SB = 8 IT bytes (LPR lanes of 16 bytes), a copy instruction RPI rows
+  const int SB = 8 * IT, LPR = IT / 2, RPI = 64 / LPR, lg = IT == 4 ? 1 : 2;
   int WM = std::min(4, 1 << (ni - 4)), WN = std::min(4, 1 << (nj - 4));
   if (tp.layout == 4) WM = std::min(WM, 2);
   else if (tp.layout == 5) WN = std::min(WN, 2);
@@ -133,7 +136,7 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
   // takes narrower tiles instead
   auto min_ku = [&]() {
     int v = 4;
-    while (((16 * (WM + WN)) * v / 32) % 4) v *= 2;
+    while (((16 * (WM + WN)) * v / RPI) % IT) v *= 2;
     return v;
   };
   while (min_ku() > nk && (WM > 1 || WN > 1)) {
@@ -149,22 +152,23 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
   const bool direct_stores = from_table && tp.jband == 1;
   const int kub = ku == 4 ? 2 : ku == 8 ? 3 : ku == 16 ? 4 : 5;
   const int nu = nk / ku;
-  const int stage = (TM + TN) * ku * 32;
-  const int n_ins = (TM + TN) * ku / 32, per_wave = n_ins / 4;
+  const int stage = (TM + TN) * ku * SB;
+  const int n_ins = (TM + TN) * ku / RPI, per_wave = n_ins / IT;
   int P = std::max(2, std::min(8, (from_table ? tp.lds_budget : 65536) / stage));
   P = std::min(P, 2 + 63 / std::max(1, per_wave));
   if (P * stage > 163840) return false;
   lds_bytes = P * stage;
+  if (!o_) return true;  // shape check only
+  std::ostringstream& o = *o_;
   // tile index bits, fastest first: item quads inside a 128-byte line, j
   // tiles, i tiles, b bits, the line of the 512-byte row
-  std::vector<std::pair<int, int>> bits;  // (0 = j, 1 = i, 2 = b, 3 = item quad; bit)
-  bits.push_back({3, 0});
-  bits.push_back({3, 1});
+  std::vector<std::pair<int, int>> bits;  // (0 = j, 1 = i, 2 = b, 3 = item group; bit)
+  for (int t = 0; t < (IT == 4 ? 2 : 1); ++t) bits.push_back({3, t});
   for (int t = 0; t < nbj; ++t) bits.push_back({0, bj[lj + t]});
   for (int t = 0; t < nbi; ++t) bits.push_back({1, bi[li + t]});
   for (int t = 0; t < nbb; ++t) bits.push_back({2, bb[t]});
-  bits.push_back({3, 2});
-  bits.push_back({3, 3});
+  bits.push_back({3, 8});
+  bits.push_back({3, 9});
   const unsigned long long nb = 1ull << bits.size();
   k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
@@ -199,26 +203,29 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
     return e;
   };
   o << "  const int lid = threadIdx.x & 63, w4 = (int)wv;\n"
-    << "  const long long itb = (long long)(((tx >> " << qhi << ") & 3ull) * 16ull + (tx & 3ull) * 4ull);\n"
+    << "  const long long itb = (long long)(((tx >> " << qhi << ") & 3ull) * 16ull + (tx & " << 16 / IT - 1 << "ull) * "
+    << IT << "ull);\n"
     << "  const long long ba = " << A[1] << "ll" << sum_of([&](int kd, int b) { return kd == 0 ? 0ll : (long long)A[16 + b]; })
     << ";\n"
     << "  const long long bbk = " << B[1] << "ll" << sum_of([&](int kd, int b) { return kd == 1 ? 0ll : (long long)B[16 + b]; })
     << ";\n"
     << "  const long long lo = " << out << "ll" << sum_of([&](int, int b) { return 1ll << b; }) << ";\n";
-  // copies: instruction c = 4 q + wave covers row slots 32 c .. 32 c + 31;
-  // lane l fills half l & 1 of slot 32 c + l / 2 with item pair
-  // (l & 1) ^ bit 3 of the slot.  Slots 0 .. ku TM - 1 are A rows (k major),
-  // then ku TN B rows.
+  // copies: instruction c = IT q + wave covers row slots RPI c .. RPI c +
+  // RPI - 1; lane l fills 16-byte part l % LPR of slot RPI c + l / LPR with
+  // the item pair (l % LPR) ^ swz(slot): swz = bit 3 of the slot for four
+  // items per slot, bits 2..3 for eight.  Slots 0 .. ku TM - 1 are A rows (k
+  // major), then ku TN B rows.
+  const std::string swz_sl = IT == 4 ? " >> 3) & 1)" : " >> 2) & 3)";
   for (int q = 0; q < per_wave; ++q) {
     const std::string Q = std::to_string(q);
-    o << "  const int sl" << Q << " = " << 32 * 4 * q << " + 32 * w4 + (lid >> 1);\n"
+    o << "  const int sl" << Q << " = " << RPI * IT * q << " + " << RPI << " * w4 + (lid >> " << lg << ");\n"
       << "  const bool isa" << Q << " = sl" << Q << " < " << ku * TM << ";\n"
       << "  const int sr" << Q << " = isa" << Q << " ? sl" << Q << " : sl" << Q << " - " << ku * TM << ";\n"
       << "  const int kl" << Q << " = isa" << Q << " ? sr" << Q << " / " << TM << " : sr" << Q << " / " << TN << ";\n"
       << "  const int rw" << Q << " = isa" << Q << " ? sr" << Q << " % " << TM << " : sr" << Q << " % " << TN << ";\n"
       << "  const long long eo" << Q << " = isa" << Q << " ? ba" << idx_off(A, bi, "rw" + Q, li) << koff(A, "kl" + Q, 0, kub)
       << " : bbk" << idx_off(B, bj, "rw" + Q, lj) << koff(B, "kl" + Q, 0, kub) << ";\n"
-      << "  const long long src" << Q << " = itb + 2 * ((lid & 1) ^ ((sl" << Q << " >> 3) & 1));\n";
+      << "  const long long src" << Q << " = itb + 2 * ((lid & " << LPR - 1 << ") ^ ((sl" << Q << swz_sl << ");\n";
   }
   auto issue = [&](const std::string& unit, const std::string& stg) {
     o << "    {\n"
@@ -228,7 +235,7 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
       const std::string Q = std::to_string(q);
       o << "    __builtin_amdgcn_global_load_lds((const void*)(gm + (eo" << Q << " + (isa" << Q
         << " ? ka : kb)) * 64ll + src" << Q << "), (__attribute__((address_space(3))) void*)(lds + (" << stg << ") * "
-        << stage << " + " << 4 * 1024 * q << " + 1024 * w4), 16, 0, 0);\n";
+        << stage << " + " << IT * 1024 * q << " + 1024 * w4), 16, 0, 0);\n";
     }
     o << "    }\n";
   };
@@ -237,10 +244,11 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
       o << "  f32x4 cr" << f << "_" << g << " = {}, ci" << f << "_" << g << " = {};\n";
   for (int s = 0; s < P - 1; ++s) issue(std::to_string(std::min(s, nu - 1)), std::to_string(s));
   // lane read offsets: slot (4 t + l / 16) TM + 16 f + l % 16 of A, item pair
-  // w4 / 2 (swapped by bit 3 of l), item w4 & 1 of the pair
-  o << "  const int rdx = 32 * (lid & 15) + 16 * ((w4 >> 1) ^ ((lid >> 3) & 1)) + 8 * (w4 & 1);\n"
-    << "  const int rda = rdx + " << 32 * TM << " * (lid >> 4);\n"
-    << "  const int rdb = rdx + " << 32 * TN << " * (lid >> 4) + " << 32 * ku * TM << ";\n";
+  // (w4 / 2) ^ swz(slot) (swz from the low bits of l % 16), item w4 & 1 of
+  // the pair
+  o << "  const int rdx = " << SB << " * (lid & 15) + 16 * ((w4 >> 1) ^ ((lid" << swz_sl << ") + 8 * (w4 & 1);\n"
+    << "  const int rda = rdx + " << SB * TM << " * (lid >> 4);\n"
+    << "  const int rdb = rdx + " << SB * TN << " * (lid >> 4) + " << SB * ku * TM << ";\n";
   const int N = (P - 2) * per_wave;
   const int wait_imm = (N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14);
   o << "  for (int u = 0; u < " << nu << "; ++u) {\n"
@@ -257,7 +265,7 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
     const std::string T = std::to_string(t);
     for (int f = 0; f < WM; ++f) {
       const std::string F = T + "_" + std::to_string(f);
-      o << "    const C2 a" << F << " = *(const C2*)(sb + rda + " << 32 * (4 * t * TM + 16 * f) << ");\n"
+      o << "    const C2 a" << F << " = *(const C2*)(sb + rda + " << SB * (4 * t * TM + 16 * f) << ");\n"
         << "    const unsigned ap" << F << " = pk(a" << F << ".x, a" << F << ".y);\n"
         << "    const unsigned al" << F << " = pk(a" << F << ".x - lowf(ap" << F << "), a" << F << ".y - highf(ap" << F
         << "));\n"
@@ -266,7 +274,7 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
     }
     for (int g = 0; g < WN; ++g) {
       const std::string G = T + "_" + std::to_string(g);
-      o << "    const C2 b" << G << " = *(const C2*)(sb + rdb + " << 32 * (4 * t * TN + 16 * g) << ");\n"
+      o << "    const C2 b" << G << " = *(const C2*)(sb + rdb + " << SB * (4 * t * TN + 16 * g) << ");\n"
         << "    const unsigned bq" << G << " = pk(b" << G << ".x, -b" << G << ".y);\n"
         << "    const unsigned bs" << G << " = pk(b" << G << ".y, b" << G << ".x);\n"
         << "    const float brl" << G << " = b" << G << ".x - lowf(bq" << G << "), bil" << G << " = b" << G
@@ -300,36 +308,46 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
   };
   if (!direct_stores) {
     // Through LDS, ncb 16 x 16 tiles at a time: each wavefront writes its
-    // item's values as [element][4 items] (8 bytes each, item slot w4 ^
-    // ((element >> 3) & 3) so that a lane group's writes spread over the
-    // banks); then each thread stores 16 bytes (two items of one element),
-    // neighbouring threads the two halves of one element's 32-byte piece.
+    // item's values as [element][IT items] (8 bytes each; item slot w4 ^ f,
+    // f = (element >> 3) & 3 for four items, 2 ((element >> 2) & 3) for
+    // eight, so that a lane group's writes spread over the banks); then each
+    // thread stores 16 bytes (two items of one element), neighbouring
+    // threads the parts of one element's 8 IT-byte piece.
     int ncb = 1;  // tiles per round: a power of two that divides WM WN
-    while (2 * ncb <= WM * WN && 2 * ncb * 8192 <= lds_bytes) ncb *= 2;
+    while (2 * ncb <= WM * WN && 2 * ncb * 2048 * IT <= lds_bytes) ncb *= 2;
     o << "  const int wre = 64 * (lid >> 4);\n"
       << "  const int tt = threadIdx.x;\n"
-      << "  const long long seo = lo" << " + (long long)((tt >> 5) & 1) * " << (1ll << bi[0]) << "ll + (long long)((tt >> 6) & 1) * "
-      << (1ll << bi[1]) << "ll + (long long)((tt >> 7) & 1) * " << (1ll << bi[2]) << "ll";
-    for (int t = 0; t < 4; ++t) o << " + (long long)((tt >> " << t + 1 << ") & 1) * " << (1ll << bj[t]) << "ll";
-    o << ";\n"
-      << "  const long long sit = itb + 2 * ((tt & 1) ^ ((tt >> 5) & 1));\n"
-      << "  const bool sws = (tt >> 4) & 1;\n";
+      << "  const long long seo = lo";
+    for (int t = 0; t < 3; ++t) o << " + (long long)((tt >> " << lg + 4 + t << ") & 1) * " << (1ll << bi[t]) << "ll";
+    for (int t = 0; t < 4; ++t) o << " + (long long)((tt >> " << lg + t << ") & 1) * " << (1ll << bj[t]) << "ll";
+    o << ";\n";
+    if (IT == 4)
+      o << "  const long long sit = itb + 2 * ((tt & 1) ^ ((tt >> 5) & 1));\n"
+        << "  const bool sws = (tt >> 4) & 1;\n";
+    else
+      o << "  const long long sit = itb + 2 * ((tt & 3) ^ ((tt >> 4) & 3));\n";
     for (int c0 = 0; c0 < WM * WN; c0 += ncb) {
       o << "  __syncthreads();\n";
       for (int cb = 0; cb < ncb; ++cb) {
         const int f = (c0 + cb) / WN, g = (c0 + cb) % WN;
         const std::string C = std::to_string(f) + "_" + std::to_string(g);
-        for (int e = 0; e < 4; ++e)
-          o << "  *(C2*)(lds + ((" << 256 * cb + 16 * e << " + wre + (lid & 15)) * 4 + (w4 ^ ((" << 2 * e
-            << " + ((lid >> 3) & 1)) & 3))) * 8) = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+        for (int e = 0; e < 4; ++e) {
+          o << "  *(C2*)(lds + ((" << 256 * cb + 16 * e << " + wre + (lid & 15)) * " << IT << " + (w4 ^ ";
+          if (IT == 4)
+            o << "((" << 2 * e << " + ((lid >> 3) & 1)) & 3)";
+          else
+            o << "(2 * ((lid >> 2) & 3))";
+          o << ")) * 8) = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+        }
       }
       o << "  __syncthreads();\n";
       for (int it = 0; it < 2 * ncb; ++it) {
         const int cb = it >> 1, f = (c0 + cb) / WN, g = (c0 + cb) % WN;
         long long off = fg_off(f, g) + ((it & 1) ? 1ll << bi[3] : 0);
         o << "  {\n"
-          << "  const f32x4 v = *(const f32x4*)(lds + " << 4096 * it << " + 16 * tt);\n"
-          << "  *(f32x4*)(gm + (seo + " << off << "ll) * 64ll + sit) = sws ? (f32x4){v[2], v[3], v[0], v[1]} : v;\n"
+          << "  const f32x4 v = *(const f32x4*)(lds + " << 1024 * IT * it << " + 16 * tt);\n"
+          << "  *(f32x4*)(gm + (seo + " << off << "ll) * 64ll + sit) = "
+          << (IT == 4 ? "sws ? (f32x4){v[2], v[3], v[0], v[1]} : v;\n" : "v;\n")
           << "  }\n";
       }
     }
@@ -353,8 +371,47 @@ static bool emit_mfma16_step(std::ostringstream& o, WideKernel& k, int si, int o
   return true;
 }
 
+// The tile table entry of a matrix-core step's shape, if any.
+static bool table_tile(const TileTable* tiles, int prec, int ni, int nj, int ns, MfmaTile& tp) {
+  if (!tiles) return false;
+  auto it = tiles->find(TileKey{prec, ni, nj, ns});
+  if (it == tiles->end()) return false;
+  tp = it->second;
+  return true;
+}
+
+// BF16x3 form choice: the per-item form for table layouts 0, 4, 5, 6 (plus
+// 8: eight items per block), built in for sums of 32 or more k (on shorter
+// sums, where the results' stores dominate, the 16-item forms store whole
+// 128-byte lines and were as fast or faster); its tile parameters.
+static bool bf16_per_item(bool from_table, const MfmaTile& tp, int ns, MfmaTile& t16, int& it_pref) {
+  const int lay = tp.layout & 7;
+  const bool per_item = from_table ? lay == 0 || (lay >= 4 && lay <= 6) : ns >= 5;
+  t16 = from_table ? tp : MfmaTile{2, 65536, 0, 0};
+  t16.layout = lay;
+  it_pref = from_table && (tp.layout & 8) ? 8 : 4;
+  return per_item;
+}
+
+// Block sizes a step can run at in a level kernel: bit 0 = four wavefronts,
+// bit 1 = eight, bit 2 = it asks for eight (a per-item step whose table
+// entry has eight items per block).  Vector steps take either; 16-item
+// matrix-core steps need four.
+static int step_waves(int kind, int r, int ns, int prec, const std::vector<const int32_t*>& rec, bool mfma,
+                      const TileTable* tiles) {
+  std::vector<int> bb, bi, bj;
+  if (!mfma || !mfma_bits(kind, r, ns, prec, rec, bb, bi, bj)) return 3;
+  MfmaTile tp, t16;
+  const bool from_table = table_tile(tiles, prec, (int)bi.size(), (int)bj.size(), ns, tp);
+  int it_pref = 4, lds = 0;
+  if (prec != 2 || !bf16_per_item(from_table, tp, ns, t16, it_pref)) return 1;
+  WideKernel scratch;
+  const bool ok8 = emit_mfma16_step(nullptr, scratch, 0, 0, r, ns, 8, rec[0], rec[1], bb, bi, bj, t16, true, lds);
+  return 1 | (ok8 ? 2 : 0) | (ok8 && it_pref == 8 ? 4 : 0);
+}
+
 bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
-                    const std::vector<const int32_t*>& rec, int& lds_bytes, const TileTable* tiles) {
+                    const std::vector<const int32_t*>& rec, int& lds_bytes, const TileTable* tiles, int W) {
   std::vector<int> bb, bi, bj;
   if (!mfma_bits(kind, r, ns, prec, rec, bb, bi, bj)) return false;
   const int32_t* A = rec[0];
@@ -363,21 +420,19 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   // choice (2 x 2 tiles of 16 items when both sides have 5 bits, two k per
   // unit, a ring of at most 52 KiB, bands of four j blocks).
   MfmaTile tp;
-  bool from_table = false;
-  if (tiles) {
-    auto it = tiles->find(TileKey{prec, (int)bi.size(), (int)bj.size(), ns});
-    if (it != tiles->end()) tp = it->second, from_table = true;
-  }
-  // BF16x3: the full-rate per-item form (table layouts 0, 4, 5, 6) or the
-  // 16-item forms (1, 2, 3; 7 = their built-in choice).  Built in: the
-  // per-item form, two K steps per stage, for sums of 32 or more k (on
-  // shorter sums, where the results' stores dominate, the 16-item forms
-  // store whole 128-byte lines and were as fast or faster).
+  const bool from_table = table_tile(tiles, prec, (int)bi.size(), (int)bj.size(), ns, tp);
+  // BF16x3: the full-rate per-item form, as many items per block as the
+  // level kernel has wavefronts, or the 16-item forms (1, 2, 3; 7 = their
+  // built-in choice), which need four wavefronts
   if (prec == 2) {
-    const bool per_item = from_table ? tp.layout == 0 || (tp.layout >= 4 && tp.layout <= 6) : ns >= 5;
-    const MfmaTile t16 = from_table ? tp : MfmaTile{2, 65536, 0, 0};
-    if (per_item && emit_mfma16_step(o, k, si, out, r, ns, A, B, bb, bi, bj, t16, true, lds_bytes)) return true;
+    MfmaTile t16;
+    int it_pref = 4;
+    if (bf16_per_item(from_table, tp, ns, t16, it_pref) &&
+        emit_mfma16_step(&o, k, si, out, r, ns, W, A, B, bb, bi, bj, t16, true, lds_bytes))
+      return true;
   }
+  if (W != 4) return false;
+  tp.layout &= 7;
   if (tp.layout >= 4) tp.layout = 0;
   int WI = bi.size() >= 5 ? 2 : 1, WJ = bj.size() >= 5 ? 2 : 1;
   if (tp.layout == 1) WI = WJ = 1;                                   // four item groups
@@ -621,7 +676,7 @@ bool read_tile_table(const std::string& path, TileTable& t, std::string& err) {
     int n = std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
     if (n <= 0) continue;  // blank or comment
     if (n != 8 || v[0] < 0 || v[0] > 2 || v[1] < 4 || v[2] < 4 || v[3] < 1 || v[3] > 16 || v[4] < 1 || v[4] > 16 ||
-        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 7) {
+        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 15) {
       err = "tile table " + path + " line " + std::to_string(ln) + ": expected prec ni nj nk per lds_budget jband layout";
       ok = false;
       break;
@@ -739,18 +794,31 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
     level[si] = lev;
     n_levels = std::max(n_levels, lev + 1);
   }
-  // one kernel per level; a block runs 4 wavefront tiles of one of its steps
+  // one kernel per level; a block runs W wavefront tiles of one of its
+  // steps (W = 4, or 8 when every step of the level can and one asks for it)
   std::vector<int> level_lds(n_levels, 0);  // LDS of the level's matrix-core steps
   for (int lev = 0; lev < n_levels; ++lev) {
     WideKernel k;
     k.kind = 0;
     k.name = "wl" + std::to_string(lev);
     k.blocks = 0;
+    int all8 = 1, want8 = 0;
+    for (int si = 0; si < wide.n_steps; ++si) {
+      if (level[si] != lev) continue;
+      const int32_t* sr = &wide.steps[8 * si];
+      std::vector<const int32_t*> rec(sr[4]);
+      for (int i = 0; i < sr[4]; ++i) rec[i] = &wide.ops[(size_t)(sr[6] + i) * kWideOpInts];
+      const int wmask = step_waves(sr[0], sr[2], sr[3], prec, rec, mfma, tiles);
+      all8 &= (wmask >> 1) & 1;
+      want8 |= (wmask >> 2) & 1;
+    }
+    const int W = all8 && want8 ? 8 : 4;
+    k.threads = 64 * W;
     // Two wavefronts per SIMD: caps a wavefront at 256 registers, which
     // also makes the compiler keep matrix-core accumulators in ordinary
     // VGPRs (with 512 it places them in AGPRs and copies them between
     // register sets inside the K loops).
-    o << "extern \"C\" __global__ void __launch_bounds__(256) "
+    o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * W << ") "
       << (mfma && prec != 0 ? "__attribute__((amdgpu_waves_per_eu(2))) " : "") << k.name
       << "(C2* __restrict__ mem, const C2* __restrict__ cst, const unsigned long long* __restrict__ packed, "
          "unsigned long long group_elems, unsigned long long s_begin, unsigned long long n_s, int group0, "
@@ -795,7 +863,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
         k.bytes += 8.0 * elems;
       }
       int lds_bytes = 0;
-      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes, tiles)) {
+      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes, tiles, W)) {
         level_lds[lev] = std::max(level_lds[lev], lds_bytes);
         continue;
       }
@@ -829,11 +897,11 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       while (L < r && (2 << L) <= max_acc && rows_for(L + 1) <= max_rows && (r - L - 1 >= 13 || (1 << (r - L - 1)) >= 2048))
         ++L;
       const unsigned long long tiles = 1ull << (r - L);
-      const unsigned long long nb = (tiles + 3) / 4;
+      const unsigned long long nb = (tiles + W - 1) / W;
       k.steps.push_back(si);
       o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
         << "  // step " << si << "\n"
-        << "  const unsigned long long t = (blk - " << k.blocks << "ull) * 4ull + wv;\n";
+        << "  const unsigned long long t = (blk - " << k.blocks << "ull) * " << W << "ull + wv;\n";
       o << "  if (t >= " << tiles << "ull) return;\n";
       k.blocks += nb;
       // per-operand base offsets from the tile index

@@ -20,7 +20,8 @@ struct WideDev {
   // generated item kernels, one per level of independent steps, in order
   struct Level {
     void* fn;                   // hipFunction_t
-    unsigned long long blocks;  // 256-thread blocks per 64-item group
+    unsigned long long blocks;  // blocks per 64-item group
+    int threads;                // threads per block
   };
   std::vector<Level> levels;
   // profiling: when set, levels.size() + 1 events recorded on the launch

@@ -354,7 +354,7 @@ int dev_upload(const Program& prog, const std::vector<char>& code, const WidePro
       hipFunction_t fn = nullptr;
       HIP_OK(hipModuleGetFunction(&fn, mod, k.name.c_str()));
       if (k.kind == 0)
-        dp.wide.levels.push_back({fn, k.blocks});
+        dp.wide.levels.push_back({fn, k.blocks, k.threads});
       else  // generated constant-step kernels, in step order
         dp.wide.const_plan.push_back({k.kind == 1 ? 1 : 0, k.steps.front(), (int)k.steps.size(), fn, k.blocks});
     }

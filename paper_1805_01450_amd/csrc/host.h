@@ -202,6 +202,7 @@ struct WideKernel {
   int kind;
   std::string name;
   unsigned long long blocks;
+  int threads = 256;          // threads per block (level kernels: 64 per wavefront)
   std::vector<int> steps;
   int mfma_steps = 0;       // steps of this kernel on the matrix cores
   double mfma_flops = 0.0;  // their flops per item

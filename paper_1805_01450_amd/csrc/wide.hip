@@ -226,7 +226,8 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
     for (size_t li = 0; li < wd.levels.size(); ++li) {
       const WideDev::Level& lv = wd.levels[li];
       if (ev && hipEventRecord((hipEvent_t)ev[li], stream) != hipSuccess) return -6;
-      if (hipModuleLaunchKernel((hipFunction_t)lv.fn, (unsigned)lv.blocks, (unsigned)n_groups, 1, 256, 1, 1, 0, stream,
+      if (hipModuleLaunchKernel((hipFunction_t)lv.fn, (unsigned)lv.blocks, (unsigned)n_groups, 1, (unsigned)lv.threads, 1,
+                                1, 0, stream,
                                 args, nullptr) != hipSuccess)
         return -6;
     }

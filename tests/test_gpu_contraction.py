@@ -124,7 +124,8 @@ def test_contraction_rejects_bad_shapes():
 
 TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0), (4, 81920, 1, 1),
          (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1),
-         (1, 98304, 0, 4), (2, 49152, 0, 5), (1, 32768, 0, 6)]
+         (1, 98304, 0, 4), (2, 49152, 0, 5), (1, 32768, 0, 6),
+         (2, 131072, 0, 8), (1, 131072, 1, 8), (2, 98304, 0, 13)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -132,13 +133,14 @@ TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0)
 def test_tile_variants_match_builtin_tile(tile, prec):
     """Every tile parameter set keeps the k order of each output's sum, so the
     result equals the built-in tile's bit for bit (and meets the bound).
-    BF16x3 has two families, the per-item 16 x 16 x 32 form (built-in,
-    layouts 0 and 4 to 6) and the 16-item 4 x 4 x 4 forms (layouts 1 to 3):
-    the latter sum the same terms in another order and meet the bound."""
+    BF16x3 has two families, the per-item 16 x 16 x 32 form (built in for
+    this K = 32 shape; layouts 0 and 4 to 6, plus 8 for eight items per
+    block) and the 16-item 4 x 4 x 4 forms (layouts 1 to 3): the latter sum
+    the same terms in another order and meet the bound."""
     import torch
     if prec == q.QGM_BF16X3 and tile[0] == 1 and tile[3] in (1, 2, 3):
         tile = (2,) + tile[1:]
-    shape = (1, 6, 7, 4)
+    shape = (1, 6, 7, 5)
     c0, got0, want, mag = _run(prec, *shape, 2, False, seed=11)
     c1 = q.Contraction(prec, *shape, tile=tile)
     assert c1.matrix_cores

@@ -151,7 +151,7 @@ K_LINE = re.compile(r"const long long (ka|kb) = (.*);$")
 READ16 = re.compile(r"const C2 ([ab])(\d+)_(\d+) = \*\(const C2\*\)\(sb \+ (rda|rdb) \+ (\d+)\);$")
 
 
-def check_step16(body, S, E, lds_size, group_c2, max_blocks=None):
+def check_step16(body, S, E, lds_size, group_c2, max_blocks=None, threads=256):
     """The per-item form (one item per wavefront, 16 x 16 x 32 operands):
     replays the ring and checks that lane l of wavefront w reads, for K step
     t and row tile f (column tile g), the slot a copy of the same unit filled
@@ -162,8 +162,8 @@ def check_step16(body, S, E, lds_size, group_c2, max_blocks=None):
     blocks = np.arange(S, E, dtype=np.int64)
     if max_blocks is not None and E - S > max_blocks:
         blocks = np.concatenate([blocks[:max_blocks // 2], blocks[-(max_blocks // 2):]])
-    blk = np.repeat(blocks, 256)
-    th = np.tile(np.arange(256, dtype=np.int64), len(blocks))
+    blk = np.repeat(blocks, threads)
+    th = np.tile(np.arange(threads, dtype=np.int64), len(blocks))
     env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
 
     def ev(e):
@@ -254,15 +254,15 @@ def check_step16(body, S, E, lds_size, group_c2, max_blocks=None):
     return nu
 
 
-def _result_map(body, S, n_blocks, lds_size=None):
+def _result_map(body, S, n_blocks, lds_size=None, threads=256):
     """Where each accumulator register (block, thread, tile, register) of a
     per-item step lands in the group's memory, evaluated from the generated
     result code: direct stores, or the LDS staging (writes, barrier, 16-byte
     reads and stores), replayed chunk by chunk."""
     lines = [l.strip() for l in body.split("\n")]
     blocks = np.arange(S, S + n_blocks, dtype=np.int64)
-    blk = np.repeat(blocks, 256)
-    th = np.tile(np.arange(256, dtype=np.int64), len(blocks))
+    blk = np.repeat(blocks, threads)
+    th = np.tile(np.arange(threads, dtype=np.int64), len(blocks))
     env = {"np": np, "blk": blk, "threadIdx_x": th, "wv": th >> 6}
 
     def ev(e):
@@ -312,10 +312,11 @@ def _result_map(body, S, n_blocks, lds_size=None):
                 lds[(b_, aa)] = ("read", None)
                 lds[(b_, aa + 8)] = ("read", None)
             continue
-        m = re.match(r"\*\(f32x4\*\)\(gm \+ \((seo \+ \d+ll)\) \* 64ll \+ sit\) = sws \? .* : v;$", l)
+        m = re.match(r"\*\(f32x4\*\)\(gm \+ \((seo \+ \d+ll)\) \* 64ll \+ sit\) = (?:sws \? .* : )?v;$", l)
         if m:
             g = ev(m.group(1)) * 64 + env["sit"]
-            for (lo8, hi8), gg, sw in zip(cur, g.tolist(), env["sws"].astype(bool).tolist()):
+            sws = env["sws"].astype(bool) if "sws" in env else np.zeros_like(blk, dtype=bool)
+            for (lo8, hi8), gg, sw in zip(cur, g.tolist(), sws.tolist()):
                 for key, dst in ((hi8, gg), (lo8, gg + 1)) if sw else ((lo8, gg), (hi8, gg + 1)):
                     assert key not in out
                     out[key] = dst
@@ -328,14 +329,21 @@ def check_epilogue16(src_lds, src_direct, n_blocks=4):
     m1, m2 = STEP.search(src_lds), STEP.search(src_direct)
     assert m1.group(4) and m2.group(4) and m1.group(1) == m2.group(1)
     lds_size = int(re.search(r"char lds\[(\d+)\]", src_lds).group(1))
-    got = _result_map(m1.group(5), int(m1.group(1)), n_blocks, lds_size)
-    want = _result_map(m2.group(5), int(m2.group(1)), n_blocks)
-    assert len(want) == n_blocks * 256 * 4 * len({k[2] for k in want})
+    threads = _threads(src_lds, m1.start())
+    assert threads == _threads(src_direct, m2.start())
+    got = _result_map(m1.group(5), int(m1.group(1)), n_blocks, lds_size, threads)
+    want = _result_map(m2.group(5), int(m2.group(1)), n_blocks, threads=threads)
+    assert len(want) == n_blocks * threads * 4 * len({k[2] for k in want})
     assert got == want
 
 
 STEP = re.compile(r"  if \(blk >= (\d+)ull && blk < (\d+)ull\) \{\n  // step (\d+) \(matrix cores(, per item)?\)[^\n]*\n"
                   r"(.*?)\n  return;\n  \}", re.S)
+
+
+def _threads(src, at):
+    """Threads per block of the kernel whose body holds position `at`."""
+    return int(list(re.finditer(r"__launch_bounds__\((\d+)\)", src[:at]))[-1].group(1))
 
 
 def check_source(src, group_elems, max_blocks=None):
@@ -344,8 +352,10 @@ def check_source(src, group_elems, max_blocks=None):
     for m in steps:
         lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
         if m.group(4):
-            nu = check_step16(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
-            shapes.add("per item")
+            threads = _threads(src, m.start())
+            nu = check_step16(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks,
+                              threads)
+            shapes.add("per item" if threads == 256 else "per item x8")
         else:
             nu = check_step(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
             shapes.add(re.search(r"const int wi = (.*?), wj = (.*?), wq = (.*?);", m.group(5)).groups())
@@ -421,7 +431,9 @@ def test_matrix_core_step_indexing_tile_variants(tile, shape, prec, tmp_path, mo
     assert n == 1
 
 
-PER_ITEM_TILES = [(2, 65536, 0, 0), (4, 65536, 1, 0), (2, 98304, 0, 4), (4, 32768, 0, 5), (1, 49152, 1, 6)]
+PER_ITEM_TILES = [(2, 65536, 0, 0), (4, 65536, 1, 0), (2, 98304, 0, 4), (4, 32768, 0, 5), (1, 49152, 1, 6),
+                  # eight items per block (layout + 8)
+                  (2, 131072, 0, 8), (1, 131072, 1, 8), (2, 65536, 0, 12), (2, 98304, 0, 13), (1, 65536, 1, 14)]
 
 
 @pytest.mark.parametrize("tile", PER_ITEM_TILES)
@@ -436,7 +448,7 @@ def test_per_item_form_variants(tile, shape, tmp_path, monkeypatch):
     assert con.matrix_cores
     src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
     n, shapes = check_source(src, con.elems, max_blocks=16)
-    assert n == 1 and shapes == {"per item"}
+    assert n == 1 and shapes == {"per item x8" if tile[3] & 8 else "per item"}
     if tile[2] != 1:
         for f in glob.glob(str(tmp_path / "qgm_contract_*.hip")):
             os.remove(f)
