@@ -368,17 +368,21 @@ def check_source(src, group_elems, max_blocks=None):
 SHAPE_212 = ("w4 & 1", "0", "w4 >> 1")
 
 
-@pytest.mark.parametrize("plan,max_blocks,prec", [("7x7x30", None, q.QGM_C64), ("7x7x30", None, q.QGM_BF16X3),
-                                                  ("8x8x40-k8", 8, q.QGM_C64)])
-def test_matrix_core_step_indexing_stored_plans(plan, max_blocks, prec, tmp_path, monkeypatch):
+@pytest.mark.parametrize("plan,max_blocks,prec,table", [("7x7x30", None, q.QGM_C64, False),
+                                                        ("7x7x30", None, q.QGM_BF16X3, False),
+                                                        ("8x8x40-k8", 8, q.QGM_C64, False),
+                                                        ("8x8x40-k8", 4, q.QGM_BF16X3, True)])
+def test_matrix_core_step_indexing_stored_plans(plan, max_blocks, prec, table, tmp_path, monkeypatch):
     """Every matrix-core step of the stored plans (of the benchmark's 8x8x40
-    k = 8 plan: the first and last four blocks of each step)."""
+    k = 8 plan: the first and last blocks of each step; BF16x3 with the
+    stored tile table the benchmark uses)."""
     here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
     rec = json.load(open(os.path.join(here, plan + ".json")))
     cz = rec["circuit"]
     c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
     monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
-    st = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE).stats()
+    tiles = os.path.join(here, "tiles_mi355x.txt") if table else None
+    st = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE, tile_table_path=tiles).stats()
     src = open(glob.glob(str(tmp_path / "qgm_wide_*.hip"))[0]).read()
     n, _ = check_source(src, st["item_elems"], max_blocks)
     assert n == st["mfma_steps"] >= 1
