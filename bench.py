@@ -226,7 +226,10 @@ def level_roofline(levels, workload, prec_name):
     i = max(range(len(ms_l)), key=lambda j: ms_l[j])
     k_flops = fl_l[i] * items_l
     k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
-    mpeak = PEAK_FP64_MATRIX_TFLOPS if prec_name == "c128" else PEAK_FP32_MATRIX_TFLOPS
+    # matrix-core peak in useful (complex) flops: FP64, FP32, or for BF16x3
+    # the bfloat16 peak over the three bfloat16 products per real product
+    mpeak = {"c128": PEAK_FP64_MATRIX_TFLOPS, "bf16x3": PEAK_BF16_MATRIX_TFLOPS / 3}.get(prec_name,
+                                                                                       PEAK_FP32_MATRIX_TFLOPS)
     peak = mpeak if mf_l[i] else PEAK_FP32_VECTOR_TFLOPS
     traffic = measured_traffic(workload, f"wl{i}", 1, prec_name)
     roof = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
