@@ -452,8 +452,11 @@ typedef struct qgm_contraction qgm_contraction;
  *     form with at most 32 rows, 32 columns, or both; 1 to 3 = the 16-item
  *     forms above, 7 = their built-in choice; 8 + (0, 4, 5, 6) = the
  *     per-item form with eight items (wavefronts) per block instead of
- *     four.  In the per-item form jband 1 stores results straight from
- *     registers instead of through LDS.
+ *     four.  16 + (0, 4, 5, 6) (+ 8): the per-item form for either
+ *     precision; complex64 runs it on v_mfma_f32_16x16x4_f32 (four real
+ *     products per tile and K step of four complex k).  In the per-item
+ *     form jband 1 stores results straight from registers instead of
+ *     through LDS.
  *   Built in for BF16x3: the per-item form with two K steps per stage and
  *   a 64 KiB ring when the step sums 5 or more bits, else layout 7. */
 typedef struct {

@@ -971,7 +971,7 @@ qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t 
   GUARD_BEGIN
   if (!out) return fail(QGM_E_ARG, "null argument");
   if (tile && (tile->per < 1 || tile->per > 16 || (tile->per & (tile->per - 1)) || tile->lds_budget < 1024 ||
-               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 15))
+               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 31))
     return fail(QGM_E_ARG, "tile parameters out of range");
   *out = nullptr;
   if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");
@@ -1216,14 +1216,35 @@ qgm_status qgm_plan_tune_tiles(qgm_plan* p, const char* table_path, void* stream
           if (st) break;
           if (!have || ms < best_ms) best = t, best_ms = ms, have = true;
         }
-      for (int lds : {53248, 81920, 114688})
-        for (int jb = 0; jb <= 3 && !st; ++jb) {
-          qgm_tile t{best.per, lds, jb, best.layout};
-          if (lds == 53248 && jb == 2) continue;  // timed in stage 1
+      // complex64 also tries its per-item form (FP32 16 x 16 x 4, layouts
+      // 16 + the per-item variants, + 8 for eight items per block)
+      if (key.prec == QGM_C64 && key.nk >= 2)
+        for (int layout : {16, 20, 21, 22, 24, 28, 29, 30})
+          for (int per : {1, 2}) {
+            if (st || 4 * per > (1 << key.nk)) continue;
+            qgm_tile t{per, layout & 8 ? 131072 : 65536, 0, layout};
+            float ms = 0;
+            st = time_tile(key, nb, t, ms);
+            if (!st && ms < best_ms) best = t, best_ms = ms;
+          }
+      if (best.layout & 16) {
+        for (int lds : best.layout & 8 ? std::vector<int>{65536, 98304, 163840} : std::vector<int>{32768, 49152, 98304}) {
+          if (st) break;
+          qgm_tile t{best.per, lds, 0, best.layout};
           float ms = 0;
           st = time_tile(key, nb, t, ms);
           if (!st && ms < best_ms) best = t, best_ms = ms;
         }
+      } else {
+        for (int lds : {53248, 81920, 114688})
+          for (int jb = 0; jb <= 3 && !st; ++jb) {
+            qgm_tile t{best.per, lds, jb, best.layout};
+            if (lds == 53248 && jb == 2) continue;  // timed in stage 1
+            float ms = 0;
+            st = time_tile(key, nb, t, ms);
+            if (!st && ms < best_ms) best = t, best_ms = ms;
+          }
+      }
     }
     if (st) break;
     table[key] = MfmaTile{best.per, best.lds_budget, best.jband, best.layout};

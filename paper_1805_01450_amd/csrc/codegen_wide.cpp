@@ -11,6 +11,8 @@
 // an output row are independent and issued together.
 #include <algorithm>
 #include <cstdio>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <sstream>
@@ -117,11 +119,11 @@ bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni
 // Tiles are numbered with the four item quads of a 128-byte line fastest
 // (they read the same lines at the same time), then j tiles, i tiles, b
 // bits and the four lines of a row; each XCD takes a contiguous range.
-static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int out, int r, int ns, int IT,
+static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int out, int r, int ns, int IT, int prec,
                              const int32_t* A, const int32_t* B, const std::vector<int>& bb, const std::vector<int>& bi,
                              const std::vector<int>& bj, const MfmaTile& tp, bool from_table, int& lds_bytes) {
   const int ni = (int)bi.size(), nj = (int)bj.size();
-  if (ni < 4 || nj < 4 || ns < 2 || (IT != 4 && IT != 8)) return false;
+  if (ni < 4 || nj < 4 || ns < 2 || (IT != 4 && IT != 8) || (prec != 1 && prec != 2)) return false;
   // IT items per block, one per wavefront: an operand row slot holds
   // SB = 8 IT bytes (LPR lanes of 16 bytes), a copy instruction RPI rows
   const int SB = 8 * IT, LPR = IT / 2, RPI = 64 / LPR, lg = IT == 4 ? 1 : 2;
@@ -172,7 +174,8 @@ static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int 
   const unsigned long long nb = 1ull << bits.size();
   k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
-    << "  // step " << si << " (matrix cores, per item) b " << nbb << " i " << ni << " j " << nj << " k " << ns << "\n"
+    << "  // step " << si << " (matrix cores, per item) b " << nbb << " i " << ni << " j " << nj << " k " << ns
+    << (prec == 1 ? " fp32" : " bf16x3") << "\n"
     << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
     << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
   k.blocks += nb;
@@ -261,7 +264,35 @@ static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int 
   issue("un", "(u + " + std::to_string(P - 1) + ") % " + std::to_string(P));
   o << "    }\n"
     << "    const char* sb = lds + (u % " << P << ") * " << stage << ";\n";
-  for (int t = 0; t < ku / 4; ++t) {
+  for (int t = 0; t < ku / 4 && prec == 1; ++t) {
+    // complex64: four FP32 16 x 16 x 4 products per tile and K step, lane
+    // group l / 16 holding complex k = 4 t + l / 16 (Cr += ar br - ai bi,
+    // Ci += ar bi + ai br)
+    const std::string T = std::to_string(t);
+    for (int f = 0; f < WM; ++f) {
+      const std::string F = T + "_" + std::to_string(f);
+      o << "    const C2 a" << F << " = *(const C2*)(sb + rda + " << SB * (4 * t * TM + 16 * f) << ");\n"
+        << "    const float na" << F << " = -a" << F << ".y;\n";
+    }
+    for (int g = 0; g < WN; ++g) {
+      const std::string G = T + "_" + std::to_string(g);
+      o << "    const C2 b" << G << " = *(const C2*)(sb + rdb + " << SB * (4 * t * TN + 16 * g) << ");\n";
+    }
+    for (int f = 0; f < WM; ++f)
+      for (int g = 0; g < WN; ++g) {
+        const std::string C = std::to_string(f) + "_" + std::to_string(g);
+        const std::string F = T + "_" + std::to_string(f), G = T + "_" + std::to_string(g);
+        o << "    cr" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(a" << F << ".x, b" << G << ".x, cr" << C
+          << ", 0, 0, 0);\n"
+          << "    cr" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(na" << F << ", b" << G << ".y, cr" << C
+          << ", 0, 0, 0);\n"
+          << "    ci" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(a" << F << ".x, b" << G << ".y, ci" << C
+          << ", 0, 0, 0);\n"
+          << "    ci" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(a" << F << ".y, b" << G << ".x, ci" << C
+          << ", 0, 0, 0);\n";
+      }
+  }
+  for (int t = 0; t < ku / 4 && prec == 2; ++t) {
     const std::string T = std::to_string(t);
     for (int f = 0; f < WM; ++f) {
       const std::string F = T + "_" + std::to_string(f);
@@ -380,13 +411,21 @@ static bool table_tile(const TileTable* tiles, int prec, int ni, int nj, int ns,
   return true;
 }
 
-// BF16x3 form choice: the per-item form for table layouts 0, 4, 5, 6 (plus
-// 8: eight items per block), built in for sums of 32 or more k (on shorter
-// sums, where the results' stores dominate, the 16-item forms store whole
-// 128-byte lines and were as fast or faster); its tile parameters.
-static bool bf16_per_item(bool from_table, const MfmaTile& tp, int ns, MfmaTile& t16, int& it_pref) {
+// Form choice of a matrix-core step.  Table layouts: 1, 2, 3 = 16-item
+// variants (7 = their built-in choice); 0, 4, 5, 6 = per-item full tile,
+// at most 32 rows, 32 columns, both (BF16x3), or the same plus 16 (either
+// precision); + 8 = eight items per block.  Built in: BF16x3 per-item for
+// sums of 32 or more k (on shorter sums, where the results' stores
+// dominate, the 16-item forms store whole 128-byte lines and were as fast
+// or faster), complex64 the 16-item form.
+static bool per_item_choice(int prec, bool from_table, const MfmaTile& tp, int ns, MfmaTile& t16, int& it_pref) {
   const int lay = tp.layout & 7;
-  const bool per_item = from_table ? lay == 0 || (lay >= 4 && lay <= 6) : ns >= 5;
+  const bool variant = lay == 0 || (lay >= 4 && lay <= 6);
+  bool per_item;
+  if (prec == 2)
+    per_item = from_table ? (tp.layout & 16) || variant : ns >= 5;
+  else
+    per_item = prec == 1 && from_table && (tp.layout & 16) && variant;
   t16 = from_table ? tp : MfmaTile{2, 65536, 0, 0};
   t16.layout = lay;
   it_pref = from_table && (tp.layout & 8) ? 8 : 4;
@@ -404,9 +443,9 @@ static int step_waves(int kind, int r, int ns, int prec, const std::vector<const
   MfmaTile tp, t16;
   const bool from_table = table_tile(tiles, prec, (int)bi.size(), (int)bj.size(), ns, tp);
   int it_pref = 4, lds = 0;
-  if (prec != 2 || !bf16_per_item(from_table, tp, ns, t16, it_pref)) return 1;
+  if (!per_item_choice(prec, from_table, tp, ns, t16, it_pref)) return 1;
   WideKernel scratch;
-  const bool ok8 = emit_mfma16_step(nullptr, scratch, 0, 0, r, ns, 8, rec[0], rec[1], bb, bi, bj, t16, true, lds);
+  const bool ok8 = emit_mfma16_step(nullptr, scratch, 0, 0, r, ns, 8, prec, rec[0], rec[1], bb, bi, bj, t16, true, lds);
   return 1 | (ok8 ? 2 : 0) | (ok8 && it_pref == 8 ? 4 : 0);
 }
 
@@ -421,14 +460,13 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   // unit, a ring of at most 52 KiB, bands of four j blocks).
   MfmaTile tp;
   const bool from_table = table_tile(tiles, prec, (int)bi.size(), (int)bj.size(), ns, tp);
-  // BF16x3: the full-rate per-item form, as many items per block as the
-  // level kernel has wavefronts, or the 16-item forms (1, 2, 3; 7 = their
-  // built-in choice), which need four wavefronts
-  if (prec == 2) {
+  // the per-item form, as many items per block as the level kernel has
+  // wavefronts, or the 16-item forms, which need four wavefronts
+  {
     MfmaTile t16;
     int it_pref = 4;
-    if (bf16_per_item(from_table, tp, ns, t16, it_pref) &&
-        emit_mfma16_step(&o, k, si, out, r, ns, W, A, B, bb, bi, bj, t16, true, lds_bytes))
+    if (per_item_choice(prec, from_table, tp, ns, t16, it_pref) &&
+        emit_mfma16_step(&o, k, si, out, r, ns, W, prec, A, B, bb, bi, bj, t16, true, lds_bytes))
       return true;
   }
   if (W != 4) return false;
@@ -676,7 +714,7 @@ bool read_tile_table(const std::string& path, TileTable& t, std::string& err) {
     int n = std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
     if (n <= 0) continue;  // blank or comment
     if (n != 8 || v[0] < 0 || v[0] > 2 || v[1] < 4 || v[2] < 4 || v[3] < 1 || v[3] > 16 || v[4] < 1 || v[4] > 16 ||
-        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 15) {
+        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 31) {
       err = "tile table " + path + " line " + std::to_string(ln) + ": expected prec ni nj nk per lds_budget jband layout";
       ok = false;
       break;
@@ -873,11 +911,42 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       // by the next tiles while it is still in cache; the bits every large
       // operand shares vary slowest.  perm[k] is the output bit at position k.
       std::vector<int> perm(r), weight(r, 0);
+      std::vector<double> wbytes(r, 0.0);
       for (int j = 0; j < r; ++j) {
         perm[j] = j;
         for (int i = 0; i < m; ++i) weight[j] += rec[i][0] == WOP_ITEM && rec[i][16 + j] != 0;
       }
-      std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return weight[x] < weight[y]; });
+      {
+        // A streaming step (at most 3 summed bits) whose largest item
+        // operand is at least 8 times larger than every other: ties are
+        // broken by the size of the operands a bit indexes, so the bits the
+        // large operand does not carry vary first and its rows are reused
+        // by the neighbouring tiles of one block instead of being fetched
+        // again by tiles on other XCDs.  GEMM-shaped steps keep the plain
+        // order (the size order made such complex128 steps up to 2.3x
+        // slower).
+        std::vector<double> sz;
+        for (int i = 0; i < m; ++i) {
+          if (rec[i][0] != WOP_ITEM) continue;
+          int nv = 0;
+          for (int j = 0; j < r; ++j) nv += rec[i][16 + j] != 0;
+          for (int j = 0; j < ns; ++j) nv += rec[i][48 + j] != 0;
+          sz.push_back(std::ldexp(1.0, nv));
+        }
+        std::sort(sz.rbegin(), sz.rend());
+        if (ns <= 3 && sz.size() >= 2 && sz[0] >= 8 * sz[1])
+          for (int i = 0; i < m; ++i) {
+            if (rec[i][0] != WOP_ITEM) continue;
+            int nv = 0;
+            for (int j = 0; j < r; ++j) nv += rec[i][16 + j] != 0;
+            for (int j = 0; j < ns; ++j) nv += rec[i][48 + j] != 0;
+            for (int j = 0; j < r; ++j)
+              if (rec[i][16 + j]) wbytes[j] += std::ldexp(1.0, nv);
+          }
+      }
+      std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+        return weight[x] != weight[y] ? weight[x] < weight[y] : wbytes[x] < wbytes[y];
+      });
       // Tile: the first L bits of perm.  A wavefront keeps 2^L accumulators
       // (64 items each) and, per summed index, loads each operand row the
       // tile needs once: a register-blocked contraction.  L grows while the

@@ -125,7 +125,15 @@ def test_contraction_rejects_bad_shapes():
 TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0), (4, 81920, 1, 1),
          (1, 53248, 2, 2), (4, 114688, 2, 3), (2, 53248, 3, 1),
          (1, 98304, 0, 4), (2, 49152, 0, 5), (1, 32768, 0, 6),
-         (2, 131072, 0, 8), (1, 131072, 1, 8), (2, 98304, 0, 13)]
+         (2, 131072, 0, 8), (1, 131072, 1, 8), (2, 98304, 0, 13),
+         # the per-item form for either precision (complex64: FP32 16 x 16 x 4)
+         (2, 65536, 0, 16), (1, 131072, 0, 24), (2, 98304, 0, 21)]
+
+
+def _per_item(prec, layout):
+    if prec == q.QGM_BF16X3:
+        return bool(layout & 16) or (layout & 7) in (0, 4, 5, 6)
+    return bool(layout & 16)
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -133,10 +141,12 @@ TILES = [(1, 53248, 2, 0), (4, 53248, 2, 0), (2, 81920, 0, 0), (2, 114688, 3, 0)
 def test_tile_variants_match_builtin_tile(tile, prec):
     """Every tile parameter set keeps the k order of each output's sum, so the
     result equals the built-in tile's bit for bit (and meets the bound).
-    BF16x3 has two families, the per-item 16 x 16 x 32 form (built in for
-    this K = 32 shape; layouts 0 and 4 to 6, plus 8 for eight items per
-    block) and the 16-item 4 x 4 x 4 forms (layouts 1 to 3): the latter sum
-    the same terms in another order and meet the bound."""
+    Each precision has two families, the per-item forms (BF16x3 16 x 16 x
+    32, built in for this K = 32 shape: layouts 0 and 4 to 6, or + 16;
+    complex64 16 x 16 x 4: layouts + 16; + 8 for eight items per block) and
+    the 16-item forms (layouts 1 to 3; complex64's built-in): across
+    families the same terms are summed in another order and meet the
+    bound."""
     import torch
     if prec == q.QGM_BF16X3 and tile[0] == 1 and tile[3] in (1, 2, 3):
         tile = (2,) + tile[1:]
@@ -162,7 +172,8 @@ def test_tile_variants_match_builtin_tile(tile, prec):
     c1.run(d_mem, 2)
     torch.cuda.synchronize()
     got1 = d_mem.cpu().numpy()[:, ea + eb:, :].transpose(0, 2, 1).reshape(items, 1 << nb, 1 << nj, 1 << ni)
-    if prec == q.QGM_BF16X3 and tile[3] in (1, 2, 3):
+    builtin_per_item = prec == q.QGM_BF16X3  # for this K = 32 shape
+    if _per_item(prec, tile[3]) != builtin_per_item:
         assert (np.abs(got1 - want) / mag).max() <= _eps(prec, 1 << nk)
     else:
         assert np.array_equal(got1, got0)
@@ -170,10 +181,10 @@ def test_tile_variants_match_builtin_tile(tile, prec):
 
 def test_plan_tile_tuner_and_table(tmp_path):
     """qgm_plan_tune_tiles on the 7x7x30 plan writes a table; a plan created
-    with it gives the default plan's amplitudes: complex64 bit for bit (tiles
-    change neither the k order of a sum nor which products are formed);
-    BF16x3 within its error bound, since the tuner may pick the other form
-    family for a shape (same products, another summation order)."""
+    with it gives the default plan's amplitudes within the precision's
+    bound: tiles of one form family keep the k order of every sum, but the
+    tuner may pick the other family for a shape (the same products summed
+    in another order)."""
     import json
     import os
     from workload import generate_circuit, random_bitstrings
@@ -189,8 +200,6 @@ def test_plan_tile_tuner_and_table(tmp_path):
         assert n >= 1
         t = q.Plan(c, rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE, tile_table_path=table)
         got, want = t.amplitudes(bits), p.amplitudes(bits)
-        if prec == q.QGM_C64:
-            assert np.array_equal(got, want)
-        else:
-            tol = np.sqrt(p.stats()["n_steps"]) * 3 * 2.0 ** -16
-            assert np.max(np.abs(got - want) / np.abs(want)) <= tol
+        tol = 2e-4 if prec == q.QGM_C64 else np.sqrt(p.stats()["n_steps"]) * 3 * 2.0 ** -16
+        note("tuned against built-in tiles, max rel diff", np.max(np.abs(got - want) / np.abs(want)))
+        assert np.max(np.abs(got - want) / np.abs(want)) <= tol

@@ -370,12 +370,12 @@ SHAPE_212 = ("w4 & 1", "0", "w4 >> 1")
 
 @pytest.mark.parametrize("plan,max_blocks,prec,table", [("7x7x30", None, q.QGM_C64, False),
                                                         ("7x7x30", None, q.QGM_BF16X3, False),
-                                                        ("8x8x40-k8", 8, q.QGM_C64, False),
+                                                        ("8x8x40-k8", 4, q.QGM_C64, True),
                                                         ("8x8x40-k8", 4, q.QGM_BF16X3, True)])
 def test_matrix_core_step_indexing_stored_plans(plan, max_blocks, prec, table, tmp_path, monkeypatch):
     """Every matrix-core step of the stored plans (of the benchmark's 8x8x40
-    k = 8 plan: the first and last blocks of each step; BF16x3 with the
-    stored tile table the benchmark uses)."""
+    k = 8 plan: the first and last blocks of each step, with the stored tile
+    table the benchmark uses)."""
     here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
     rec = json.load(open(os.path.join(here, plan + ".json")))
     cz = rec["circuit"]
@@ -457,5 +457,25 @@ def test_per_item_form_variants(tile, shape, tmp_path, monkeypatch):
         for f in glob.glob(str(tmp_path / "qgm_contract_*.hip")):
             os.remove(f)
         q.Contraction(q.QGM_BF16X3, *shape, tile=(tile[0], tile[1], 1, tile[3]))
+        direct = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+        check_epilogue16(src, direct)
+
+
+@pytest.mark.parametrize("tile", [(2, 65536, 0, 16), (1, 131072, 0, 24), (2, 65536, 0, 21), (1, 49152, 1, 22)])
+@pytest.mark.parametrize("shape", [(1, 6, 7, 5), (0, 6, 6, 3)])
+def test_per_item_form_complex64(tile, shape, tmp_path, monkeypatch):
+    """complex64 in the per-item form (FP32 16 x 16 x 4): the same copies,
+    operand reads and result placement as the BF16x3 form."""
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    con = q.Contraction(q.QGM_C64, *shape, tile=tile)
+    assert con.matrix_cores
+    src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+    assert "__builtin_amdgcn_mfma_f32_16x16x4f32" in src
+    n, shapes = check_source(src, con.elems, max_blocks=16)
+    assert n == 1 and shapes == {"per item x8" if tile[3] & 8 else "per item"}
+    if tile[2] != 1:
+        for f in glob.glob(str(tmp_path / "qgm_contract_*.hip")):
+            os.remove(f)
+        q.Contraction(q.QGM_C64, *shape, tile=(tile[0], tile[1], 1, tile[3]))
         direct = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
         check_epilogue16(src, direct)
