@@ -15,6 +15,8 @@
 // Tensors that depend on no fixed variable are the same for every item and
 // are computed once per call ("constant" steps).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
 #include <cmath>
 #include <cstring>
@@ -437,25 +439,32 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       // A large step also takes over the eliminations that follow it in the
       // order while each touches its output and, besides, only small tensors
       // (constants, leaves, rank <= 2) over variables the step already
-      // spans: those variables are summed here, and the large intermediates
-      // between the steps are never written (the sums are regrouped).
+      // spans, plus at most one variable new to it (the eliminated variable
+      // is summed here, so the span stays the same): those variables are
+      // summed here, and the large intermediates between the steps are never
+      // written (the sums are regrouped; the pairwise pre-contraction below
+      // then folds such a factor into the operand it shares variables with).
       constexpr int kFuseMinSpan = 16, kFuseMaxSum = 8;
       for (size_t oi = (size_t)pos[v] + 1; oi < order.size(); ++oi) {
         const int u = order[oi];
         if (done[u] || std::find(S.begin(), S.end(), u) != S.end()) continue;
         if ((int)(out.size() + S.size()) < kFuseMinSpan || (int)S.size() >= kFuseMaxSum) break;
         if (std::find(out.begin(), out.end(), u) == out.end()) break;
-        std::vector<int> tu;
+        std::vector<int> tu, fresh;
         bool ok = true;
         for (size_t i = 0; i < T.size() && ok; ++i) {
           if (!T[i].alive || std::find(tv.begin(), tv.end(), (int)i) != tv.end()) continue;
           if (std::find(T[i].vars.begin(), T[i].vars.end(), u) == T[i].vars.end()) continue;
           ok = T[i].is_const || T[i].leaf >= 0 || T[i].vars.size() <= 2;
           for (int w : T[i].vars)
-            ok = ok && (std::find(out.begin(), out.end(), w) != out.end() ||
-                        std::find(S.begin(), S.end(), w) != S.end());
+            if (std::find(out.begin(), out.end(), w) == out.end() && std::find(S.begin(), S.end(), w) == S.end() &&
+                std::find(fresh.begin(), fresh.end(), w) == fresh.end())
+              fresh.push_back(w);
           tu.push_back((int)i);
         }
+        // one variable new to the step is taken along: u is summed here,
+        // so the step's span stays the same
+        ok = ok && fresh.size() <= 1;
         if (!ok) break;
         tv.insert(tv.end(), tu.begin(), tu.end());
         split_vars();

@@ -230,3 +230,26 @@ def test_config4_checkpointed_gradient_vs_oracle(config4_rz, ck):
     assert a == a0
     assert np.max(np.abs(d - d0)) <= 1e-14 * scale
     assert np.max(np.abs(d[which] - want)) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("prec", [q.QGM_C128, q.QGM_C64, q.QGM_BF16X3])
+def test_benchmark_whole_amplitude_vs_oracle(prec):
+    """The benchmark's result itself: the whole 8x8x40 amplitude (all 256
+    slices of the stored k = 8 plan, the matrix-core steps and the stored
+    tile table as bench.py runs them) against the FP64 oracle's sum of every
+    slice (tests/golden/make_stored_plan_slices.py --whole)."""
+    gold = GOLD["8x8x40-k8-whole"]
+    rec = _plan_rec("8x8x40-k8")
+    c = rec["circuit"]
+    assert gold["circuit"] == c and gold["k"] == rec["k"] == 8
+    text = generate_circuit(c["n"], c["depth"], c["seed"])
+    x = random_bitstrings(c["n"] ** 2, 1, gold["bitstring_seed"])[0]
+    tiles = os.path.join(os.path.dirname(q.__file__), "plans", "tiles_mi355x.txt")
+    p = q.Plan(q.Circuit(text), rec["sliced"], rec["order"], prec=prec, engine=q.QGM_ENGINE_WIDE,
+               tile_table_path=tiles if prec != q.QGM_C128 else None)
+    got = p.amplitudes([x])[0]
+    ref = complex(gold["alpha"][0], gold["alpha"][1])
+    tol = {q.QGM_C128: C128_TOL, q.QGM_C64: C64_TOL, q.QGM_BF16X3: bf16x3_tol(p.stats()["n_steps"])}[prec]
+    err = abs(got - ref) / abs(ref)
+    note("8x8x40-k8 whole amplitude prec", prec, got, "oracle", ref, "rel err", err, "tol", tol)
+    assert err <= tol
