@@ -35,6 +35,7 @@ PEAK_FP32_VECTOR_NONPACKED_TFLOPS = 78.6  # the same without packed FP32, which 
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X published dense FP32 matrix-core peak
 PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X published dense BF16 matrix-core peak
 PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X published dense FP64 matrix-core peak
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X published vector FP64 peak
 PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")  # rocprofv3 HBM byte counters, summarised
 GOLDEN_SLICES = os.path.join(ROOT, "tests", "golden", "stored_plan_slices.json")
@@ -230,7 +231,8 @@ def level_roofline(levels, workload, prec_name):
     # the bfloat16 peak over the three bfloat16 products per real product
     mpeak = {"c128": PEAK_FP64_MATRIX_TFLOPS, "bf16x3": PEAK_BF16_MATRIX_TFLOPS / 3}.get(prec_name,
                                                                                        PEAK_FP32_MATRIX_TFLOPS)
-    peak = mpeak if mf_l[i] else PEAK_FP32_VECTOR_TFLOPS
+    vpeak = PEAK_FP64_VECTOR_TFLOPS if prec_name == "c128" else PEAK_FP32_VECTOR_TFLOPS
+    peak = mpeak if mf_l[i] else vpeak
     traffic = measured_traffic(workload, f"wl{i}", 1, prec_name)
     roof = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
             "frac": k_tf / peak, "traffic": traffic, "kernel": f"wl{i} (generated level kernel, {prec_name})",
@@ -240,7 +242,7 @@ def level_roofline(levels, workload, prec_name):
     for j in sorted(range(len(ms_l)), key=lambda x: -ms_l[x])[:8]:
         tf = fl_l[j] * items_l / (ms_l[j] * 1e-3) / 1e12
         gb = by_l[j] * items_l / (ms_l[j] * 1e-3) / 1e9
-        pk = mpeak if mf_l[j] else PEAK_FP32_VECTOR_TFLOPS
+        pk = mpeak if mf_l[j] else vpeak
         fr_f, fr_b = tf / pk, gb / PEAK_HBM_GBS
         per_level.append({"kernel": f"wl{j}", "ms": ms_l[j], "tflops": tf, "hbm_gbs": gb,
                           "bound": ("mfma" if mf_l[j] else "alu") if fr_f >= fr_b else "hbm",
