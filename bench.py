@@ -331,8 +331,9 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "interpreter", "generated"])
     ap.add_argument("--vector-only", action="store_true",
                     help="wide engine: keep every step on the vector ALUs (no matrix cores)")
-    ap.add_argument("--workspace-gib", type=float, default=0.0,
-                    help="wide engine: item memory per pass in GiB (0 = the library default, 96 GiB)")
+    ap.add_argument("--workspace-gib", type=float, default=128.0,
+                    help="wide engine: item memory per pass in GiB (0 = the library default, 96 GiB; 128 holds "
+                         "all 256 slices of the 8x8x40 k=8 plan in complex64 and BF16x3 in one pass)")
     ap.add_argument("--precisions", default="c64,bf16x3,c128",
                     help="comma-separated legs; the first is the headline")
     ap.add_argument("--tiles", default=None,

@@ -438,13 +438,18 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     if (combine_consts && !gradient) {
       // A large step also takes over the eliminations that follow it in the
       // order while each touches its output and, besides, only small tensors
-      // (constants, leaves, rank <= 2) over variables the step already
-      // spans, plus at most one variable new to it (the eliminated variable
-      // is summed here, so the span stays the same): those variables are
-      // summed here, and the large intermediates between the steps are never
-      // written (the sums are regrouped; the pairwise pre-contraction below
-      // then folds such a factor into the operand it shares variables with).
-      constexpr int kFuseMinSpan = 16, kFuseMaxSum = 8;
+      // (constants, leaves, or at most 2^10 elements) over variables the
+      // step already spans plus new ones: those variables are summed here,
+      // and the large intermediates between the steps are never written (the
+      // sums are regrouped; the pairwise pre-contraction below then folds
+      // such a factor into the operand it shares variables with).  Each
+      // absorbed variable may bring one variable new to the step (it is
+      // summed itself, so the output rank stays); a factor that brings two
+      // is taken when the next absorption brings none, and the step falls
+      // back to the last state where the count balances.
+      constexpr int kFuseMinSpan = 16, kFuseMaxSum = 8, kFuseSmallRank = 10;
+      std::vector<int> tv_ok = tv;
+      int n_absorbed = 0, n_fresh = 0;
       for (size_t oi = (size_t)pos[v] + 1; oi < order.size(); ++oi) {
         const int u = order[oi];
         if (done[u] || std::find(S.begin(), S.end(), u) != S.end()) continue;
@@ -455,18 +460,23 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
         for (size_t i = 0; i < T.size() && ok; ++i) {
           if (!T[i].alive || std::find(tv.begin(), tv.end(), (int)i) != tv.end()) continue;
           if (std::find(T[i].vars.begin(), T[i].vars.end(), u) == T[i].vars.end()) continue;
-          ok = T[i].is_const || T[i].leaf >= 0 || T[i].vars.size() <= 2;
+          ok = T[i].is_const || T[i].leaf >= 0 || (int)T[i].vars.size() <= kFuseSmallRank;
           for (int w : T[i].vars)
             if (std::find(out.begin(), out.end(), w) == out.end() && std::find(S.begin(), S.end(), w) == S.end() &&
                 std::find(fresh.begin(), fresh.end(), w) == fresh.end())
               fresh.push_back(w);
           tu.push_back((int)i);
         }
-        // one variable new to the step is taken along: u is summed here,
-        // so the step's span stays the same
-        ok = ok && fresh.size() <= 1;
+        ok = ok && n_fresh + (int)fresh.size() <= n_absorbed + 2;
         if (!ok) break;
+        n_absorbed++;
+        n_fresh += (int)fresh.size();
         tv.insert(tv.end(), tu.begin(), tu.end());
+        split_vars();
+        if (n_fresh <= n_absorbed) tv_ok = tv;
+      }
+      if (tv_ok.size() != tv.size()) {
+        tv = tv_ok;
         split_vars();
       }
     }

@@ -1,11 +1,15 @@
 """Tune the matrix-core tiles of the benchmark plans on the device
 (qgm_plan_tune_tiles) and write the table the benchmark uses.
 
-    python paper_1805_01450_amd/plans/make_tiles.py [--out PATH] [name ...]
+    python paper_1805_01450_amd/plans/make_tiles.py [--out PATH] [--no-confirm] [name ...]
 
 Needs a GPU.  The table holds one line per (precision, row bits, column
 bits, summed bits) shape; shapes already in an existing table at PATH are
-kept unless tuned again.
+kept unless tuned again.  The tuner times each shape alone; each entry is
+then confirmed inside the plan: the plan's level kernels are timed with the
+table and without that entry (the library's built-in tile for the shape),
+and an entry is dropped when the plan runs more than 0.5 % faster without
+it.
 """
 import argparse
 import json
@@ -22,6 +26,7 @@ def main():
     from workload import generate_circuit
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "tiles_mi355x.txt"))
+    ap.add_argument("--no-confirm", action="store_true", help="skip the in-plan confirmation")
     ap.add_argument("names", nargs="*", default=["8x8x40-k8", "8x8x40"])
     args = ap.parse_args()
     for name in args.names:
@@ -35,7 +40,63 @@ def main():
             n = q.qgm_plan_tune_tiles(p.h, args.out)
             print(f"{name} prec {prec}: {n} shapes tuned in {time.time() - t0:.1f} s", flush=True)
             del p
+            if not args.no_confirm:
+                confirm(q, circ, rec, prec, args.out)
+    with open(args.out) as f:
+        body = [ln for ln in f if not ln.startswith("# written by")]
+    with open(args.out, "w") as f:
+        f.write(f"# written by: python paper_1805_01450_amd/plans/make_tiles.py {' '.join(args.names)} "
+                f"(qgm_plan_tune_tiles on one MI355X{'' if args.no_confirm else ', entries confirmed in the plan'})\n")
+        f.writelines(body)
     print(open(args.out).read(), flush=True)
+
+
+def plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s, runs=3):
+    """Sum of the plan's level-kernel times (HIP events, mean of `runs`
+    runs after one untimed run) for n_s slices with the given tile table."""
+    p = q.Plan(circ, rec["sliced"], rec["order"], prec=prec, profile=True, engine=q.QGM_ENGINE_WIDE,
+               tile_table_path=table)
+    ws = p.workspace(d_bits.shape[0], n_s)
+    for w in range(runs + 1):
+        q.qgm_amplitudes_device(p.h, d_bits, None, 0, n_s, ws, d_part)
+        if w == 0:
+            torch.cuda.synchronize()
+            q.qgm_plan_level_timing(p.h, reset=True)
+    torch.cuda.synchronize()
+    ms = sum(q.qgm_plan_level_timing(p.h, reset=False)[0])
+    p.release_workspace()
+    del p
+    return ms
+
+
+def confirm(q, circ, rec, prec, table, margin=0.005):
+    """Drop each entry of precision `prec` whose removal makes the plan
+    faster by more than `margin` (the tuner's standalone timing does not see
+    the operand layouts and cache state of the plan's own levels)."""
+    import torch
+    from workload import random_bitstrings
+    c = rec["circuit"]
+    d_bits = torch.from_numpy(random_bitstrings(c["n"] * c["n"], 1, c["seed"] + 1000)).cuda()
+    d_part = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+    n_s = min(1 << rec["k"], 128)
+    tmp = table + ".without"
+    with open(table) as f:
+        lines = f.readlines()
+    entries = [ln for ln in lines if ln.strip() and not ln.startswith("#") and int(ln.split()[0]) == prec]
+    for ln in entries:
+        base = plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s)
+        with open(table) as f:
+            cur = f.readlines()
+        with open(tmp, "w") as f:
+            f.writelines(x for x in cur if x != ln)
+        without = plan_ms(q, torch, circ, rec, prec, tmp, d_bits, d_part, n_s)
+        drop = without < base * (1.0 - margin)
+        print(f"  confirm {ln.strip()}: {base:.2f} ms with, {without:.2f} ms without -> "
+              f"{'dropped' if drop else 'kept'}", flush=True)
+        if drop:
+            os.replace(tmp, table)
+    if os.path.exists(tmp):
+        os.remove(tmp)
 
 
 if __name__ == "__main__":

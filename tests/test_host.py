@@ -222,8 +222,10 @@ def test_stored_plans_are_valid(monkeypatch):
         assert sorted(rec["order"]) == sorted(set(free) - set(rec["sliced"]))
         q.qgm_order_cost(c.h, rec["sliced"], rec["order"])  # the library validates the plan
         if os.path.basename(path) in ("7x7x30.json", "8x8x40.json"):  # compiled in full for the main two
+            # the recorded rank is the program's when the plan was searched;
+            # the program transforms merge steps and never raise it
             st = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE).stats()
-            assert st["max_rank"] == rec["max_rank"]
+            assert 0 < st["max_rank"] <= rec["max_rank"]
 
 
 def test_matrix_core_step_selection():
@@ -271,9 +273,10 @@ def test_planner_choose_k():
 
 def test_workspace_cap_applies_to_the_wide_program(monkeypatch):
     """The cap is checked against the program the wide engine runs: at
-    8x8x40, k = 8 one 64-slice group needs 33.6 GiB after the constant
-    regrouping (far more before it), so a 40 GiB cap is accepted and a
-    30 GiB cap is refused."""
+    8x8x40, k = 8 one 64-slice group needs about 28 GiB after the constant
+    regrouping and the step merges (far more before them), so a cap at that
+    need, rounded up to a GiB, is accepted and one a GiB below it is
+    refused."""
     monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")  # structure only: no kernel build
     import json
     import os
@@ -283,10 +286,13 @@ def test_workspace_cap_applies_to_the_wide_program(monkeypatch):
     cz = rec["circuit"]
     c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
     st = q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE,
-                workspace_cap=40 << 30).stats()
-    assert st["item_elems"] * 64 * 8 < 40 << 30
+                workspace_cap=48 << 30).stats()
+    need = st["item_elems"] * 64 * 8
+    assert 16 << 30 < need < 40 << 30
+    cap = -(-need // (1 << 30)) << 30
+    q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, workspace_cap=cap)
     with pytest.raises(q.QgmError) as e:
-        q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, workspace_cap=30 << 30)
+        q.Plan(c, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, workspace_cap=cap - (1 << 30))
     assert e.value.status == -5
 
 
