@@ -479,3 +479,27 @@ def test_per_item_form_complex64(tile, shape, tmp_path, monkeypatch):
         q.Contraction(q.QGM_C64, *shape, tile=(tile[0], tile[1], 1, tile[3]))
         direct = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
         check_epilogue16(src, direct)
+
+
+@pytest.mark.parametrize("prec,tile", [(q.QGM_C64, (2, 65536, 0, 16)), (q.QGM_C64, (1, 131072, 0, 24)),
+                                       (q.QGM_C64, (2, 65536, 1, 21)), (q.QGM_BF16X3, (2, 65536, 0, 0)),
+                                       (q.QGM_BF16X3, (2, 131072, 0, 8)), (q.QGM_BF16X3, (2, 65536, 1, 4))])
+@pytest.mark.parametrize("shape", [(0, 6, 6, 3), (1, 6, 7, 5), (1, 7, 6, 2)])
+def test_per_item_results_cover_the_output(prec, tile, shape, tmp_path, monkeypatch):
+    """Over all blocks of a per-item step, the results of every item and
+    output element are written exactly once: the tile index covers each
+    (item group, row tile, column tile, batch) combination once."""
+    monkeypatch.setenv("QGM_DUMP_DIR", str(tmp_path))
+    con = q.Contraction(prec, *shape, tile=tile)
+    assert con.matrix_cores
+    src = open(glob.glob(str(tmp_path / "qgm_contract_*.hip"))[0]).read()
+    m = STEP.search(src)
+    assert m.group(4)
+    S, E = int(m.group(1)), int(m.group(2))
+    lds_size = int(list(re.finditer(r"char lds\[(\d+)\]", src[:m.start()]))[-1].group(1))
+    res = _result_map(m.group(5), S, E - S, lds_size, _threads(src, m.start()))
+    dst = np.array(list(res.values()), dtype=np.int64)
+    nb, ni, nj, _ = shape
+    assert len(dst) == 64 << (nb + ni + nj)
+    assert len(np.unique(dst)) == len(dst)
+    assert dst.min() >= 0 and dst.max() < con.elems * 64
