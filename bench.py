@@ -223,10 +223,13 @@ def level_roofline(levels, workload, prec_name):
     """Roofline of the dominant level kernel (longest HIP-event duration) and
     of the eight longest: the ceiling each is closest to (matrix cores,
     vector ALUs or HBM) and that fraction."""
-    ms_l, fl_l, mf_l, _, items_l, by_l = levels  # the first pass of items is timed
+    # the first pass of items is timed; flops and bytes count a step shared
+    # between the pass's groups once per pass
+    ms_l, fl_l, mf_l, _, items_l, by_l, _ = levels
     i = max(range(len(ms_l)), key=lambda j: ms_l[j])
     k_flops = fl_l[i] * items_l
     k_tf = k_flops / (ms_l[i] * 1e-3) / 1e12
+    k_gbs = by_l[i] * items_l / (ms_l[i] * 1e-3) / 1e9
     # matrix-core peak in useful (complex) flops: FP64, FP32, or for BF16x3
     # the bfloat16 peak over the three bfloat16 products per real product
     mpeak = {"c128": PEAK_FP64_MATRIX_TFLOPS, "bf16x3": PEAK_BF16_MATRIX_TFLOPS / 3}.get(prec_name,
@@ -234,10 +237,17 @@ def level_roofline(levels, workload, prec_name):
     vpeak = PEAK_FP64_VECTOR_TFLOPS if prec_name == "c128" else PEAK_FP32_VECTOR_TFLOPS
     peak = mpeak if mf_l[i] else vpeak
     traffic = measured_traffic(workload, f"wl{i}", 1, prec_name)
-    roof = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
-            "frac": k_tf / peak, "traffic": traffic, "kernel": f"wl{i} (generated level kernel, {prec_name})",
-            "kernel_ms": ms_l[i], "flops_per_launch": k_flops, "algorithmic_bytes_per_launch": by_l[i] * items_l,
-            "matrix_core_steps": mf_l[i], "slices_per_launch": items_l}
+    # the ceiling the kernel is closest to: its arithmetic (matrix cores or
+    # vector ALUs) or HBM
+    if k_gbs / PEAK_HBM_GBS > k_tf / peak:
+        roof = {"bound": "hbm", "achieved": k_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": k_gbs / PEAK_HBM_GBS,
+                "achieved_tflops": k_tf, "frac_of_arith_peak": k_tf / peak}
+    else:
+        roof = {"bound": "mfma" if mf_l[i] else "alu", "achieved": k_tf, "peak": peak, "unit": "TFLOP/s",
+                "frac": k_tf / peak}
+    roof.update({"traffic": traffic, "kernel": f"wl{i} (generated level kernel, {prec_name})",
+                 "kernel_ms": ms_l[i], "flops_per_launch": k_flops, "algorithmic_bytes_per_launch": by_l[i] * items_l,
+                 "matrix_core_steps": mf_l[i], "slices_per_launch": items_l})
     per_level = []
     for j in sorted(range(len(ms_l)), key=lambda x: -ms_l[x])[:8]:
         tf = fl_l[j] * items_l / (ms_l[j] * 1e-3) / 1e12
@@ -450,9 +460,16 @@ def main():
                     if st["engine"] == q.QGM_ENGINE_GENERATED else None,
                     "kernel": {1: "chain_kernel", 2: "qgm_chain (generated)"}.get(st["engine"], "?"),
                     "kernel_ms": k_ms, "flops_per_launch": flops_launch}
+    # work per slice as run: steps shared between the groups of a pass
+    # count once per pass (the timed first pass; the whole run is one pass
+    # when the workspace holds it)
+    lv = r["levels"] if wide and r["levels"] and r["levels"][0] else None
+    flops_run = sum(lv[1]) if lv else st["flops_item"]
+    bytes_run = sum(lv[5]) if lv else st["bytes_item"]
+    roof_run = lv[6] if lv else st["roof_s_item"]
     roofline["chain_ms"] = r["ms_chain"]
-    roofline["chain_tflops"] = flops_launch / (r["ms_chain"] * 1e-3) / 1e12
-    roofline["chain_hbm_gbs"] = st["bytes_item"] * n_items / (r["ms_chain"] * 1e-3) / 1e9
+    roofline["chain_tflops"] = flops_run * n_items / (r["ms_chain"] * 1e-3) / 1e12
+    roofline["chain_hbm_gbs"] = bytes_run * n_items / (r["ms_chain"] * 1e-3) / 1e9
 
     a128 = complex(results["c128"]["amps"][0]) if "c128" in results else None
 
@@ -485,6 +502,7 @@ def main():
                    "matrix_core_tiles": os.path.relpath(tile_path, ROOT) if tile_path else "built-in",
                    "compile_s": round(st["compile_s"], 1), "max_rank": st["max_rank"],
                    "flops_per_slice": st["flops_item"], "bytes_per_slice": st["bytes_item"],
+                   "flops_per_slice_run": flops_run, "bytes_per_slice_run": bytes_run,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "engine": {1: "interpreter", 2: "generated", 3: "wide"}[st["engine"]],
@@ -494,7 +512,7 @@ def main():
         "mfma_flops_share": st["flops_mfma"] / st["flops_item"],
         "mfma_steps": st["mfma_steps"],
         "launches_per_pass": st["launches"],
-        "roofline_time_frac": st["roof_s_item"] * n_items / (ms_step * 1e-3) if wide else None,
+        "roofline_time_frac": roof_run * n_items / (ms_step * 1e-3) if wide else None,
     }
     if n_run is None and n_bs == 1:
         line["amplitude"] = [complex(r["amps"][0]).real, complex(r["amps"][0]).imag]

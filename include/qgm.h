@@ -259,6 +259,28 @@ qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t targe
 qgm_status qgm_order_search(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k, const int32_t* init_order,
                             int32_t n_order, int64_t max_nodes, int32_t beam, int32_t* order_out, double* cost,
                             int32_t* width, int32_t* complete);
+/* Not in the paper (a layout choice of this library).  The same sliced
+ * variables in an order for group sharing.  Slice s fixes sliced_vars[j] to
+ * bit j of s; 64 consecutive slices form one item group, so bits 6 and up
+ * tell the groups of a pass apart, and an item step that depends on none of
+ * the sliced variables at the bits that vary within a pass (nor on the
+ * output bits, when a pass spans several bitstrings) is computed once per
+ * pass and read by every group (WIDE engine; only when the call's slice
+ * range starts at a multiple of 64 and holds a multiple of 64 slices).
+ * From bit 6 up, each position gets the variable that leaves the most item
+ * work (the compiled program's per-step roofline time) independent of the
+ * variables already placed there; bits 0..5 keep the others in their given
+ * order.  The amplitude (the sum over all slices) does not change; which
+ * assignment a single slice index denotes does.  qgm_plan_slices and
+ * qgm_plan_slices_ex return their sliced variables in this order.
+ * sliced_out: k ids (may alias sliced_vars only if the caller copies them
+ * first: it is written after the input is read).  *shared_frac (may be
+ * NULL): the fraction of the item work independent of the variables at
+ * bits 6 and 7.  k <= 6: the input order.  Errors: QGM_E_SLICE,
+ * QGM_E_ORDER as for qgm_plan_create, QGM_E_ARG. */
+qgm_status qgm_sliced_order_for_groups(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k,
+                                       const int32_t* order, int32_t n_order, int32_t* sliced_out,
+                                       double* shared_frac);
 /* Cost (sum of 2^deg(v)) and width (max deg(v)) of eliminating `order` after
  * removing the sliced vertices (Section "Variable elimination", cost model).
  * Errors: QGM_E_SLICE, QGM_E_ORDER as for qgm_plan_create. */
@@ -377,17 +399,21 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
  * duration averaged over the runs since the last reset, measured with HIP
  * events recorded on the run's stream around each launch of the first pass
  * of items, plus the kernel's useful flops and algorithmic bytes per slice
- * contraction (the flops_item / bytes_item conventions of qgm_stats) and its
- * number of matrix-core steps.
+ * contraction of that pass (the flops_item / bytes_item conventions of
+ * qgm_stats; a step computed once for the G groups of the pass, see
+ * qgm_sliced_order_for_groups, counts 1 / G per item) and its number of
+ * matrix-core steps.
  * Fills min(cap, *n_levels) entries of the caller's arrays; *n_levels gets
  * the level count, *n_runs the runs averaged, *items the slice contractions
  * that first pass held (the last run's; a run larger than the workspace
- * takes several passes).  Waits for the last recorded run.  reset = 1
- * forgets the runs afterwards.  Other engines: *n_levels = 0.  Errors:
- * QGM_E_ARG (null or negative arguments, plan not profiling), QGM_E_HIP. */
+ * takes several passes), *roof_s_item (may be NULL) the pass's roofline
+ * time per slice contraction (as qgm_stats roof_s_item, shared steps at
+ * 1 / G).  Waits for the last recorded run.  reset = 1 forgets the runs
+ * afterwards.  Other engines: *n_levels = 0.  Errors: QGM_E_ARG (null or
+ * negative arguments, plan not profiling), QGM_E_HIP. */
 qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, double* bytes_item,
                                  int32_t* mfma_steps, int32_t cap, int32_t* n_levels, int32_t* n_runs,
-                                 uint64_t* items);
+                                 uint64_t* items, double* roof_s_item);
 /* Not in the paper (which evaluates amplitudes only): reverse-mode
  * differentiation of the elimination of Section "Variable elimination".
  * Amplitudes and their derivatives with respect to every RZ angle, for a

@@ -91,6 +91,15 @@ def qgm_order_search(c, sliced, init_order, max_nodes: int, beam: int = 0):
     return list(out[:len(init_order)]), cost.value, width.value, bool(complete.value)
 
 
+def qgm_sliced_order_for_groups(c, sliced, order):
+    """The same sliced variables ordered for group sharing, and the fraction
+    of the item work independent of those at slice bits 6 and 7."""
+    out, frac = (C.c_int32 * max(1, len(sliced)))(), C.c_double()
+    check(lib.qgm_sliced_order_for_groups(c, _i32(sliced), len(sliced), _i32(order), len(order), out,
+                                          C.byref(frac)))
+    return list(out[:len(sliced)]), frac.value
+
+
 def qgm_order_cost(c, sliced, order):
     cost, width = C.c_double(), C.c_int32()
     check(lib.qgm_order_cost(c, _i32(sliced), len(sliced), _i32(order), len(order), C.byref(cost), C.byref(width)))
@@ -239,18 +248,19 @@ def qgm_plan_timing(p, reset: bool = True):
 
 def qgm_plan_level_timing(p, reset: bool = True):
     """Per level kernel of a WIDE plan: (ms, flops_item, mfma_steps) lists, the
-    number of runs averaged, the items of the timed (first) pass, and the
-    bytes_item list."""
-    nl, nr, it = C.c_int32(), C.c_int32(), C.c_uint64()
-    check(lib.qgm_plan_level_timing(p, 0, None, None, None, None, 0, C.byref(nl), C.byref(nr), C.byref(it)))
+    number of runs averaged, the items of the timed (first) pass, the
+    bytes_item list and that pass's roofline seconds per item (work of steps
+    shared between the pass's groups counted once per pass)."""
+    nl, nr, it, roof = C.c_int32(), C.c_int32(), C.c_uint64(), C.c_double()
+    check(lib.qgm_plan_level_timing(p, 0, None, None, None, None, 0, C.byref(nl), C.byref(nr), C.byref(it), None))
     n = nl.value
     ms = (C.c_double * max(1, n))()
     fl = (C.c_double * max(1, n))()
     by = (C.c_double * max(1, n))()
     mf = (C.c_int32 * max(1, n))()
     check(lib.qgm_plan_level_timing(p, 1 if reset else 0, ms, fl, by, mf, n, C.byref(nl), C.byref(nr),
-                                    C.byref(it)))
-    return list(ms[:n]), list(fl[:n]), list(mf[:n]), nr.value, it.value, list(by[:n])
+                                    C.byref(it), C.byref(roof)))
+    return list(ms[:n]), list(fl[:n]), list(mf[:n]), nr.value, it.value, list(by[:n]), roof.value
 
 
 def qgm_plan_autotune(p, n_bs: int, n_slices: int, workspace, stream=None) -> int:

@@ -66,6 +66,7 @@ def _load():
         "qgm_plan_slices": (i32, [P, i32, i32, dbl, u64, pi32, pi32, pi32, pi32]),
         "qgm_plan_slices_ex": (i32, [P, i32, i32, dbl, u64, i32, pi32, pi32, pi32, pi32]),
         "qgm_order_cost": (i32, [P, pi32, i32, pi32, i32, pd, pi32]),
+        "qgm_sliced_order_for_groups": (i32, [P, pi32, i32, pi32, i32, pi32, pd]),
         "qgm_order_search": (i32, [P, pi32, i32, pi32, i32, C.c_int64, i32, pi32, pd, pi32, pi32]),
         "qgm_plan_create": (i32, [P, pi32, i32, pi32, i32, C.POINTER(PlanOpts), C.POINTER(P)]),
         "qgm_plan_stats": (i32, [P, C.POINTER(Stats)]),
@@ -74,7 +75,7 @@ def _load():
         "qgm_amplitudes_range": (i32, [P, pu8, i32, pd, u64, u64, P, sz, P, pd]),
         "qgm_amplitudes_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P]),
         "qgm_plan_timing": (i32, [P, i32, pd, pi32]),
-        "qgm_plan_level_timing": (i32, [P, i32, pd, pd, pd, pi32, i32, pi32, pi32, C.POINTER(u64)]),
+        "qgm_plan_level_timing": (i32, [P, i32, pd, pd, pd, pi32, i32, pi32, pi32, C.POINTER(u64), pd]),
         "qgm_plan_autotune": (i32, [P, i32, u64, P, sz, P, pi32]),
         "qgm_gradients_device": (i32, [P, P, i32, P, u64, u64, P, sz, P, P, P]),
         "qgm_amplitude_grad": (i32, [P, pu8, pd, P, sz, P, pd, pd]),
@@ -100,7 +101,7 @@ def _load():
 
 lib = _load()
 DECLARED = ("qgm_circuit_parse", "qgm_circuit_info", "qgm_circuit_vars", "qgm_circuit_graph", "qgm_circuit_free",
-            "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_order_search", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
+            "qgm_plan_slices", "qgm_plan_slices_ex", "qgm_order_cost", "qgm_sliced_order_for_groups", "qgm_order_search", "qgm_plan_create", "qgm_plan_stats", "qgm_workspace_size",
             "qgm_amplitudes", "qgm_amplitudes_range", "qgm_amplitudes_device", "qgm_amplitudes_device_noalloc",
             "qgm_gradients_device", "qgm_amplitude_grad", "qgm_graph_create", "qgm_graph_launch", "qgm_graph_free",
             "qgm_plan_timing", "qgm_plan_level_timing", "qgm_plan_autotune", "qgm_plan_free",

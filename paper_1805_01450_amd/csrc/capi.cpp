@@ -46,6 +46,7 @@ struct qgm_plan {
   std::vector<std::array<hipEvent_t, 4>> runs;  // profiling events, one set per run
   std::vector<std::vector<hipEvent_t>> level_runs;  // WIDE profiling: events around each level launch
   std::vector<uint64_t> level_items;                 // items of the pass those events cover
+  std::vector<uint64_t> level_vary;                  // that pass's group_vary_mask
   TileTable tiles;                                   // WIDE: matrix-core tile table (opts.tile_table_path)
   std::string tile_table_path;
   ~qgm_plan() {
@@ -231,10 +232,30 @@ qgm_status qgm_plan_slices_ex(const qgm_circuit* c, int32_t k_req, int32_t targe
   if (!plan_slices(c->net, k_req, target_rank, time_budget_s, seed, sl, ord, flags))
     return fail((flags & QGM_PLAN_CHOOSE_K) ? QGM_E_WORKSPACE : QGM_E_SLICE,
                 "no plan found (QGM_PLAN_CHOOSE_K: no k fits a 64-item group in 96 GiB)");
+  sl = sliced_order_for_groups(c->net, sl, ord);
   for (size_t i = 0; i < sl.size(); ++i) sliced_out[i] = sl[i];
   *k_out = (int32_t)sl.size();
   for (size_t i = 0; i < ord.size(); ++i) order_out[i] = ord[i];
   *n_order_out = (int32_t)ord.size();
+  return QGM_OK;
+  GUARD_END
+}
+
+qgm_status qgm_sliced_order_for_groups(const qgm_circuit* c, const int32_t* sliced_vars, int32_t k,
+                                       const int32_t* order, int32_t n_order, int32_t* sliced_out,
+                                       double* shared_frac) {
+  GUARD_BEGIN
+  if (!c || !sliced_out) return fail(QGM_E_ARG, "null argument");
+  std::vector<int> sv, ov;
+  qgm_status s = validate_plan_inputs(c->net, sliced_vars, k, order, n_order, sv, ov);
+  if (s) return s;
+  std::string err;
+  int code = 0;
+  if (!validate_plan(c->net, sv, ov, err, code)) return fail((qgm_status)code, err);
+  double frac = 0.0;
+  const std::vector<int> out = sliced_order_for_groups(c->net, sv, ov, &frac);
+  for (size_t i = 0; i < out.size(); ++i) sliced_out[i] = out[i];
+  if (shared_frac) *shared_frac = frac;
   return QGM_OK;
   GUARD_END
 }
@@ -374,8 +395,8 @@ qgm_status qgm_plan_create(const qgm_circuit* c, const int32_t* sliced_vars, int
     if (FILE* f = std::fopen((std::string(dir) + "/qgm_program_" + std::to_string((uintptr_t)p) + ".txt").c_str(), "w")) {
       for (size_t i = 0; i < p->prog.steps.size(); ++i) {
         const Step& st = p->prog.steps[i];
-        std::fprintf(f, "%zu kind %d const %d r %d ns %d m %d out_tid %d |", i, st.kind, st.is_const, st.r, st.ns, st.m,
-                     st.out_tid);
+        std::fprintf(f, "%zu kind %d const %d r %d ns %d m %d out_tid %d fix %llx |", i, st.kind, st.is_const, st.r,
+                     st.ns, st.m, st.out_tid, (unsigned long long)st.fix_mask);
         for (int v : st.out_vars) std::fprintf(f, " o%d", v);
         for (int v : st.sum_vars) std::fprintf(f, " s%d", v);
         for (const Operand& op : st.opnd) {
@@ -543,6 +564,7 @@ qgm_status enqueue_run(qgm_plan* p, const uint8_t* d_bits, int32_t n_bs, const d
         if (hipEventCreate(&e) != hipSuccess) return fail(QGM_E_HIP, "hipEventCreate failed");
       p->level_runs.push_back(le);
       p->level_items.push_back(std::min<uint64_t>((uint64_t)n_bs * (s_end - s_begin), (uint64_t)ws.wide_groups * 64));
+      p->level_vary.push_back(group_vary_mask(0, (int)((p->level_items.back() + 63) / 64), s_begin, s_end - s_begin));
       p->dev.wide.level_events = (void* const*)p->level_runs.back().data();
     }
   }
@@ -721,6 +743,7 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->level_runs.clear();
     p->level_items.clear();
+    p->level_vary.clear();
   }
   return QGM_OK;
   GUARD_END
@@ -728,7 +751,7 @@ qgm_status qgm_plan_timing(qgm_plan* p, int32_t reset, double ms[3], int32_t* n_
 
 qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double* flops_item, double* bytes_item,
                                  int32_t* mfma_steps, int32_t cap, int32_t* n_levels, int32_t* n_runs,
-                                 uint64_t* items) {
+                                 uint64_t* items, double* roof_s_item) {
   GUARD_BEGIN
   if (!p || !n_levels || !n_runs || !items || cap < 0 ||
       (cap > 0 && (!ms || !flops_item || !bytes_item || !mfma_steps)))
@@ -741,6 +764,20 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
   *n_levels = (int32_t)lv.size();
   *n_runs = (int32_t)p->level_runs.size();
   *items = p->level_items.empty() ? 0 : p->level_items.back();
+  // work of the timed pass: a step shared between its G groups is done for
+  // one group, 1 / G of it per item of the pass
+  const uint64_t vary = p->level_vary.empty() ? ~0ull : p->level_vary.back();
+  const double G = (double)std::max<uint64_t>(1, (*items + 63) / 64);
+  std::vector<double> eff_f(lv.size(), 0.0), eff_b(lv.size(), 0.0);
+  double roof = 0.0;
+  for (size_t i = 0; i < lv.size(); ++i)
+    for (size_t j = 0; j < lv[i]->step_flops.size(); ++j) {
+      const double w = (lv[i]->step_fix[j] & vary) == 0 ? 1.0 / G : 1.0;
+      eff_f[i] += w * lv[i]->step_flops[j];
+      eff_b[i] += w * lv[i]->step_bytes[j];
+      roof += w * std::max(lv[i]->step_flops[j] / 157.3e12, lv[i]->step_bytes[j] / 8e12);
+    }
+  if (roof_s_item) *roof_s_item = roof;
   for (int i = 0; i < std::min<int>(cap, (int)lv.size()); ++i) {
     double acc = 0;
     for (auto& r : p->level_runs) {
@@ -751,8 +788,8 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
       acc += t;
     }
     ms[i] = p->level_runs.empty() ? 0.0 : acc / p->level_runs.size();
-    flops_item[i] = lv[i]->flops;
-    bytes_item[i] = lv[i]->bytes;
+    flops_item[i] = eff_f[i];
+    bytes_item[i] = eff_b[i];
     mfma_steps[i] = lv[i]->mfma_steps;
   }
   if (reset) {
@@ -760,6 +797,7 @@ qgm_status qgm_plan_level_timing(qgm_plan* p, int32_t reset, double* ms, double*
       for (hipEvent_t e : r) (void)hipEventDestroy(e);
     p->level_runs.clear();
     p->level_items.clear();
+    p->level_vary.clear();
   }
   return QGM_OK;
   GUARD_END
@@ -1076,7 +1114,9 @@ qgm_status qgm_contraction_run(qgm_contraction* c, void* d_mem, int64_t n_groups
   int a_g0 = 0, a_log2 = 40;
   void* a_res = d_mem;
   void* a_gres = d_mem;
-  void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
+  unsigned long long a_vary = ~0ull;  // one contraction step: nothing shared between groups
+  void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres,
+                  &a_vary};
   hipError_t e = hipModuleLaunchKernel(c->fn, (unsigned)c->kern.blocks, (unsigned)n_groups, 1, (unsigned)c->kern.threads, 1, 1, 0,
                                        (hipStream_t)stream, args, nullptr);
   if (e != hipSuccess) return fail(QGM_E_HIP, std::string("contraction launch: ") + hipGetErrorString(e));

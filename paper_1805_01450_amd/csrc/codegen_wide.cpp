@@ -119,7 +119,8 @@ bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni
 // Tiles are numbered with the four item quads of a 128-byte line fastest
 // (they read the same lines at the same time), then j tiles, i tiles, b
 // bits and the four lines of a row; each XCD takes a contiguous range.
-static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int out, int r, int ns, int IT, int prec,
+static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, WideKernel& k, int si, int out, int r,
+                             int ns, int IT, int prec,
                              const int32_t* A, const int32_t* B, const std::vector<int>& bb, const std::vector<int>& bi,
                              const std::vector<int>& bj, const MfmaTile& tp, bool from_table, int& lds_bytes) {
   const int ni = (int)bi.size(), nj = (int)bj.size();
@@ -176,6 +177,7 @@ static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int 
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
     << "  // step " << si << " (matrix cores, per item) b " << nbb << " i " << ni << " j " << nj << " k " << ns
     << (prec == 1 ? " fp32" : " bf16x3") << "\n"
+    << pre
     << "  const unsigned long long g = blk - " << k.blocks << "ull;\n"
     << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
   k.blocks += nb;
@@ -236,7 +238,7 @@ static bool emit_mfma16_step(std::ostringstream* o_, WideKernel& k, int si, int 
       << "    const long long kb = 0ll" << koff(B, unit, kub, ns) << ";\n";
     for (int q = 0; q < per_wave; ++q) {
       const std::string Q = std::to_string(q);
-      o << "    __builtin_amdgcn_global_load_lds((const void*)(gm + (eo" << Q << " + (isa" << Q
+      o << "    __builtin_amdgcn_global_load_lds((const void*)((isa" << Q << " ? gq0 : gq1) + (eo" << Q << " + (isa" << Q
         << " ? ka : kb)) * 64ll + src" << Q << "), (__attribute__((address_space(3))) void*)(lds + (" << stg << ") * "
         << stage << " + " << IT * 1024 * q << " + 1024 * w4), 16, 0, 0);\n";
     }
@@ -445,11 +447,13 @@ static int step_waves(int kind, int r, int ns, int prec, const std::vector<const
   int it_pref = 4, lds = 0;
   if (!per_item_choice(prec, from_table, tp, ns, t16, it_pref)) return 1;
   WideKernel scratch;
-  const bool ok8 = emit_mfma16_step(nullptr, scratch, 0, 0, r, ns, 8, prec, rec[0], rec[1], bb, bi, bj, t16, true, lds);
+  const bool ok8 = emit_mfma16_step(nullptr, std::string(), scratch, 0, 0, r, ns, 8, prec, rec[0], rec[1], bb, bi, bj, t16,
+                                    true, lds);
   return 1 | (ok8 ? 2 : 0) | (ok8 && it_pref == 8 ? 4 : 0);
 }
 
-bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int out, int r, int ns, int prec,
+bool emit_mfma_step(std::ostringstream& o, const std::string& pre, WideKernel& k, int si, int kind, int out, int r,
+                    int ns, int prec,
                     const std::vector<const int32_t*>& rec, int& lds_bytes, const TileTable* tiles, int W) {
   std::vector<int> bb, bi, bj;
   if (!mfma_bits(kind, r, ns, prec, rec, bb, bi, bj)) return false;
@@ -466,7 +470,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
     MfmaTile t16;
     int it_pref = 4;
     if (per_item_choice(prec, from_table, tp, ns, t16, it_pref) &&
-        emit_mfma16_step(&o, k, si, out, r, ns, W, prec, A, B, bb, bi, bj, t16, true, lds_bytes))
+        emit_mfma16_step(&o, pre, k, si, out, r, ns, W, prec, A, B, bb, bi, bj, t16, true, lds_bytes))
       return true;
   }
   if (W != 4) return false;
@@ -502,6 +506,7 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
   k.blocks = (k.blocks + 7) & ~7ull;
   o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
     << "  // step " << si << " (matrix cores) b " << nbb << " i " << bi.size() << " j " << bj.size() << " k " << ns << "\n"
+    << pre
     << "  const unsigned long long g = blk - " << k.blocks << "ull;\n";
   if (nb >= 8)
     o << "  const unsigned long long tx = (g & 7ull) * " << (nb >> 3) << "ull + (g >> 3);\n";
@@ -590,7 +595,8 @@ bool emit_mfma_step(std::ostringstream& o, WideKernel& k, int si, int kind, int 
       o << "    {\n"
         << "    const long long e = eo" << Q << " + (isa" << Q << " ? 0ll" << koff(A, kv) << " : 0ll" << koff(B, kv)
         << ");\n"
-        << "    __builtin_amdgcn_global_load_lds((const void*)(gm + e * 64ll + itb + 2 * pq" << Q << "), "
+        << "    __builtin_amdgcn_global_load_lds((const void*)((isa" << Q << " ? gq0 : gq1) + e * 64ll + itb + 2 * pq" << Q
+        << "), "
         << "(__attribute__((address_space(3))) void*)(lds + (" << stg << ") * " << stage << " + lds" << Q
         << "), 16, 0, 0);\n"
         << "    }\n";
@@ -861,7 +867,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       << "(C2* __restrict__ mem, const C2* __restrict__ cst, const unsigned long long* __restrict__ packed, "
          "unsigned long long group_elems, unsigned long long s_begin, unsigned long long n_s, int group0, "
          "int ns_log2, unsigned long long n_items, unsigned long long n_bs, C2* __restrict__ res, "
-         "C2* __restrict__ gres) {\n"
+         "C2* __restrict__ gres, unsigned long long vary) {\n"
       << "/*LDS" << lev << "*/\n"
       << "  const int lane = threadIdx.x & 63;\n"
       << "  const unsigned long long wv = (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
@@ -878,7 +884,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       << "  }\n"
       << "  const unsigned long long s = s_begin + sl;\n"
       << "  const unsigned long long xb = packed[b];\n"
-      << "  (void)s; (void)xb; (void)res; (void)gres; (void)valid; (void)sl; (void)n_bs;\n"
+      << "  (void)s; (void)xb; (void)res; (void)gres; (void)valid; (void)sl; (void)n_bs; (void)vary;\n"
       << "  C2* gm = mem + (unsigned long long)blockIdx.y * group_elems * 64ull;\n"
       << "  (void)gm;\n"
       << "  const unsigned long long blk = blockIdx.x;\n";
@@ -899,9 +905,36 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
           elems += (double)(1ull << nv);
         }
         k.bytes += 8.0 * elems;
+        k.step_flops.push_back((double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0));
+        k.step_bytes.push_back(8.0 * elems);
+        k.step_fix.push_back(wide.step_fix.empty() ? ~0ull : wide.step_fix[si]);
+      }
+      // Group sharing: a step whose values depend on none of the fixed
+      // variables that differ between the groups of a pass (`vary`, set by
+      // the host per pass) runs in group 0 only, and every group reads such
+      // an operand from group 0's memory (the same offsets in every group).
+      std::string pre;
+      {
+        char line[160];
+        const uint64_t sf = wide.step_fix.empty() ? ~0ull : wide.step_fix[si];
+        if (sf != ~0ull) {
+          std::snprintf(line, sizeof(line), "  if ((0x%llxull & vary) == 0ull && blockIdx.y != 0u) return;\n",
+                        (unsigned long long)sf);
+          pre += line;
+        }
+        for (int i = 0; i < m; ++i) {
+          if (rec[i][0] != WOP_ITEM) continue;
+          const uint64_t of = wide.op_fix.empty() ? ~0ull : wide.op_fix[(size_t)ob + i];
+          if (of == ~0ull)
+            std::snprintf(line, sizeof(line), "  C2* const gq%d = gm;\n", i);
+          else
+            std::snprintf(line, sizeof(line), "  C2* const gq%d = (0x%llxull & vary) == 0ull ? mem : gm;\n", i,
+                          (unsigned long long)of);
+          pre += line;
+        }
       }
       int lds_bytes = 0;
-      if (mfma && emit_mfma_step(o, k, si, kind, out, r, ns, prec, rec, lds_bytes, tiles, W)) {
+      if (mfma && emit_mfma_step(o, pre, k, si, kind, out, r, ns, prec, rec, lds_bytes, tiles, W)) {
         level_lds[lev] = std::max(level_lds[lev], lds_bytes);
         continue;
       }
@@ -970,6 +1003,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       k.steps.push_back(si);
       o << "  if (blk >= " << k.blocks << "ull && blk < " << k.blocks + nb << "ull) {\n"
         << "  // step " << si << "\n"
+        << pre
         << "  const unsigned long long t = (blk - " << k.blocks << "ull) * " << W << "ull + wv;\n";
       o << "  if (t >= " << tiles << "ull) return;\n";
       k.blocks += nb;
@@ -1026,7 +1060,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
             if ((e >> d) & 1) off += rec[i][16 + perm[dep[i][d]]];
           o << "    const C2 v" << i << "_" << e << " = ";
           if (rec[i][0] == WOP_ITEM)
-            o << "gm[(p" << i << " + " << off << "ll) * 64ll + lane];\n";
+            o << "gq" << i << "[(p" << i << " + " << off << "ll) * 64ll + lane];\n";
           else
             o << "cst[p" << i << " + " << off << "ll];\n";
         }

@@ -114,6 +114,7 @@ struct Operand {
   int storage;            // element offset (constant area or packed item memory)
   std::vector<int> vars;  // bit j of the element index = value of vars[j]
   int tid = -1;           // compile-time tensor id (for the memory check)
+  uint64_t fix_mask = 0;  // fixed variables its values depend on (as Step::fix_mask)
 };
 
 struct Step {
@@ -128,6 +129,10 @@ struct Step {
   std::vector<Operand> opnd;
   int out_tid = -1;   // compile-time tensor id of the output (item memory outputs)
   double flops = 0;   // useful real flops per item
+  // fixed variables the output depends on: bit j = sliced variable j (bit j
+  // of the slice index), bit 63 = the output bits; all bits set for steps
+  // that write per-item results (FINAL, GRAD)
+  uint64_t fix_mask = 0;
 };
 
 struct Program {
@@ -176,6 +181,18 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
                      Program& prog, std::string& err, int& code, bool gradient = false, bool combine_consts = false,
                      int checkpoint_every = 0, const std::vector<int>& open_qubits = {});
 
+// The same sliced variables in an order for group sharing (slice-index bits
+// 6 and up tell the 64-item groups of a pass apart; an item step that
+// depends on none of a pass's varying bits runs once per pass): from bit 6
+// up, each position takes the variable that leaves the most item work (the
+// program's per-step roofline time) independent of the variables placed
+// there so far; bits 0..5 keep the others in their given order.  Returns the
+// input unchanged when k <= 6 or the program does not compile.  *shared_frac
+// (if not null) gets the fraction of the item work independent of the
+// variables at bits 6 and 7.
+std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<int>& sliced,
+                                         const std::vector<int>& order, double* shared_frac = nullptr);
+
 // ------------------------------------------------------------ wide engine
 // Descriptors for plans whose tensors are too large for registers or LDS.
 // Item tensors live in HBM as [element][64 items] rows; every step is one
@@ -188,6 +205,9 @@ struct WideProgram {
   std::vector<int32_t> steps;  // 8 ints per step: kind, out, r, ns, m, grad_slot, op_begin, is_const
   std::vector<int32_t> ops;    // kWideOpInts ints per operand
   int n_steps = 0;
+  // fixed-variable dependence (Step::fix_mask) per step and per operand;
+  // empty: every step depends on all of them
+  std::vector<uint64_t> step_fix, op_fix;
 };
 
 // Builds the wide descriptors; false (with err) if a step exceeds the limits.
@@ -208,7 +228,31 @@ struct WideKernel {
   double mfma_flops = 0.0;  // their flops per item
   double flops = 0.0;       // flops per item of all its steps
   double bytes = 0.0;       // algorithmic bytes per item of all its steps (8 B per element)
+  // per item step of a level kernel: flops, bytes and fixed-variable
+  // dependence (Step::fix_mask), for the work a pass with group sharing does
+  std::vector<double> step_flops, step_bytes;
+  std::vector<uint64_t> step_fix;
 };
+
+// Fixed variables that differ between the 64-item groups first_group ..
+// first_group + n_groups - 1 of a pass (item i: bitstring i / n_s, slice
+// s_begin + i % n_s): slice bits, and bit 63 when the groups span several
+// bitstrings.  Lanes of different groups agree on slice bits 0..5 only
+// when n_s and s_begin are multiples of 64; otherwise all bits (~0: no step
+// is the same in every group).  A step whose fix_mask has none of these
+// bits computes the same values in every group of the pass.
+inline uint64_t group_vary_mask(uint64_t first_group, int n_groups, uint64_t s_begin, uint64_t n_s) {
+  if (n_s % 64 != 0 || s_begin % 64 != 0) return ~0ull;
+  const uint64_t i0 = first_group * 64;
+  const uint64_t b0 = i0 / n_s, s0 = s_begin + i0 % n_s;
+  uint64_t v = 0;
+  for (int y = 1; y < n_groups; ++y) {
+    const uint64_t iy = i0 + (uint64_t)y * 64;
+    if (iy / n_s != b0) v |= 1ull << 63;
+    v |= (s_begin + iy % n_s) ^ s0;
+  }
+  return v;
+}
 // Tile parameters of a matrix-core step (two-operand contraction with ni
 // row, nj column and nk summed bits).  per: k steps per LDS stage (one block
 // barrier each); lds_budget: bytes of LDS the operand ring may take (2..8

@@ -132,6 +132,7 @@ struct Tn {
   int producer = -1;      // forward step that produced it
   int id = -1;            // index in the tensor list
   std::vector<int> inputs;  // tensors consumed by the producing step
+  uint64_t fix_mask = 0;    // fixed variables it depends on (as Step::fix_mask)
 };
 
 int popc_bits(int x) { return __builtin_popcount((unsigned)x); }
@@ -235,9 +236,11 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     L.factor = f;
     L.table = table;
     std::vector<int> fv;
+    uint64_t fm = 0;
     for (int j = 0; j < fa.nv; ++j) {
       int v = fa.var[j];
       if (fixed_src[v] >= 0) {
+        fm |= fixed_src[v] == 1 ? 1ull << fixed_bit[v] : 1ull << 63;
         L.dep_src[L.ndep] = fixed_src[v];
         L.dep_bit[L.ndep] = fixed_bit[v];
         L.dep_stride[L.ndep] = 1 << j;
@@ -252,6 +255,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     Tn t;
     t.vars = fv;
     t.id = (int)T.size();
+    t.fix_mask = fm;
     if (L.ndep == 0) {
       t.is_const = 1;
       t.storage = table;
@@ -281,6 +285,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     Tn t;
     t.leaf = (int)prog.leaves.size();
     t.id = (int)T.size();
+    t.fix_mask = 1ull << 63;
     prog.leaves.push_back(L);
     T.push_back(t);
   }
@@ -304,6 +309,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     st.r = (int)t.vars.size();
     st.leaf = t.leaf;
     st.out_tid = t.id;
+    st.fix_mask = t.fix_mask;
     prog.steps.push_back(st);
     step_buf.push_back(t.storage);
   };
@@ -313,6 +319,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     o.storage = t.storage;
     o.vars = t.vars;
     o.tid = t.id;
+    o.fix_mask = t.fix_mask;
     if (!t.is_const) bufs[t.storage].last = (int)prog.steps.size();
     return o;
   };
@@ -336,6 +343,8 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     for (int e = 0; e < n_extra; ++e) st.opnd.push_back(Operand{1, extra_const, {}});
     st.m = (int)st.opnd.size();
     st.flops = std::ldexp(1.0, st.r + st.ns) * (6.0 * std::max(0, st.m - 1) + 2.0);
+    for (int i : in) st.fix_mask |= T[i].fix_mask;
+    if (kind != ST_ELIM) st.fix_mask = ~0ull;  // per-item results: every item writes its own
     int id = -1, buf = -1;
     if (kind == ST_ELIM) {
       Tn nt;
@@ -354,6 +363,7 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
       nt.id = (int)T.size();
       st.out_tid = nt.id;
       for (int i : in) nt.grad |= T[i].grad;
+      nt.fix_mask = st.fix_mask;
       T.push_back(nt);
       id = (int)T.size() - 1;
       elim_created.push_back(id);
@@ -759,6 +769,55 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   }
   (void)popc_bits;
   return true;
+}
+
+std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<int>& sliced,
+                                         const std::vector<int>& order, double* shared_frac) {
+  if (shared_frac) *shared_frac = 0.0;
+  const int k = (int)sliced.size();
+  if (k <= 6) return sliced;
+  Program prog;
+  std::string err;
+  int code = 0;
+  if (!compile_program(net, sliced, order, prog, err, code, false, true)) return sliced;
+  // per item step: roofline time (as Program::roof_s_item) and the sliced
+  // positions it depends on
+  std::vector<std::pair<double, uint64_t>> work;
+  double total = 0.0;
+  for (const Step& st : prog.steps) {
+    if (st.is_const || st.kind == ST_LEAF) continue;
+    double elems = std::ldexp(1.0, st.r);
+    for (const Operand& o : st.opnd) elems += std::ldexp(1.0, (int)o.vars.size());
+    const double t = std::max(st.flops / 157.3e12, 8.0 * elems / 8e12);
+    work.push_back({t, st.fix_mask});
+    total += t;
+  }
+  if (total <= 0.0) return sliced;
+  std::vector<int> pos_at;  // sliced positions chosen for bits 6, 7, ...
+  uint64_t chosen = 0;
+  for (int b = 6; b < k; ++b) {
+    int best = -1;
+    double best_w = -1.0;
+    for (int j = 0; j < k; ++j) {
+      if ((chosen >> j) & 1) continue;
+      const uint64_t m = chosen | (1ull << j);
+      double w = 0.0;
+      for (auto& x : work)
+        if ((x.second & m) == 0) w += x.first;
+      if (w > best_w) {
+        best_w = w;
+        best = j;
+      }
+    }
+    chosen |= 1ull << best;
+    pos_at.push_back(best);
+    if (b == std::min(k - 1, 7) && shared_frac) *shared_frac = best_w / total;
+  }
+  std::vector<int> out;
+  for (int j = 0; j < k; ++j)
+    if (!((chosen >> j) & 1)) out.push_back(sliced[j]);
+  for (int j : pos_at) out.push_back(sliced[j]);
+  return out;
 }
 
 }  // namespace qgm

@@ -71,9 +71,11 @@ bool encode_wide(const Program& prog, WideProgram& wide, std::string& err) {
         rec[48 + (ps - st.sum_vars.begin())] = stride_of[j];
       }
       wide.ops.insert(wide.ops.end(), rec.begin(), rec.end());
+      wide.op_fix.push_back(o.fix_mask);
     }
     const int32_t srec[8] = {st.kind, st.out, st.r, st.ns, st.m, st.grad_slot, op_begin, st.is_const};
     wide.steps.insert(wide.steps.end(), srec, srec + 8);
+    wide.step_fix.push_back(st.fix_mask);
     wide.n_steps++;
   }
   return true;

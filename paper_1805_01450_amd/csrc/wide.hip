@@ -221,7 +221,11 @@ int wide_launch_steps(const WideDev& wd, int first_group, int n_groups, const vo
     int a_log2 = (n_s & (n_s - 1)) == 0 ? __builtin_ctzll(n_s) : -1;
     void* a_res = res;
     void* a_gres = gres;
-    void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres};
+    // group sharing: steps that depend on none of these fixed variables run
+    // in group 0 of the pass only, and the other groups read their results
+    unsigned long long a_vary = group_vary_mask((uint64_t)first_group, n_groups, s_begin, n_s);
+    void* args[] = {&a_mem, &a_cst, &a_packed, &a_ge, &a_sb, &a_ns, &a_g0, &a_log2, &a_ni, &a_nbs, &a_res, &a_gres,
+                    &a_vary};
     void* const* ev = first_group == 0 ? wd.level_events : nullptr;
     for (size_t li = 0; li < wd.levels.size(); ++li) {
       const WideDev::Level& lv = wd.levels[li];

@@ -597,28 +597,39 @@ def test_matrix_core_steps_8x8x40():
 def test_level_timing_entry_point(cuda):
     """qgm_plan_level_timing on a profiling wide plan: one entry per level
     launch, positive HIP-event durations that add up to about the chain's,
-    per-level flops summing to the plan's flops per slice, the matrix-core
-    step counts, and the items of the timed pass."""
+    per-level flops summing to the plan's flops per slice (one 64-item group:
+    nothing shared), the matrix-core step counts, and the items of the timed
+    pass; with two bitstrings in the pass, the steps that depend on no
+    output bit run once for both groups, so the pass's work per item lies
+    between half and all of the plan's."""
     text, sl, order = _stored("7x7x30")
     c = q.Circuit(text)
     p = q.Plan(c, sl, order, prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE, profile=True)
     st = p.stats()
     bits = random_bitstrings(49, 2, 55)
     for _ in range(3):
-        p.amplitudes(bits)
+        p.amplitudes(bits[:1])
     cuda.cuda.synchronize()
-    ms, fl, mf, runs, items, by = q.qgm_plan_level_timing(p.h, reset=False)
+    ms, fl, mf, runs, items, by, roof = q.qgm_plan_level_timing(p.h, reset=False)
     (ms_pro, ms_chain, ms_red), n = q.qgm_plan_timing(p.h, reset=True)
     note("levels", len(ms), "runs", runs, "items", items, "sum ms", sum(ms), "chain ms", ms_chain)
-    assert len(ms) == st["launches"] and runs == 3 and items == 2 * 64
+    assert len(ms) == st["launches"] and runs == 3 and items == 64
     assert all(t > 0 for t in ms)
     assert abs(sum(fl) - st["flops_item"]) <= 1e-9 * st["flops_item"]
     assert abs(sum(by) - st["bytes_item"]) <= 1e-9 * st["bytes_item"]
+    assert abs(roof - st["roof_s_item"]) <= 1e-9 * st["roof_s_item"]
     assert sum(mf) == st["mfma_steps"]
     assert 0.5 * ms_chain <= sum(ms) <= 1.05 * ms_chain
     # reset forgot the runs
-    ms2, _, _, runs2, _, _ = q.qgm_plan_level_timing(p.h, reset=True)
+    ms2, _, _, runs2, _, _, _ = q.qgm_plan_level_timing(p.h, reset=True)
     assert runs2 == 0 and all(t == 0 for t in ms2)
+    p.amplitudes(bits)
+    cuda.cuda.synchronize()
+    ms, fl, mf, runs, items, by, roof = q.qgm_plan_level_timing(p.h, reset=True)
+    note("two bitstrings: flops per item", sum(fl), "of", st["flops_item"], "roofline", roof, "of", st["roof_s_item"])
+    assert runs == 1 and items == 2 * 64
+    assert 0.5 * st["flops_item"] <= sum(fl) <= st["flops_item"] * (1 + 1e-9)
+    assert 0.5 * st["roof_s_item"] <= roof <= st["roof_s_item"] * (1 + 1e-9)
 
 
 def test_matrix_core_steps_8x8x40_k10():

@@ -253,3 +253,36 @@ def test_benchmark_whole_amplitude_vs_oracle(prec):
     err = abs(got - ref) / abs(ref)
     note("8x8x40-k8 whole amplitude prec", prec, got, "oracle", ref, "rel err", err, "tol", tol)
     assert err <= tol
+
+
+def test_group_sharing_matches_unshared_passes():
+    """Steps that depend on none of the slice bits (or bitstrings) that differ
+    between the 64-item groups of a pass run in group 0 only and the other
+    groups read their results (the stored k = 8 plan's sliced order puts the
+    variables the least work depends on at slice bits 6 and 7).  Every slice
+    value is the same whether or not a step is shared, so a pass of four
+    groups (sharing over bits 6 and 7), of two bitstrings x two groups (bit 6
+    and the bitstring), and a range that starts inside a group (no sharing)
+    must give the amplitudes of one-group passes (nothing to share) up to the
+    FP64 reduction order."""
+    rec = _plan_rec("8x8x40-k8")
+    c = rec["circuit"]
+    text = generate_circuit(c["n"], c["depth"], c["seed"])
+    xs = random_bitstrings(c["n"] ** 2, 2, 1000)
+    circ = q.Circuit(text)
+    tiles = os.path.join(os.path.dirname(q.__file__), "plans", "tiles_mi355x.txt")
+    p4 = q.Plan(circ, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE,
+                tile_table_path=tiles, workspace_cap=128 << 30)
+    p1 = q.Plan(circ, rec["sliced"], rec["order"], prec=q.QGM_C64, engine=q.QGM_ENGINE_WIDE,
+                tile_table_path=tiles, workspace_cap=30 << 30)
+    assert p4.stats()["item_elems"] * 64 * 8 <= 30 << 30  # one group fits the small cap
+
+    def amp(p, bits, s0, s1):
+        part = p.amplitudes_range(bits, None, s0, s1)
+        return part[:, 0] + part[:, 2] + 1j * (part[:, 1] + part[:, 3])
+
+    for bits, s0, s1 in (([xs[0]], 0, 256), (list(xs), 0, 128), ([xs[0]], 32, 160)):
+        a4, a1 = amp(p4, bits, s0, s1), amp(p1, bits, s0, s1)
+        err = np.abs(a4 - a1) / np.abs(a1)
+        note("group sharing", len(bits), "bitstrings, slices", s0, s1, a4, a1, "rel diff", err)
+        assert np.all(err <= 1e-12)

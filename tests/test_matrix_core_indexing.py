@@ -57,7 +57,9 @@ def _py_expr(e):
     return e.replace("threadIdx.x", "threadIdx_x")
 
 
-COPY = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(gm \+ e \* 64ll \+ itb \+ 2 \* pq(\d+)\), "
+# (the A rows of a step come from operand 0's base gq0, the B rows from gq1)
+COPY = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(\(isa(\d+) \? gq0 : gq1\) \+ e \* 64ll \+ itb \+ "
+                  r"2 \* pq\1\), "
                   r"\(__attribute__\(\(address_space\(3\)\)\) void\*\)\(lds \+ \((.*?)\) \* (\d+) \+ lds(\d+)\), 16, 0, 0\);")
 E_LINE = re.compile(r"const (?:long long|unsigned) e = (.*);$")
 
@@ -144,8 +146,8 @@ def check_step(body, S, E, lds_size, group_c2, max_blocks=None):
     return nu
 
 
-COPY16 = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(gm \+ \(eo(\d+) \+ \(isa\d+ \? ka : kb\)\) \* 64ll "
-                    r"\+ src\d+\), \(__attribute__\(\(address_space\(3\)\)\) void\*\)\(lds \+ \((.*?)\) \* (\d+) \+ "
+COPY16 = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(\(isa(\d+) \? gq0 : gq1\) \+ "
+                    r"\(eo\1 \+ \(isa\1 \? ka : kb\)\) \* 64ll \+ src\d+\), \(__attribute__\(\(address_space\(3\)\)\) void\*\)\(lds \+ \((.*?)\) \* (\d+) \+ "
                     r"(\d+) \+ 1024 \* w4\), 16, 0, 0\);")
 K_LINE = re.compile(r"const long long (ka|kb) = (.*);$")
 READ16 = re.compile(r"const C2 ([ab])(\d+)_(\d+) = \*\(const C2\*\)\(sb \+ (rda|rdb) \+ (\d+)\);$")
