@@ -192,6 +192,9 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
 // variables at bits 6 and 7.
 std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<int>& sliced,
                                          const std::vector<int>& order, double* shared_frac = nullptr);
+// The greedy choice behind it on a compiled program (combine_consts) with k
+// sliced variables: the sliced positions for bits 6, 7, ..., k - 1.
+std::vector<int> group_bit_positions(const Program& prog, int k, double* shared_frac = nullptr);
 
 // ------------------------------------------------------------ wide engine
 // Descriptors for plans whose tensors are too large for registers or LDS.

@@ -539,8 +539,30 @@ static bool plan_once(const Network& net, int k_req, int target_rank, double tim
       if (!compile_program(net, sliced_vars, order_vars, prog, err, code, false, true)) return false;
       // seconds per slice at the rates the wide engine reaches on one
       // MI355X: matrix-core contractions ~65 TFLOP/s, other steps ~30
-      // TFLOP/s, streaming ~5 TB/s
-      *score = prog.flops_mc_item / 65e12 + (prog.flops_item - prog.flops_mc_item) / 30e12 + prog.bytes_item / 5e12;
+      // TFLOP/s, streaming ~5 TB/s; with group sharing, in passes of G
+      // groups (what 96 GiB holds in complex64, at most 4 and 2^(k - 6)),
+      // a step independent of the sliced variables at the varying group
+      // bits counts 1 / G
+      const int k = (int)sliced_vars.size();
+      int G = 1;
+      const double group_bytes = (double)prog.item_elems * 64.0 * 8.0;
+      while (G < 4 && G < (1 << std::max(0, k - 6)) && (G + 1) * group_bytes <= 96.0 * (1ull << 30)) ++G;
+      uint64_t vary = 0;
+      if (G > 1) {
+        const std::vector<int> pos = group_bit_positions(prog, k);
+        for (int y = 1; y < G; ++y)
+          for (int t = 0; t < 2 && t < (int)pos.size(); ++t)
+            if ((y >> t) & 1) vary |= 1ull << pos[t];
+      }
+      double sc = 0.0;
+      for (const Step& st : prog.steps) {
+        if (st.is_const || st.kind == ST_LEAF) continue;
+        double elems = std::ldexp(1.0, st.r);
+        for (const Operand& o : st.opnd) elems += std::ldexp(1.0, (int)o.vars.size());
+        const double t = st.flops / (matrix_core_shape(st) ? 65e12 : 30e12) + 8.0 * elems / 5e12;
+        sc += (G > 1 && (st.fix_mask & vary) == 0) ? t / G : t;
+      }
+      *score = sc;
       if (item_elems) *item_elems = prog.item_elems;
     } else if (objective == OBJ_COST) {
       *score = order_cost(g, order1, removed).cost;

@@ -771,15 +771,10 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
   return true;
 }
 
-std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<int>& sliced,
-                                         const std::vector<int>& order, double* shared_frac) {
+std::vector<int> group_bit_positions(const Program& prog, int k, double* shared_frac) {
   if (shared_frac) *shared_frac = 0.0;
-  const int k = (int)sliced.size();
-  if (k <= 6) return sliced;
-  Program prog;
-  std::string err;
-  int code = 0;
-  if (!compile_program(net, sliced, order, prog, err, code, false, true)) return sliced;
+  std::vector<int> pos_at;  // sliced positions chosen for bits 6, 7, ...
+  if (k <= 6) return pos_at;
   // per item step: roofline time (as Program::roof_s_item) and the sliced
   // positions it depends on
   std::vector<std::pair<double, uint64_t>> work;
@@ -792,8 +787,6 @@ std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<i
     work.push_back({t, st.fix_mask});
     total += t;
   }
-  if (total <= 0.0) return sliced;
-  std::vector<int> pos_at;  // sliced positions chosen for bits 6, 7, ...
   uint64_t chosen = 0;
   for (int b = 6; b < k; ++b) {
     int best = -1;
@@ -811,8 +804,23 @@ std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<i
     }
     chosen |= 1ull << best;
     pos_at.push_back(best);
-    if (b == std::min(k - 1, 7) && shared_frac) *shared_frac = best_w / total;
+    if (b == std::min(k - 1, 7) && shared_frac && total > 0.0) *shared_frac = best_w / total;
   }
+  return pos_at;
+}
+
+std::vector<int> sliced_order_for_groups(const Network& net, const std::vector<int>& sliced,
+                                         const std::vector<int>& order, double* shared_frac) {
+  if (shared_frac) *shared_frac = 0.0;
+  const int k = (int)sliced.size();
+  if (k <= 6) return sliced;
+  Program prog;
+  std::string err;
+  int code = 0;
+  if (!compile_program(net, sliced, order, prog, err, code, false, true)) return sliced;
+  const std::vector<int> pos_at = group_bit_positions(prog, k, shared_frac);
+  uint64_t chosen = 0;
+  for (int j : pos_at) chosen |= 1ull << j;
   std::vector<int> out;
   for (int j = 0; j < k; ++j)
     if (!((chosen >> j) & 1)) out.push_back(sliced[j]);
