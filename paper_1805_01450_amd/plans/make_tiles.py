@@ -5,11 +5,13 @@
 
 Needs a GPU.  The table holds one line per (precision, row bits, column
 bits, summed bits) shape; shapes already in an existing table at PATH are
-kept unless tuned again.  The tuner times each shape alone; each entry is
-then confirmed inside the plan: the plan's level kernels are timed with the
-table and without that entry (the library's built-in tile for the shape),
-and an entry is dropped when the plan runs more than 0.5 % faster without
-it.
+kept unless tuned again.  The tuner times each shape alone, which does not
+see the operand strides and cache state of the plan's own levels; so each
+entry is then settled inside the plan: the plan's level kernels are timed
+with the tuned entry, without it (the library's built-in tile for the
+shape) and with the per-item form at its default tile (complex64: four
+items per block; BF16x3: eight), and the fastest is kept unless it beats
+the tuned entry by less than 0.5 %.
 """
 import argparse
 import json
@@ -46,7 +48,7 @@ def main():
         body = [ln for ln in f if not ln.startswith("# written by")]
     with open(args.out, "w") as f:
         f.write(f"# written by: python paper_1805_01450_amd/plans/make_tiles.py {' '.join(args.names)} "
-                f"(qgm_plan_tune_tiles on one MI355X{'' if args.no_confirm else ', entries confirmed in the plan'})\n")
+                f"(qgm_plan_tune_tiles on one MI355X{'' if args.no_confirm else ', entries settled in the plan'})\n")
         f.writelines(body)
     print(open(args.out).read(), flush=True)
 
@@ -70,31 +72,44 @@ def plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s, runs=3):
 
 
 def confirm(q, circ, rec, prec, table, margin=0.005):
-    """Drop each entry of precision `prec` whose removal makes the plan
-    faster by more than `margin` (the tuner's standalone timing does not see
-    the operand layouts and cache state of the plan's own levels)."""
+    """Settle each entry of precision `prec` inside the plan: the tuned
+    entry, no entry (the built-in tile) or the per-item form's default tile,
+    whichever runs the plan fastest (by more than `margin` against the tuned
+    entry)."""
     import torch
     from workload import random_bitstrings
     c = rec["circuit"]
     d_bits = torch.from_numpy(random_bitstrings(c["n"] * c["n"], 1, c["seed"] + 1000)).cuda()
     d_part = torch.empty((1, 4), dtype=torch.float64, device="cuda")
     n_s = min(1 << rec["k"], 128)
-    tmp = table + ".without"
+    tmp = table + ".candidate"
+    per_item = "2 65536 0 16" if prec == q.QGM_C64 else "2 131072 0 8"
     with open(table) as f:
         lines = f.readlines()
     entries = [ln for ln in lines if ln.strip() and not ln.startswith("#") and int(ln.split()[0]) == prec]
     for ln in entries:
-        base = plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s)
         with open(table) as f:
             cur = f.readlines()
-        with open(tmp, "w") as f:
-            f.writelines(x for x in cur if x != ln)
-        without = plan_ms(q, torch, circ, rec, prec, tmp, d_bits, d_part, n_s)
-        drop = without < base * (1.0 - margin)
-        print(f"  confirm {ln.strip()}: {base:.2f} ms with, {without:.2f} ms without -> "
-              f"{'dropped' if drop else 'kept'}", flush=True)
-        if drop:
-            os.replace(tmp, table)
+        base = plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s)
+        shape = " ".join(ln.split()[:4])
+        alt = {"built-in": [x for x in cur if x != ln],
+               "per-item": [x if x != ln else f"{shape} {per_item}\n" for x in cur]}
+        if " ".join(ln.split()[4:]) == per_item:
+            del alt["per-item"]
+        best, best_ms = None, base * (1.0 - margin)
+        times = []
+        for name, body in alt.items():
+            with open(tmp, "w") as f:
+                f.writelines(body)
+            t = plan_ms(q, torch, circ, rec, prec, tmp, d_bits, d_part, n_s)
+            times.append(f"{t:.2f} ms {name}")
+            if t < best_ms:
+                best, best_ms = name, t
+        print(f"  confirm {ln.strip()}: {base:.2f} ms tuned, " + ", ".join(times) +
+              f" -> {best or 'tuned'}", flush=True)
+        if best:
+            with open(table, "w") as f:
+                f.writelines(alt[best])
     if os.path.exists(tmp):
         os.remove(tmp)
 
