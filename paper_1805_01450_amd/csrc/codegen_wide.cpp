@@ -64,8 +64,15 @@ std::string lit(double v) {
 // complex64 / BF16x3 two-operand contraction of the matrix-core shape.
 static bool mfma_bits(int kind, int r, int ns, int prec, const std::vector<const int32_t*>& rec, std::vector<int>& bb,
                       std::vector<int>& bi, std::vector<int>& bj) {
-  if (kind != ST_ELIM || rec.size() != 2 || rec[0][0] != WOP_ITEM || rec[1][0] != WOP_ITEM) return false;
+  if (kind != ST_ELIM || rec.size() < 2 || rec.size() > 3 || rec[0][0] != WOP_ITEM || rec[1][0] != WOP_ITEM)
+    return false;
   if (ns < 1 || (prec != 1 && prec != 2)) return false;
+  if (rec.size() == 3) {
+    // a constant scale of the output (no summed variable), applied to the results
+    if (rec[2][0] != WOP_CONST) return false;
+    for (int j = 0; j < ns; ++j)
+      if (rec[2][48 + j] != 0) return false;
+  }
   const int32_t* A = rec[0];
   const int32_t* B = rec[1];
   for (int j = 0; j < r; ++j) {
@@ -121,8 +128,9 @@ bool mfma_step_shape(const WideProgram& wide, int si, int prec, int& nb, int& ni
 // bits and the four lines of a row; each XCD takes a contiguous range.
 static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, WideKernel& k, int si, int out, int r,
                              int ns, int IT, int prec,
-                             const int32_t* A, const int32_t* B, const std::vector<int>& bb, const std::vector<int>& bi,
-                             const std::vector<int>& bj, const MfmaTile& tp, bool from_table, int& lds_bytes) {
+                             const int32_t* A, const int32_t* B, const int32_t* Sc, const std::vector<int>& bb,
+                             const std::vector<int>& bi, const std::vector<int>& bj, const MfmaTile& tp,
+                             bool from_table, int& lds_bytes) {
   const int ni = (int)bi.size(), nj = (int)bj.size();
   if (ni < 4 || nj < 4 || ns < 2 || (IT != 4 && IT != 8) || (prec != 1 && prec != 2)) return false;
   // IT items per block, one per wavefront: an operand row slot holds
@@ -215,6 +223,31 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
     << "  const long long bbk = " << B[1] << "ll" << sum_of([&](int kd, int b) { return kd == 1 ? 0ll : (long long)B[16 + b]; })
     << ";\n"
     << "  const long long lo = " << out << "ll" << sum_of([&](int, int b) { return 1ll << b; }) << ";\n";
+  if (Sc) {
+    // the scale's element of this lane's results: tile part, then rows
+    // 4 (l / 16) + .. and column l % 16
+    o << "  const long long scl = " << Sc[1] << "ll" << sum_of([&](int, int b) { return (long long)Sc[16 + b]; })
+      << " + (long long)((lid >> 4) & 1) * " << Sc[16 + bi[2]] << "ll + (long long)((lid >> 5) & 1) * "
+      << Sc[16 + bi[3]] << "ll";
+    for (int t = 0; t < 4; ++t) o << " + (long long)((lid >> " << t << ") & 1) * " << Sc[16 + bj[t]] << "ll";
+    o << ";\n";
+  }
+  // offset in the scale of register e of tile (f, g), beyond scl
+  auto sc_off = [&](int f, int g, int e) {
+    long long off = 0;
+    if (e & 1) off += Sc[16 + bi[0]];
+    if (e & 2) off += Sc[16 + bi[1]];
+    if (f & 1) off += Sc[16 + bi[4]];
+    if (f & 2) off += Sc[16 + bi[5]];
+    if (g & 1) off += Sc[16 + bj[4]];
+    if (g & 2) off += Sc[16 + bj[5]];
+    return off;
+  };
+  // the value stored for register e of tile C (f, g)
+  auto result = [&](const std::string& C, int f, int g, int e) {
+    const std::string v = "C2{cr" + C + "[" + std::to_string(e) + "], ci" + C + "[" + std::to_string(e) + "]}";
+    return Sc ? "cm(" + v + ", cst[scl + " + std::to_string(sc_off(f, g, e)) + "ll])" : v;
+  };
   // copies: instruction c = IT q + wave covers row slots RPI c .. RPI c +
   // RPI - 1; lane l fills 16-byte part l % LPR of slot RPI c + l / LPR with
   // the item pair (l % LPR) ^ swz(slot): swz = bit 3 of the slot for four
@@ -370,7 +403,7 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
             o << "((" << 2 * e << " + ((lid >> 3) & 1)) & 3)";
           else
             o << "(2 * ((lid >> 2) & 3))";
-          o << ")) * 8) = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+          o << ")) * 8) = " << result(C, f, g, e) << ";\n";
         }
       }
       o << "  __syncthreads();\n";
@@ -397,7 +430,7 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
           if (e & 1) off += 1ll << bi[0];
           if (e & 2) off += 1ll << bi[1];
           const std::string C = std::to_string(f) + "_" + std::to_string(g);
-          o << "  gm[(so + " << off << "ll) * 64ll + sit] = C2{cr" << C << "[" << e << "], ci" << C << "[" << e << "]};\n";
+          o << "  gm[(so + " << off << "ll) * 64ll + sit] = " << result(C, f, g, e) << ";\n";
         }
   }
   o << "  return;\n  }\n";
@@ -447,8 +480,8 @@ static int step_waves(int kind, int r, int ns, int prec, const std::vector<const
   int it_pref = 4, lds = 0;
   if (!per_item_choice(prec, from_table, tp, ns, t16, it_pref)) return 1;
   WideKernel scratch;
-  const bool ok8 = emit_mfma16_step(nullptr, std::string(), scratch, 0, 0, r, ns, 8, prec, rec[0], rec[1], bb, bi, bj, t16,
-                                    true, lds);
+  const bool ok8 = emit_mfma16_step(nullptr, std::string(), scratch, 0, 0, r, ns, 8, prec, rec[0], rec[1], nullptr, bb,
+                                    bi, bj, t16, true, lds);
   return 1 | (ok8 ? 2 : 0) | (ok8 && it_pref == 8 ? 4 : 0);
 }
 
@@ -459,6 +492,7 @@ bool emit_mfma_step(std::ostringstream& o, const std::string& pre, WideKernel& k
   if (!mfma_bits(kind, r, ns, prec, rec, bb, bi, bj)) return false;
   const int32_t* A = rec[0];
   const int32_t* B = rec[1];
+  const int32_t* Sc = rec.size() == 3 ? rec[2] : nullptr;  // constant scale of the results
   // Tile parameters: a tuned table entry for this shape, else the built-in
   // choice (2 x 2 tiles of 16 items when both sides have 5 bits, two k per
   // unit, a ring of at most 52 KiB, bands of four j blocks).
@@ -470,7 +504,7 @@ bool emit_mfma_step(std::ostringstream& o, const std::string& pre, WideKernel& k
     MfmaTile t16;
     int it_pref = 4;
     if (per_item_choice(prec, from_table, tp, ns, t16, it_pref) &&
-        emit_mfma16_step(&o, pre, k, si, out, r, ns, W, prec, A, B, bb, bi, bj, t16, true, lds_bytes))
+        emit_mfma16_step(&o, pre, k, si, out, r, ns, W, prec, A, B, Sc, bb, bi, bj, t16, true, lds_bytes))
       return true;
   }
   if (W != 4) return false;
@@ -562,6 +596,12 @@ bool emit_mfma_step(std::ostringstream& o, const std::string& pre, WideKernel& k
     << (WJ == 2 ? " + (long long)wj * " + std::to_string(1ll << bj[4]) + "ll" : "")
     << " + (long long)(sub & 1) * " << (1ll << bj[0]) << "ll + (long long)(sub >> 1) * " << (1ll << bj[1]) << "ll;\n"
     << "  const int it = (int)itb + wq * 16 + (lid >> 2);\n";
+  if (Sc)  // the scale's element of this lane's results (as lo, with the scale's strides)
+    o << "  const long long scl = " << Sc[1] << "ll" << sum_of([&](int, int b) { return (long long)Sc[16 + b]; })
+      << (WI == 2 ? " + (long long)wi * " + std::to_string(Sc[16 + bi[4]]) + "ll" : "")
+      << (WJ == 2 ? " + (long long)wj * " + std::to_string(Sc[16 + bj[4]]) + "ll" : "")
+      << " + (long long)(sub & 1) * " << Sc[16 + bj[0]] << "ll + (long long)(sub >> 1) * " << Sc[16 + bj[1]]
+      << "ll;\n";
   // Copies: instruction j = 4 q + wave of a unit; j < per nA: A rows, else
   // B rows.  A copy moves 1 KiB = 1024 / (128 WQ) rows of 16 WQ items into
   // LDS slots of 16 bytes (two items of one row), 8 WQ slots per row: lane
@@ -696,8 +736,18 @@ bool emit_mfma_step(std::ostringstream& o, const std::string& pre, WideKernel& k
           if ((row >> t) & 1) off += 1ll << bi[t];
         if (cg & 1) off += 1ll << bj[2];
         if (cg & 2) off += 1ll << bj[3];
-        o << "  gm[(lo + " << off << "ll) * 64ll + it] = C2{cr" << rg << "_" << cg << "[" << e << "], ci" << rg << "_" << cg << "[" << e
-          << "]};\n";
+        const std::string v = "C2{cr" + std::to_string(rg) + "_" + std::to_string(cg) + "[" + std::to_string(e) +
+                              "], ci" + std::to_string(rg) + "_" + std::to_string(cg) + "[" + std::to_string(e) + "]}";
+        if (Sc) {
+          long long soff = 0;
+          for (int t = 0; t < 4; ++t)
+            if ((row >> t) & 1) soff += Sc[16 + bi[t]];
+          if (cg & 1) soff += Sc[16 + bj[2]];
+          if (cg & 2) soff += Sc[16 + bj[3]];
+          o << "  gm[(lo + " << off << "ll) * 64ll + it] = cm(" << v << ", cst[scl + " << soff << "ll]);\n";
+        } else {
+          o << "  gm[(lo + " << off << "ll) * 64ll + it] = " << v << ";\n";
+        }
       }
   o << "  return;\n  }\n";
   return true;
@@ -894,8 +944,17 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int kind = sr[0], out = sr[1], r = sr[2], ns = sr[3], m = sr[4], slot = sr[5], ob = sr[6];
       std::vector<const int32_t*> rec(m);
       for (int i = 0; i < m; ++i) rec[i] = &wide.ops[(size_t)(ob + i) * kWideOpInts];
+      // operands that carry no summed bit multiply each sum once
+      std::vector<char> has_sum(m, 0);
+      int m_in = 0;
+      for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < ns; ++j) has_sum[i] |= rec[i][48 + j] != 0;
+        m_in += has_sum[i];
+      }
+      const bool factor_out = ns >= 1 && m_in >= 1 && m_in < m;
       if (kind == ST_ELIM || kind == ST_FINAL) {
-        k.flops += (double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0);
+        const double sflops = step_flops(r, ns, factor_out ? m_in : m, factor_out ? m - m_in : 0);
+        k.flops += sflops;
         // every operand and the output once, 8 B per element
         double elems = (double)(1ull << r);
         for (int i = 0; i < m; ++i) {
@@ -905,7 +964,7 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
           elems += (double)(1ull << nv);
         }
         k.bytes += 8.0 * elems;
-        k.step_flops.push_back((double)(1ull << (r + ns)) * (6.0 * std::max(0, m - 1) + 2.0));
+        k.step_flops.push_back(sflops);
         k.step_bytes.push_back(8.0 * elems);
         k.step_fix.push_back(wide.step_fix.empty() ? ~0ull : wide.step_fix[si]);
       }
@@ -1026,12 +1085,13 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
           o << " + (long long)((t >> " << (k2 - L) << ") & 1ull) * " << (1ll << perm[k2]) << "ll";
         o << ";\n";
       }
-      // item operands first in every product
-      std::vector<int> order;
+      // item operands first in every product; operands with no summed bit
+      // (factor_out) multiply each sum after the loop
+      std::vector<int> order, after;
       for (int i = 0; i < m; ++i)
-        if (rec[i][0] == WOP_ITEM) order.push_back(i);
+        if (rec[i][0] == WOP_ITEM) (factor_out && !has_sum[i] ? after : order).push_back(i);
       for (int i = 0; i < m; ++i)
-        if (rec[i][0] != WOP_ITEM) order.push_back(i);
+        if (rec[i][0] != WOP_ITEM) (factor_out && !has_sum[i] ? after : order).push_back(i);
       // tile bits each operand depends on, and its row index for output lo
       std::vector<std::vector<int>> dep(m);
       for (int i = 0; i < m; ++i)
@@ -1047,23 +1107,27 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
       const int nsum = 1 << ns;
       if (nsum > 4) o << "  #pragma unroll 2\n";
       o << "  for (int q = 0; q < " << nsum << "; ++q) {\n";
-      for (int i = 0; i < m; ++i) {
+      for (int i : order) {
         o << "    const long long p" << i << " = o" << i;
         for (int j = 0; j < ns; ++j)
           if (rec[i][48 + j]) o << " + (long long)((q >> " << j << ") & 1) * " << rec[i][48 + j] << "ll";
         o << ";\n";
       }
-      for (int i : order)
+      // operand i's values at this tile's rows, from base p<i> (in the loop)
+      // or o<i> (after it)
+      auto load_rows = [&](int i, const std::string& ind, const std::string& base) {
         for (int e = 0; e < (1 << dep[i].size()); ++e) {
           long long off = 0;
           for (size_t d = 0; d < dep[i].size(); ++d)
             if ((e >> d) & 1) off += rec[i][16 + perm[dep[i][d]]];
-          o << "    const C2 v" << i << "_" << e << " = ";
+          o << ind << "const C2 v" << i << "_" << e << " = ";
           if (rec[i][0] == WOP_ITEM)
-            o << "gq" << i << "[(p" << i << " + " << off << "ll) * 64ll + lane];\n";
+            o << "gq" << i << "[(" << base << i << " + " << off << "ll) * 64ll + lane];\n";
           else
-            o << "cst[p" << i << " + " << off << "ll];\n";
+            o << "cst[" << base << i << " + " << off << "ll];\n";
         }
+      };
+      for (int i : order) load_rows(i, "    ", "p");
       for (int lo = 0; lo < (1 << L); ++lo) {
         std::string cur = m == 0 ? "C2{(R)1, (R)0}" : "";
         for (size_t q2 = 0; q2 < order.size(); ++q2) {
@@ -1074,6 +1138,13 @@ std::string generate_wide_source(const Program& prog, const WideProgram& wide, i
         o << "    a" << lo << " = cad(a" << lo << ", " << cur << ");\n";
       }
       o << "  }\n";
+      for (int i : after) load_rows(i, "  ", "o");
+      for (int lo = 0; lo < (1 << L) && !after.empty(); ++lo) {
+        o << "  a" << lo << " = ";
+        std::string cur = "a" + std::to_string(lo);
+        for (int i : after) cur = "cm(" + cur + ", v" + std::to_string(i) + "_" + std::to_string(row_of(i, lo)) + ")";
+        o << cur << ";\n";
+      }
       for (int lo = 0; lo < (1 << L); ++lo) {
         if (kind == ST_ELIM) {
           long long lo_off = 0;

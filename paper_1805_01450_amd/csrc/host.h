@@ -2,6 +2,8 @@
 // planner and the compiled per-slice contraction program.
 #pragma once
 #include <cstddef>
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -236,6 +238,19 @@ struct WideKernel {
   std::vector<double> step_flops, step_bytes;
   std::vector<uint64_t> step_fix;
 };
+
+// Useful real flops of one product-sum step per item: 2^(r + ns) products
+// of the m_in operands that carry summed variables (6 flops per complex
+// multiply, 2 per complex add), then, when something is summed, each of the
+// 2^r sums times the m_out operands that carry none (they are the same for
+// every summed index, so they multiply the sum once).
+inline double step_flops(int r, int ns, int m_in, int m_out) {
+  if (ns == 0 || m_in == 0) {
+    m_in += m_out;
+    m_out = 0;
+  }
+  return std::ldexp(1.0, r + ns) * (6.0 * std::max(0, m_in - 1) + 2.0) + 6.0 * std::ldexp(1.0, r) * m_out;
+}
 
 // Fixed variables that differ between the 64-item groups first_group ..
 // first_group + n_groups - 1 of a pass (item i: bitstring i / n_s, slice

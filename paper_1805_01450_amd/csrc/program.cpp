@@ -140,11 +140,18 @@ int popc_bits(int x) { return __builtin_popcount((unsigned)x); }
 }  // namespace
 
 bool matrix_core_shape(const Step& st) {
-  if (st.kind != ST_ELIM || st.is_const || st.opnd.size() != 2 || st.ns < 1) return false;
+  if (st.kind != ST_ELIM || st.is_const || st.opnd.size() < 2 || st.opnd.size() > 3 || st.ns < 1) return false;
   const Operand& a = st.opnd[0];
   const Operand& b = st.opnd[1];
   if (a.is_const || b.is_const) return false;
   auto has = [](const Operand& o, int v) { return std::find(o.vars.begin(), o.vars.end(), v) != o.vars.end(); };
+  if (st.opnd.size() == 3) {
+    // a constant scale of the output, applied to the results
+    const Operand& c = st.opnd[2];
+    if (!c.is_const) return false;
+    for (int v : c.vars)
+      if (std::find(st.out_vars.begin(), st.out_vars.end(), v) == st.out_vars.end()) return false;
+  }
   int rows = 0, cols = 0;
   for (int v : st.out_vars) {
     const bool ia = has(a, v), ib = has(b, v);
@@ -342,7 +349,19 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
     for (int i : in) st.opnd.push_back(as_operand(T[i]));
     for (int e = 0; e < n_extra; ++e) st.opnd.push_back(Operand{1, extra_const, {}});
     st.m = (int)st.opnd.size();
-    st.flops = std::ldexp(1.0, st.r + st.ns) * (6.0 * std::max(0, st.m - 1) + 2.0);
+    // item steps multiply the operands that carry no summed variable into
+    // each sum once (the wide kernels do; plans of the other engines have
+    // no such operand); constant steps multiply every operand in the loop
+    int m_in = st.m, m_out = 0;
+    if (!make_const) {
+      m_in = 0;
+      for (const Operand& o : st.opnd) {
+        bool summed = false;
+        for (int u : o.vars) summed = summed || std::find(sum_vars.begin(), sum_vars.end(), u) != sum_vars.end();
+        (summed ? m_in : m_out)++;
+      }
+    }
+    st.flops = step_flops(st.r, st.ns, m_in, m_out);
     for (int i : in) st.fix_mask |= T[i].fix_mask;
     if (kind != ST_ELIM) st.fix_mask = ~0ull;  // per-item results: every item writes its own
     int id = -1, buf = -1;
@@ -528,6 +547,58 @@ bool compile_program(const Network& net, const std::vector<int>& sliced, const s
           S.swap(S2);
           rest_tv.push_back(k);
           tv.swap(rest_tv);
+        }
+      }
+      // A small constant factor whose variables all belong to a large item
+      // operand made by an earlier item step is multiplied in by that step
+      // (one more operand of it, a scale of its output; the same product,
+      // grouped differently): no pass over a large tensor is spent on it,
+      // which the pairwise pre-contraction below would spend when it pairs
+      // the factor with the other operand and adds a variable to it.
+      if ((int)(out.size() + S.size()) >= 16 && tv.size() > 2) {
+        for (size_t x = 0; x < tv.size();) {
+          const Tn& C = T[tv[x]];
+          int host = -1;
+          if (C.is_const && C.leaf < 0 && (int)C.vars.size() <= 10)
+            for (int y : tv) {
+              const Tn& Y = T[y];
+              if (y == tv[x] || Y.is_const || Y.leaf >= 0 || Y.producer < 0 || (int)Y.vars.size() < 16) continue;
+              const Step& ps = prog.steps[Y.producer];
+              if (ps.kind != ST_ELIM || ps.is_const || ps.out_tid != Y.id) continue;
+              bool sub = true;
+              for (int u : C.vars) sub = sub && std::find(Y.vars.begin(), Y.vars.end(), u) != Y.vars.end();
+              if (!sub) continue;
+              // one scale per step, and only on a product of two operands
+              if (ps.opnd.size() != 2) continue;
+              host = y;
+              break;
+            }
+          if (host < 0) {
+            ++x;
+            continue;
+          }
+          Step& ps = prog.steps[T[host].producer];
+          const double old_bytes = 8.0 * [&] {
+            double e = std::ldexp(1.0, ps.r);
+            for (const Operand& o : ps.opnd) e += std::ldexp(1.0, (int)o.vars.size());
+            return e;
+          }();
+          const double old_t = std::max(ps.flops / 157.3e12, old_bytes / 8e12);
+          const bool old_mc = matrix_core_shape(ps);
+          ps.opnd.push_back(as_operand(C));
+          ps.m = (int)ps.opnd.size();
+          const double old_flops = ps.flops;
+          ps.flops = step_flops(ps.r, ps.ns, 2, 1);  // the scale multiplies each sum once
+          const double new_bytes = old_bytes + 8.0 * std::ldexp(1.0, (int)C.vars.size());
+          prog.flops_item += ps.flops - old_flops;
+          prog.bytes_item += new_bytes - old_bytes;
+          prog.roof_s_item += std::max(ps.flops / 157.3e12, new_bytes / 8e12) - old_t;
+          if (old_mc) prog.flops_mc_item -= old_flops;
+          if (matrix_core_shape(ps)) prog.flops_mc_item += ps.flops;
+          for (int u : C.vars) count[u]--;
+          T[tv[x]].alive = 0;
+          tv.erase(tv.begin() + x);
+          split_vars();
         }
       }
       // Pairwise pre-contraction of a large step: while it has more than

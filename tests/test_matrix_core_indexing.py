@@ -140,10 +140,32 @@ def check_step(body, S, E, lds_size, group_c2, max_blocks=None):
         r = np.stack(r, 0)
         assert all(len(np.unique(r[:, c])) == r.shape[0] for c in range(0, r.shape[1], 61)), \
             "a summed row read twice or not at all"
+    st_lines = [l for l in lines if l.startswith("gm[(lo + ")]
     stores = np.concatenate([ev(re.match(r"gm\[\((lo \+ \d+ll)\) \* 64ll \+ it\]", l).group(1)) * 64 + env["it"]
-                             for l in lines if l.startswith("gm[(lo + ")])
+                             for l in st_lines])
     assert len(np.unique(stores)) == len(stores) and stores.min() >= 0 and stores.max() < group_c2
+    scaled = [re.search(r", cst\[scl \+ (\d+)ll\]\);$", l) for l in st_lines]
+    if any(scaled):
+        assert all(scaled), "some results of a scaled step stored unscaled"
+        sidx = np.concatenate([env["scl"] + int(m.group(1)) for m in scaled])
+        check_scale_linear(stores // 64, sidx)
     return nu
+
+
+def check_scale_linear(elem, sidx):
+    """A step with a constant scale operand multiplies output element e by the
+    scale's entry at e's values of the scale's variables: the entry index is
+    base + sum_j bit_j(e) * w_j for fixed weights w_j.  Checks that the
+    generated index has that form on the elements evaluated (a least-squares
+    fit over their bits must reproduce every index exactly)."""
+    elem = np.asarray(elem, dtype=np.int64)
+    sidx = np.asarray(sidx, dtype=np.int64)
+    rel = elem - elem.min()
+    nbits = max(1, int(rel.max()).bit_length())
+    bits = ((rel[:, None] >> np.arange(nbits)[None, :]) & 1).astype(np.float64)
+    X = np.concatenate([np.ones((len(rel), 1)), bits], 1)
+    w, *_ = np.linalg.lstsq(X, sidx.astype(np.float64), rcond=None)
+    assert np.array_equal(np.rint(X @ w).astype(np.int64), sidx), "scale index not linear in the output bits"
 
 
 COPY16 = re.compile(r"__builtin_amdgcn_global_load_lds\(\(const void\*\)\(\(isa(\d+) \? gq0 : gq1\) \+ "
@@ -256,7 +278,10 @@ def check_step16(body, S, E, lds_size, group_c2, max_blocks=None, threads=256):
     return nu
 
 
-def _result_map(body, S, n_blocks, lds_size=None, threads=256):
+RES = r"(?:cm\()?C2\{cr(?P<c>\d+_\d+)\[(?P<e>\d)\], ci(?P=c)\[(?P=e)\]\}(?:, cst\[scl \+ (?P<s>\d+)ll\]\))?"
+
+
+def _result_map(body, S, n_blocks, lds_size=None, threads=256, scales=None):
     """Where each accumulator register (block, thread, tile, register) of a
     per-item step lands in the group's memory, evaluated from the generated
     result code: direct stores, or the LDS staging (writes, barrier, 16-byte
@@ -283,25 +308,31 @@ def _result_map(body, S, n_blocks, lds_size=None, threads=256):
     direct = [l for l in lines if l.startswith("gm[(so + ")]
     if direct:
         for l in direct:
-            m = re.match(r"gm\[\((so \+ \d+ll)\) \* 64ll \+ sit\] = C2\{cr(\d+_\d+)\[(\d)\], ci\2\[\3\]\};$", l)
+            m = re.match(r"gm\[\((so \+ \d+ll)\) \* 64ll \+ sit\] = " + RES + ";$", l)
             g = ev(m.group(1)) * 64 + env["sit"]
             for b_, t_, gg in zip(blk.tolist(), th.tolist(), g.tolist()):
-                key = (b_, t_, m.group(2), int(m.group(3)))
+                key = (b_, t_, m.group("c"), int(m.group("e")))
                 assert key not in out
                 out[key] = gg
+            if m.group("s") is not None and scales is not None:
+                for b_, t_, sc in zip(blk.tolist(), th.tolist(), (env["scl"] + int(m.group("s"))).tolist()):
+                    scales[(b_, t_, m.group("c"), int(m.group("e")))] = sc
         return out
     i_epi = next(i for i, l in enumerate(lines) if l.startswith("const int wre"))
     lds = {}
     for l in lines[i_epi:]:
         if l == "__syncthreads();":
             continue
-        m = re.match(r"\*\(C2\*\)\(lds \+ (.*)\) = C2\{cr(\d+_\d+)\[(\d)\], ci\2\[\3\]\};$", l)
+        m = re.match(r"\*\(C2\*\)\(lds \+ (.*)\) = " + RES + ";$", l)
         if m:
             a = ev(m.group(1))
+            if m.group("s") is not None and scales is not None:
+                for b_, t_, sc in zip(blk.tolist(), th.tolist(), (env["scl"] + int(m.group("s"))).tolist()):
+                    scales[(b_, t_, m.group("c"), int(m.group("e")))] = sc
             assert a.min() >= 0 and (lds_size is None or a.max() + 8 <= lds_size)
             for b_, t_, aa in zip(blk.tolist(), th.tolist(), a.tolist()):
                 assert (b_, aa) not in lds or lds[(b_, aa)][0] == "read", "LDS slot written twice in one chunk"
-                lds[(b_, aa)] = ("acc", (b_, t_, m.group(2), int(m.group(3))))
+                lds[(b_, aa)] = ("acc", (b_, t_, m.group("c"), int(m.group("e"))))
             continue
         m = re.match(r"const f32x4 v = \*\(const f32x4\*\)\(lds \+ (\d+) \+ 16 \* tt\);$", l)
         if m:
@@ -358,6 +389,13 @@ def check_source(src, group_elems, max_blocks=None):
             nu = check_step16(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks,
                               threads)
             shapes.add("per item" if threads == 256 else "per item x8")
+            if "cst[scl + " in m.group(5):
+                scales = {}
+                res = _result_map(m.group(5), int(m.group(1)), min(4, int(m.group(2)) - int(m.group(1))), lds_size,
+                                  threads, scales)
+                assert set(scales) == set(res), "some results of a scaled step stored unscaled"
+                keys = sorted(res)
+                check_scale_linear([res[k_] // 64 for k_ in keys], [scales[k_] for k_ in keys])
         else:
             nu = check_step(m.group(5), int(m.group(1)), int(m.group(2)), lds_size, group_elems * 64, max_blocks)
             shapes.add(re.search(r"const int wi = (.*?), wj = (.*?), wq = (.*?);", m.group(5)).groups())
