@@ -79,7 +79,8 @@ typedef struct {
                             the program is not a tree); 0 = chosen by the cost model */
   int32_t vector_only;   /* WIDE: 1 = run every step on the vector ALUs; 0 = two-operand
                             complex64 and BF16x3 contractions with >= 4 row bits, >= 4
-                            column bits and >= 1 summed bit run on the matrix cores */
+                            column bits and >= 1 summed bit (optionally times a constant
+                            scale of the results) run on the matrix cores */
   int32_t checkpoint_every;  /* gradient plans: 0 = every forward tensor stays in item memory
                                 until its reverse step; n > 0 = only every n-th forward
                                 elimination output is kept (a checkpoint) and the others are
@@ -144,7 +145,7 @@ typedef struct {
                              steps; otherwise the item steps' kernel count */
   int32_t mfma_steps;     /* WIDE, complex64 and BF16x3: item steps that run on the matrix
                              cores (two-operand contractions with >= 4 row, >= 4 column and
-                             >= 1 summed bits) */
+                             >= 1 summed bits, optionally times a constant scale) */
   double flops_mfma;      /* the part of flops_item those steps perform */
   double roof_s_item;     /* chain roofline time per slice contraction: the sum over item
                              steps of max(flops / 157.3 TFLOP/s, bytes / 8 TB/s), MI355X's
