@@ -484,6 +484,11 @@ typedef struct qgm_contraction qgm_contraction;
  *     products per tile and K step of four complex k).  In the per-item
  *     form jband 1 stores results straight from registers instead of
  *     through LDS.
+ *     complex64 per-item layouts + 32: the three-multiplication complex
+ *     product (Cr = sum ar br - sum ai bi, Ci = sum (ar + ai)(br + bi) -
+ *     sum ar br - sum ai bi: three FP32 products per tile and K step
+ *     instead of four; error bound (3K + 9) 2^-24 sum |a||b| instead of
+ *     (2K + 2) 2^-24 for a sum of K terms).
  *   Built in for BF16x3: the per-item form with two K steps per stage and
  *   a 64 KiB ring when the step sums 5 or more bits, else layout 7. */
 typedef struct {

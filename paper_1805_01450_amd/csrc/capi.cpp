@@ -1009,7 +1009,7 @@ qgm_status qgm_contraction_create(int32_t prec, int32_t nb, int32_t ni, int32_t 
   GUARD_BEGIN
   if (!out) return fail(QGM_E_ARG, "null argument");
   if (tile && (tile->per < 1 || tile->per > 16 || (tile->per & (tile->per - 1)) || tile->lds_budget < 1024 ||
-               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 31))
+               tile->lds_budget > 163840 || tile->jband < 0 || tile->jband > 8 || tile->layout < 0 || tile->layout > 63))
     return fail(QGM_E_ARG, "tile parameters out of range");
   *out = nullptr;
   if (prec != QGM_C128 && prec != QGM_C64 && prec != QGM_BF16X3) return fail(QGM_E_UNSUPPORTED, "unknown precision");

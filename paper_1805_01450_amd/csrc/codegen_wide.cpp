@@ -137,9 +137,12 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
   // SB = 8 IT bytes (LPR lanes of 16 bytes), a copy instruction RPI rows
   const int SB = 8 * IT, LPR = IT / 2, RPI = 64 / LPR, lg = IT == 4 ? 1 : 2;
   int WM = std::min(4, 1 << (ni - 4)), WN = std::min(4, 1 << (nj - 4));
-  if (tp.layout == 4) WM = std::min(WM, 2);
-  else if (tp.layout == 5) WN = std::min(WN, 2);
-  else if (tp.layout == 6) WM = std::min(WM, 2), WN = std::min(WN, 2);
+  const int lay = tp.layout & 7;
+  // complex64, layout + 32: the three-multiplication complex product
+  const bool m3 = prec == 1 && (tp.layout & 32);
+  if (lay == 4) WM = std::min(WM, 2);
+  else if (lay == 5) WN = std::min(WN, 2);
+  else if (lay == 6) WM = std::min(WM, 2), WN = std::min(WN, 2);
   const int nk = 1 << ns;
   // complex k per stage: 4 per K step, times the table's steps per stage
   // (at most the whole sum), and more when the copies of a stage do not
@@ -279,7 +282,8 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
   };
   for (int f = 0; f < WM; ++f)
     for (int g = 0; g < WN; ++g)
-      o << "  f32x4 cr" << f << "_" << g << " = {}, ci" << f << "_" << g << " = {};\n";
+      o << "  f32x4 cr" << f << "_" << g << " = {}, ci" << f << "_" << g << " = {}"
+        << (m3 ? ", cs" + std::to_string(f) + "_" + std::to_string(g) + " = {}" : "") << ";\n";
   for (int s = 0; s < P - 1; ++s) issue(std::to_string(std::min(s, nu - 1)), std::to_string(s));
   // lane read offsets: slot (4 t + l / 16) TM + 16 f + l % 16 of A, item pair
   // (w4 / 2) ^ swz(slot) (swz from the low bits of l % 16), item w4 & 1 of
@@ -299,7 +303,34 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
   issue("un", "(u + " + std::to_string(P - 1) + ") % " + std::to_string(P));
   o << "    }\n"
     << "    const char* sb = lds + (u % " << P << ") * " << stage << ";\n";
-  for (int t = 0; t < ku / 4 && prec == 1; ++t) {
+  for (int t = 0; t < ku / 4 && m3; ++t) {
+    // complex64, three-multiplication form: Cr += ar br, Cs += ai bi, Ci +=
+    // (ar + ai)(br + bi) per tile and K step; after the sum Re = Cr - Cs and
+    // Im = Ci - Cr - Cs (three FP32 16 x 16 x 4 products instead of four)
+    const std::string T = std::to_string(t);
+    for (int f = 0; f < WM; ++f) {
+      const std::string F = T + "_" + std::to_string(f);
+      o << "    const C2 a" << F << " = *(const C2*)(sb + rda + " << SB * (4 * t * TM + 16 * f) << ");\n"
+        << "    const float sa" << F << " = a" << F << ".x + a" << F << ".y;\n";
+    }
+    for (int g = 0; g < WN; ++g) {
+      const std::string G = T + "_" + std::to_string(g);
+      o << "    const C2 b" << G << " = *(const C2*)(sb + rdb + " << SB * (4 * t * TN + 16 * g) << ");\n"
+        << "    const float sb" << G << " = b" << G << ".x + b" << G << ".y;\n";
+    }
+    for (int f = 0; f < WM; ++f)
+      for (int g = 0; g < WN; ++g) {
+        const std::string C = std::to_string(f) + "_" + std::to_string(g);
+        const std::string F = T + "_" + std::to_string(f), G = T + "_" + std::to_string(g);
+        o << "    cr" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(a" << F << ".x, b" << G << ".x, cr" << C
+          << ", 0, 0, 0);\n"
+          << "    cs" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(a" << F << ".y, b" << G << ".y, cs" << C
+          << ", 0, 0, 0);\n"
+          << "    ci" << C << " = __builtin_amdgcn_mfma_f32_16x16x4f32(sa" << F << ", sb" << G << ", ci" << C
+          << ", 0, 0, 0);\n";
+      }
+  }
+  for (int t = 0; t < ku / 4 && prec == 1 && !m3; ++t) {
     // complex64: four FP32 16 x 16 x 4 products per tile and K step, lane
     // group l / 16 holding complex k = 4 t + l / 16 (Cr += ar br - ai bi,
     // Ci += ar bi + ai br)
@@ -362,6 +393,13 @@ static bool emit_mfma16_step(std::ostringstream* o_, const std::string& pre, Wid
   }
   o << "  }\n"
     << "  __builtin_amdgcn_s_waitcnt(" << ((7 << 4) | (15 << 8)) << ");  // no copy left in flight\n";
+  if (m3)
+    for (int f = 0; f < WM; ++f)
+      for (int g = 0; g < WN; ++g) {
+        const std::string C = std::to_string(f) + "_" + std::to_string(g);
+        o << "  ci" << C << " = ci" << C << " - (cr" << C << " + cs" << C << ");\n"
+          << "  cr" << C << " = cr" << C << " - cs" << C << ";\n";
+      }
   // results: register e of tile (f, g) is row 16 f + 4 (l / 16) + e, column
   // 16 g + l % 16, item itb + w4
   auto fg_off = [&](int f, int g) {
@@ -462,7 +500,7 @@ static bool per_item_choice(int prec, bool from_table, const MfmaTile& tp, int n
   else
     per_item = prec == 1 && from_table && (tp.layout & 16) && variant;
   t16 = from_table ? tp : MfmaTile{2, 65536, 0, 0};
-  t16.layout = lay;
+  t16.layout = lay | (tp.layout & 32);
   it_pref = from_table && (tp.layout & 8) ? 8 : 4;
   return per_item;
 }
@@ -770,7 +808,7 @@ bool read_tile_table(const std::string& path, TileTable& t, std::string& err) {
     int n = std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]);
     if (n <= 0) continue;  // blank or comment
     if (n != 8 || v[0] < 0 || v[0] > 2 || v[1] < 4 || v[2] < 4 || v[3] < 1 || v[3] > 16 || v[4] < 1 || v[4] > 16 ||
-        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 31) {
+        (v[4] & (v[4] - 1)) || v[5] < 1024 || v[5] > 163840 || v[6] < 0 || v[6] > 8 || v[7] < 0 || v[7] > 63) {
       err = "tile table " + path + " line " + std::to_string(ln) + ": expected prec ni nj nk per lds_budget jband layout";
       ok = false;
       break;

@@ -9,9 +9,10 @@ kept unless tuned again.  The tuner times each shape alone, which does not
 see the operand strides and cache state of the plan's own levels; so each
 entry is then settled inside the plan: the plan's level kernels are timed
 with the tuned entry, without it (the library's built-in tile for the
-shape) and with the per-item form at its default tile (complex64: four
-items per block; BF16x3: eight), and the fastest is kept unless it beats
-the tuned entry by less than 0.5 %.
+shape), with the per-item form at its default tile (complex64: four
+items per block; BF16x3: eight) and, for a complex64 per-item entry, with
+the same tile in the three-multiplication form (layout + 32), and the
+fastest is kept unless it beats the tuned entry by less than 0.5 %.
 """
 import argparse
 import json
@@ -92,10 +93,15 @@ def confirm(q, circ, rec, prec, table, margin=0.005):
             cur = f.readlines()
         base = plan_ms(q, torch, circ, rec, prec, table, d_bits, d_part, n_s)
         shape = " ".join(ln.split()[:4])
+        per, budget, band, layout = (int(v) for v in ln.split()[4:8])
         alt = {"built-in": [x for x in cur if x != ln],
                "per-item": [x if x != ln else f"{shape} {per_item}\n" for x in cur]}
         if " ".join(ln.split()[4:]) == per_item:
             del alt["per-item"]
+        if prec == q.QGM_C64 and layout & 16 and not layout & 32:
+            # the same per-item tile with three FP32 products per complex product
+            alt["per-item, 3 products"] = [x if x != ln else f"{shape} {per} {budget} {band} {layout | 32}\n"
+                                           for x in cur]
         best, best_ms = None, base * (1.0 - margin)
         times = []
         for name, body in alt.items():

@@ -501,7 +501,8 @@ def test_per_item_form_variants(tile, shape, tmp_path, monkeypatch):
         check_epilogue16(src, direct)
 
 
-@pytest.mark.parametrize("tile", [(2, 65536, 0, 16), (1, 131072, 0, 24), (2, 65536, 0, 21), (1, 49152, 1, 22)])
+@pytest.mark.parametrize("tile", [(2, 65536, 0, 16), (1, 131072, 0, 24), (2, 65536, 0, 21), (1, 49152, 1, 22),
+                                  (2, 65536, 0, 48), (1, 131072, 1, 56)])
 @pytest.mark.parametrize("shape", [(1, 6, 7, 5), (0, 6, 6, 3)])
 def test_per_item_form_complex64(tile, shape, tmp_path, monkeypatch):
     """complex64 in the per-item form (FP32 16 x 16 x 4): the same copies,
@@ -522,6 +523,7 @@ def test_per_item_form_complex64(tile, shape, tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("prec,tile", [(q.QGM_C64, (2, 65536, 0, 16)), (q.QGM_C64, (1, 131072, 0, 24)),
+                                       (q.QGM_C64, (2, 65536, 0, 48)),
                                        (q.QGM_C64, (2, 65536, 1, 21)), (q.QGM_BF16X3, (2, 65536, 0, 0)),
                                        (q.QGM_BF16X3, (2, 131072, 0, 8)), (q.QGM_BF16X3, (2, 65536, 1, 4))])
 @pytest.mark.parametrize("shape", [(0, 6, 6, 3), (1, 6, 7, 5), (1, 7, 6, 2)])
