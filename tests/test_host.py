@@ -537,3 +537,29 @@ def test_two_qubit_gates_variables_and_graph_match_oracle(seed):
     with pytest.raises(q.QgmError) as e:
         q.Circuit("qubits 2\n0 CX 1 1\n")
     assert e.value.status == -2 and "single qubit" in str(e.value)
+
+
+def test_sliced_order_for_groups(monkeypatch):
+    """qgm_sliced_order_for_groups returns the same sliced variables, keeps
+    plans with k <= 6 as they are, leaves the stored k = 8 plan (already in
+    that order) unchanged with a third of its item work independent of the
+    variables at slice bits 6 and 7, and is what the planner returns."""
+    monkeypatch.setenv("QGM_WIDE_PREBUILT", "1")
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_01450_amd", "plans")
+    rec = json.load(open(os.path.join(here, "8x8x40-k8.json")))
+    cz = rec["circuit"]
+    c = q.Circuit(generate_circuit(cz["n"], cz["depth"], cz["seed"]))
+    out, frac = q.qgm_sliced_order_for_groups(c.h, rec["sliced"], rec["order"])
+    assert out == rec["sliced"] and 0.3 < frac < 0.4
+    rev = rec["sliced"][::-1]
+    out2, frac2 = q.qgm_sliced_order_for_groups(c.h, rev, rec["order"])
+    assert sorted(out2) == sorted(rev) and abs(frac2 - frac) < 1e-12
+    assert set(out2[6:]) == set(out[6:])  # the same two variables go to the group bits
+    rec7 = json.load(open(os.path.join(here, "7x7x30.json")))
+    c7 = q.Circuit(generate_circuit(7, 30, 0))
+    assert q.qgm_sliced_order_for_groups(c7.h, rec7["sliced"], rec7["order"]) == (rec7["sliced"], 0.0)
+    c5 = q.Circuit(generate_circuit(5, 20, 0))
+    sl, order = c5.plan_slices(k_req=8, time_budget_s=0.3, flags=q.QGM_PLAN_DETERMINISTIC)
+    assert q.qgm_sliced_order_for_groups(c5.h, sl, order)[0] == sl
