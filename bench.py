@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "slice contractions/sec + % MFMA peak (c64 vs BF16x3) at stated amplitude rel. error"
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published vector FP32 peak (packed dual issue)
-PEAK_FP32_VECTOR_NONPACKED_TFLOPS = 78.6  # the same without packed FP32, which this build disables
+PEAK_FP32_VECTOR_NONPACKED_TFLOPS = 78.6  # the same without packed FP32, which the kernels here are compiled without
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X published dense FP32 matrix-core peak
 PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X published dense BF16 matrix-core peak
 PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X published dense FP64 matrix-core peak
@@ -354,7 +354,7 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the slice axis would shard across GPUs "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; the slice axis would shard across GPUs "
                                    "by contiguous slice ranges (qgm_amplitudes_range)"}))
         sys.exit(2)
     if args.calibrate_copy:

@@ -48,7 +48,7 @@ typedef enum {
   QGM_E_SLICE = -4,       /* sliced variables not distinct free variables, or k > 40 */
   QGM_E_WORKSPACE = -5,   /* workspace too small, or plan exceeds the caller's cap */
   QGM_E_HIP = -6,         /* HIP runtime error (message has hipGetErrorString) */
-  QGM_E_UNSUPPORTED = -7  /* option not supported by this build */
+  QGM_E_UNSUPPORTED = -7  /* option or combination of options not supported by the library */
 } qgm_status;
 
 typedef enum {
