@@ -116,6 +116,18 @@ def confirm(q, circ, rec, prec, table, margin=0.005):
         if best:
             with open(table, "w") as f:
                 f.writelines(alt[best])
+        if best == "per-item" and prec == q.QGM_C64:
+            # the chosen per-item tile in the three-product form as well
+            line3 = f"{shape} {per_item[:-2]}{int(per_item.split()[-1]) | 32}\n"
+            body = [x if x.split()[:4] != ln.split()[:4] else line3 for x in alt[best]]
+            with open(tmp, "w") as f:
+                f.writelines(body)
+            t3 = plan_ms(q, torch, circ, rec, prec, tmp, d_bits, d_part, n_s)
+            keep = t3 < best_ms * (1.0 - margin)
+            print(f"    three products: {t3:.2f} ms -> {'taken' if keep else 'not taken'}", flush=True)
+            if keep:
+                with open(table, "w") as f:
+                    f.writelines(body)
     if os.path.exists(tmp):
         os.remove(tmp)
 
